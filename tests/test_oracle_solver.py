@@ -1,0 +1,148 @@
+"""Pins of the oracle's smoother, nodal correction and V-cycle.
+
+* The V-cycle's fixed point is the solution of the whole space-time system,
+  computed here by one sparse LU of L (brute force on tiny meshes).
+* The complex diagonalised slab solve equals the real 2n block solve.
+* On one slab the damped block-Jacobi smoother contracts the error by exactly
+  1 - omega (eq. (2)).
+* The nodal correction (eq. (8)) is a Galerkin projection on the space-time
+  gradient subspace: it solves pure-gradient errors exactly and leaves a
+  residual with G^T r = 0; its time solve equals the closed-form prefix sum.
+* Rates: pure time coarsening with exact solves stays below 0.5 (section 3.1);
+  spatial coarsening without the nodal correction is ineffective (section 3.1,
+  rate near 1) and works again with it (section 3.4/4).
+* Manufactured solution: the discretisation error falls under refinement.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_09548_amd import inputs
+from oracle.vcycle import SpaceTimeMultigrid, direct_solve, SlabSolverReal, SlabSolverComplex
+from oracle.manufactured import manufactured_problem, end_value
+from oracle.dgtime import time_matrices
+
+
+def _solver(n=4, Nt=16, pt=1, **kw):
+    prob = inputs.config_block_random(n=n, Nt=Nt, pt=pt, seed=11, block_hexes=max(1, n // 2))
+    return SpaceTimeMultigrid(prob, **kw)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+@pytest.mark.parametrize("n,Nt", [(2, 4), (4, 8), (4, 16)])
+def test_vcycle_converges_to_direct_solution(n, Nt, pt):
+    s = _solver(n, Nt, pt)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((Nt, pt + 1, s.fine.n_e))
+    x, hist = s.solve(b, rtol=1e-12, max_cycles=60)
+    xd = direct_solve(s, b)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def test_complex_slab_solve_equals_real_block():
+    s = _solver(4, 2, 1)
+    lev = s.levels[0]
+    real = SlabSolverReal(lev.space.M, lev.space.K, lev.Kt, lev.Mt)
+    cplx = SlabSolverComplex(lev.space.M, lev.space.K, lev.tau)
+    r = np.random.default_rng(0).standard_normal((3, 2, s.fine.n_e))
+    a, b = real.solve(r), cplx.solve(r)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+def test_single_slab_smoother_contracts_by_one_minus_omega():
+    s = _solver(4, 1, 1)
+    lev = s.levels[0]
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal((1, 2, s.fine.n_e))
+    xs = lev.solve_exact_single_slab(b)
+    x = np.zeros_like(b)
+    for k in range(3):
+        x = lev.smooth_S(x, b, 0.5)
+        assert np.allclose(xs - x, 0.5 ** (k + 1) * xs, atol=1e-12 * np.abs(xs).max())
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_nodal_correction_solves_gradient_errors(pt):
+    s = _solver(4, 8, pt)
+    lev = s.levels[0]
+    rng = np.random.default_rng(2)
+    phi = rng.standard_normal((lev.N, pt + 1, s.fine.n_v))
+    u = np.stack([(s.fine.G @ phi[:, k].T).T for k in range(pt + 1)], axis=1)
+    b = lev.apply_L(u)
+    x = lev.nodal_A(np.zeros_like(b), b)
+    assert np.linalg.norm(x - u) <= 1e-11 * np.linalg.norm(u)
+    # after A on a general residual, G^T r = 0
+    b = rng.standard_normal(b.shape)
+    x0 = rng.standard_normal(b.shape)
+    x = lev.nodal_A(x0, b)
+    r = lev.residual(x, b)
+    gr = np.stack([(s.fine.G.T @ r[:, k].T).T for k in range(pt + 1)], axis=1)
+    assert np.linalg.norm(gr) <= 1e-11 * np.linalg.norm(b)
+
+
+def test_time_solve_equals_prefix_sum_formula():
+    """Forward substitution with L_t (K_t diagonal, -N_t below) against the
+    closed form y_{n,0} = e_{n-1} + (g0 - g1)/2, y_{n,1} = (g0 + g1)/2 with
+    e_n = sum_{m <= n} g_{m,0}; and against the plain running sum for degree 0."""
+    rng = np.random.default_rng(4)
+    N, nv = 7, 5
+    for pt in (0, 1):
+        q = pt + 1
+        Kt, _, Nt = time_matrices(pt, 0.3)
+        g = rng.standard_normal((N, q, nv))
+        z = np.empty_like(g)
+        prev = np.zeros((q, nv))
+        for n in range(N):
+            z[n] = np.linalg.solve(Kt, g[n] + Nt @ prev)
+            prev = z[n]
+        if pt == 0:
+            ref = np.cumsum(g, axis=0)
+        else:
+            e = np.cumsum(g[:, 0], axis=0)
+            ref = np.empty_like(g)
+            ref[:, 0] = np.concatenate([np.zeros((1, nv)), e[:-1]]) + 0.5 * (g[:, 0] - g[:, 1])
+            ref[:, 1] = 0.5 * (g[:, 0] + g[:, 1])
+        assert np.allclose(z, ref, atol=1e-14)
+
+
+def test_config1_hierarchy_follows_coarsening_rule():
+    prob = inputs.config_unit_manufactured(4, 16, 1)
+    s = SpaceTimeMultigrid(prob)
+    ns = [prob.levels[sp_.space].n for sp_ in s.specs]
+    assert list(zip(ns, [sp_.N for sp_ in s.specs])) == [(4, 16), (2, 8), (2, 4), (2, 2), (2, 1)]
+    # lambda at the finest level: tau n^2 / 3 with h_T = sqrt(3)/n
+    assert abs(s.space[0].anisotropy(1 / 16) - (1 / 16) * 16 / 3) < 1e-14
+
+
+def test_semi_time_rate_below_half():
+    s = _solver(4, 16, 1, allow_space=False)
+    rate, _ = s.power_rate(seed=0, max_cycles=25)
+    assert rate < 0.5
+
+
+def test_spatial_coarsening_needs_nodal_correction():
+    # 64 slabs of tau = 1/16 on the 4^3 mesh: lambda = 1/3, so space coarsens;
+    # a long horizon makes the undamped gradient modes visible
+    prob = inputs.config_unit_manufactured(4, 64, 1, T=4.0)
+    without = SpaceTimeMultigrid(prob, use_nodal=False)
+    with_a = SpaceTimeMultigrid(prob, use_nodal=True)
+    assert without.specs[1].space == 1                    # space does coarsen here
+    r_without, _ = without.power_rate(seed=0, max_cycles=25)
+    r_with, _ = with_a.power_rate(seed=0, max_cycles=25)
+    assert r_without > 0.95
+    assert r_with < 0.2
+
+
+def test_manufactured_error_decreases():
+    errs = []
+    for n, Nt in ((4, 16), (8, 64)):
+        prob = inputs.config_unit_manufactured(n, Nt, 1)
+        s = SpaceTimeMultigrid(prob)
+        b_all, u0, uT = manufactured_problem(s)
+        b = s.fold_initial(s.to_interior(b_all), u0)
+        x, _ = s.solve(b, rtol=1e-11)
+        e = end_value(x, 1) - uT[s.fine.ie]
+        M = s.fine.M
+        errs.append(np.sqrt(e @ M @ e) / np.sqrt(uT[s.fine.ie] @ M @ uT[s.fine.ie]))
+    # at least first order in h (tau shrinks like h^2 here)
+    assert errs[1] < 0.5 * errs[0]
