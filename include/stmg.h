@@ -1,0 +1,213 @@
+/*
+ * stmg.h -- C ABI of the MI355X space-time multigrid library for the
+ * eddy-current equation  sigma du/dt + curl(nu curl u) = f  on a tetrahedral
+ * mesh with lowest-order Nedelec elements and upwind DG in time.
+ *
+ * Method (Neumueller & Schwalsberger, "A parallel space-time multigrid method
+ * for the eddy-current equation", 2019):
+ *   - all-at-once space-time system L x = f, block lower bidiagonal, slab block
+ *     A = K_t (x) M + M_t (x) K, coupling -N_t (x) M (section 2.1, eq. (1));
+ *   - damped block-Jacobi smoother S with exact slab solves (eq. (2));
+ *   - nodal auxiliary-space correction A = G Sigma_t K_n^{-1} G^T (eq. (8));
+ *   - hybrid smoother SAS (section 4), V-cycle over time meshes with spatial
+ *     coarsening where the local anisotropy rule (eq. (3)) holds.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Edges: the distinct vertex pairs of the finest mesh's tetrahedra, stored as
+ *   (tail, head) with tail < head, numbered in lexicographic order of
+ *   (tail, head). The edge DOF is the line integral of the field from tail to
+ *   head. The same rule numbers the edges of every coarse mesh.
+ * Boundary: a face that belongs to exactly one tetrahedron is a boundary face;
+ *   its edges and vertices are boundary DOFs, eliminated by the homogeneous
+ *   Dirichlet condition u x n = 0 (section 3).
+ * Vectors at the ABI (device pointers, FP64, caller-owned, contiguous):
+ *   full layout     [Nt][pt+1][n_edges]   all edges of the finest mesh;
+ *                   boundary entries of inputs are ignored, of outputs are 0.
+ *   level layout    [N][pt+1][n_interior] interior edges of that level's mesh
+ *                   in ascending edge order (used by the per-level entry
+ *                   points meant for testing).
+ *   Component k of slab n is the coefficient of the Legendre polynomial
+ *   psi_0 = 1, psi_1 = 2s - 1 on that slab (s in [0,1]).
+ * Right-hand side: the discrete load b[n][k][e] = int_{I_n} int f . phi_e psi_k.
+ *   The optional initial value u0 [n_edges] adds psi_k(0) M u0 to slab 0 (the
+ *   M u^0 term of eq. (1)).
+ * Streams: every device operation is enqueued on the stream given to
+ *   stmg_setup (NULL = default stream); entry points that return a host value
+ *   synchronise that stream. A handle is not re-entrant.
+ * Errors: every int-returning function returns STMG_OK or one of the codes
+ *   below; stmg_strerror names it, stmg_last_error_message gives detail.
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  STMG_OK = 0,
+  STMG_EINVAL = 1,    /* bad sizes or arguments (Nt not 2^k, pt not 0/1, sigma <= 0 ...) */
+  STMG_ENOMEM = 2,    /* host or device allocation failed */
+  STMG_ENOTCONV = 3,  /* max_cycles reached before rtol; x holds the last iterate */
+  STMG_ENUMERIC = 4,  /* NaN/Inf in data or residual, zero pivot in a factorisation */
+  STMG_EHIP = 5,      /* HIP runtime error (no device, launch failure ...) */
+  STMG_EAGAIN = 6,    /* serving: result not ready yet */
+  STMG_ENOSYS = 7     /* entry point not available in this build/handle */
+};
+
+enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
+enum { STMG_SMOOTH_SAS = 0, STMG_SMOOTH_S_ONLY = 1 };
+
+/* One mesh of a nested hierarchy. Coarse meshes (index >= 1) describe their
+ * relation to the next finer mesh:
+ *   vertex_parent[v_fine][2] = (a, b): the finer vertex is the midpoint of this
+ *     mesh's vertices a and b (a == b: it coincides with vertex a);
+ *   tet_parent[t_fine]: this mesh's tetrahedron containing the finer one.
+ * Only nested refinements are meaningful (Freudenthal/Kuhn or red). */
+typedef struct {
+  int32_t n_vertices;
+  const double *coords;          /* host [n_vertices][3] */
+  int32_t n_tets;
+  const int32_t *tets;           /* host [n_tets][4], 0-based vertex ids */
+  const int32_t *vertex_parent;  /* NULL on mesh 0; host [n_vertices(finer)][2] */
+  const int32_t *tet_parent;     /* NULL on mesh 0; host [n_tets(finer)] */
+} stmg_mesh;
+
+/* The problem of section 3: sigma du/dt + curl nu curl u = f on Omega x (0,T),
+ * sigma and nu (= mu^{-1}) piecewise constant per tetrahedron of mesh 0,
+ * tau = T/Nt, DG degree pt in time (0 = implicit Euler of eq. (1)). */
+typedef struct {
+  int32_t n_meshes;              /* >= 1; meshes[0] is the finest */
+  const stmg_mesh *meshes;       /* host array of n_meshes */
+  const double *sigma;           /* host [meshes[0].n_tets], > 0 */
+  const double *nu;              /* host [meshes[0].n_tets], >= 0 */
+  double T;                      /* > 0 */
+  int32_t Nt;                    /* power of two */
+  int32_t pt;                    /* 0 or 1 */
+} stmg_problem;
+
+typedef struct {
+  double omega;                  /* smoother damping, 0.5 (eq. (2)) */
+  double lambda_crit;            /* spatial coarsening threshold, 0.1 (section 5.1) */
+  int32_t allow_space_coarsening;/* 1: apply eq. (3); 0: coarsen in time only */
+  int32_t smoother;              /* STMG_SMOOTH_SAS (default) | STMG_SMOOTH_S_ONLY (ablation: SS) */
+  int32_t precision;             /* STMG_FP64 | STMG_FP32_REFINED */
+  double rtol;                   /* relative residual target of stmg_solve, default 1e-8 */
+  int32_t max_cycles;            /* cap of stmg_solve, default 100 */
+  int32_t host_only;             /* 1: build host data only (no device), for tests */
+  int32_t factor_on_device;      /* 1 (default): numeric factorisation on the GPU */
+  int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
+} stmg_options;
+
+typedef struct {
+  int32_t cycles;                /* V-cycles performed */
+  double rel_res;                /* final ||b - L x||_2 / ||b||_2 over interior DOFs */
+  double setup_s;                /* wall time of stmg_setup */
+  double solve_s;                /* wall time of the last stmg_solve */
+  const double *res_history;     /* [cycles] relative residuals, owned by the handle */
+} stmg_report;
+
+typedef struct {
+  int32_t n_edges;               /* all edges of mesh 0 (full layout width) */
+  int32_t n_levels;              /* space-time levels, finest first */
+  int32_t pt;
+  int64_t device_bytes;          /* device memory held by the handle */
+  int64_t factor_bytes;          /* of which triangular factors */
+} stmg_info_t;
+
+typedef struct {
+  int32_t mesh;                  /* index into problem.meshes */
+  int32_t N;                     /* slabs */
+  double tau;
+  int32_t n_e;                   /* interior edges of that mesh */
+  int32_t n_v;                   /* interior vertices */
+  int64_t nnz_pattern;           /* nonzeros of the shared M/K pattern */
+  int64_t factor_nnz_slab;       /* entries of the slab-block factor L (lower incl. diag) */
+  int64_t factor_nnz_nodal;      /* entries of the nodal factor */
+  int32_t n_supernodes_slab;
+  double lambda;                 /* eq. (3) anisotropy of this level (its tau, its mesh) */
+} stmg_level_info_t;
+
+typedef struct stmg_handle stmg_handle;
+
+const char *stmg_strerror(int code);
+/* Thread-local message of the last failing call in this thread. */
+const char *stmg_last_error_message(void);
+void stmg_default_options(stmg_options *opt);
+
+/* Build everything a solve needs: topology, FP64 assembly of M, K (Whitney
+ * elements, section 3), the space-time hierarchy (time halving, eq. (3) for
+ * space), Galerkin coarse operators, nested-dissection orderings, symbolic and
+ * numeric factorisations of every level's slab block and nodal matrix K_n, and
+ * uploads to HBM. Host arrays are borrowed for the call only. `stream` is a
+ * hipStream_t (NULL = default stream). On failure *out is NULL and nothing
+ * leaks. */
+int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream,
+               stmg_handle **out);
+void stmg_destroy(stmg_handle *h);
+
+int stmg_info(const stmg_handle *h, stmg_info_t *info);
+int stmg_level_info(const stmg_handle *h, int32_t level, stmg_level_info_t *info);
+/* Edge list of mesh 0: *edge_vertices points to [n_edges][2] (tail, head),
+ * owned by the handle. */
+int stmg_edges(const stmg_handle *h, int32_t *n_edges, const int32_t **edge_vertices);
+
+/* Solve L x = b (+ initial value) by V-cycles until ||b - Lx|| <= rtol ||b||
+ * (section 2.1; tolerance as in section 6). rhs_dev, x_dev: full layout.
+ * u0_dev, x0_dev may be NULL (zero). x_dev may alias x0_dev. Returns
+ * STMG_ENOTCONV (x holds the last iterate) if max_cycles is reached,
+ * STMG_ENUMERIC on a non-finite residual. rep may be NULL. */
+int stmg_solve(stmg_handle *h, const double *rhs_dev, const double *u0_dev,
+               const double *x0_dev, double *x_dev, stmg_report *rep);
+
+/* Split form of stmg_solve for benchmarking and resuming:
+ *   stmg_load:   take rhs (+u0) and initial guess (NULL = 0) into the
+ *                handle's internal layout; returns ||b||_2 in *bnorm.
+ *   stmg_cycles: n_cycles iterations, each one V-cycle followed by the
+ *                residual norm; res_host (may be NULL) receives the n_cycles
+ *                relative residuals (this synchronises the stream).
+ *   stmg_store:  write the current iterate in full layout. */
+int stmg_load(stmg_handle *h, const double *rhs_dev, const double *u0_dev,
+              const double *x0_dev, double *bnorm);
+int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host);
+int stmg_store(stmg_handle *h, double *x_dev);
+
+/* r = b - L x on the finest level, full layout (r's boundary entries are 0).
+ * u0_dev may be NULL. */
+int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev,
+                  const double *u0_dev, double *r_dev);
+
+/* Per-level operations in level layout, for parity tests:
+ *   STMG_OP_RESIDUAL  out = b - L_l x                    (in = x, in2 = b)
+ *   STMG_OP_SMOOTH_S  out = x + omega A_l^{-1}(b - L_l x) (eq. (2))
+ *   STMG_OP_NODAL_A   out = x + G Sigma_t K_n^{-1} G^T (b - L_l x) (eq. (8))
+ *   STMG_OP_SAS       out = S(A(S(x)))                    (section 4)
+ *   STMG_OP_SLAB_SOLVE out = (I (x) A_l^{-1}) in          (in2 unused)
+ *   STMG_OP_RESTRICT  out (level l+1) = (P_t^T (x) P_s^T) in (level l)
+ *   STMG_OP_PROLONG   out (level l-1) = (P_t (x) P_s) in (level l)
+ *   STMG_OP_VCYCLE    out = V-cycle from level l on x = in, rhs = in2
+ * `in`, `in2`, `out` are distinct device buffers. */
+enum {
+  STMG_OP_RESIDUAL = 0, STMG_OP_SMOOTH_S = 1, STMG_OP_NODAL_A = 2, STMG_OP_SAS = 3,
+  STMG_OP_SLAB_SOLVE = 4, STMG_OP_RESTRICT = 5, STMG_OP_PROLONG = 6, STMG_OP_VCYCLE = 7
+};
+int stmg_level_apply(stmg_handle *h, int32_t level, int32_t op, const double *in_dev,
+                     const double *in2_dev, double *out_dev);
+
+/* Host copies of level-l spatial operators over that level's interior DOFs in
+ * ascending order, as CSR (row_ptr [n+1], col [nnz], val [nnz]); pass NULL
+ * arrays to query sizes (*n, *nnz). which: 0 = M, 1 = K, 2 = G (edges x
+ * vertices), 3 = K_n, 4 = P_e from level l's mesh to the next finer mesh's
+ * (rows = finer interior edges). Works on host_only handles. */
+int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32_t *n_rows,
+                       int32_t *n_cols, int64_t *nnz, int64_t *row_ptr, int32_t *col,
+                       double *val);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STMG_H */

@@ -1,0 +1,800 @@
+// HIP kernels for gfx950 of the space-time V-cycle.
+//
+// Streaming kernels (residual, Jacobi update, nodal correction pieces,
+// transfers) are HBM-bound: one row of the internal layout holds the N*q
+// coefficients of one spatial DOF, so a wavefront (or a 2^k-lane part of it)
+// reads a row with consecutive lanes on consecutive 8..128-byte chunks, and
+// the DG coupling to slab n-1 stays inside the row (a lane shuffle).
+// Reductions use fixed trees, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "factor.hpp"
+#include "kernels.hpp"
+
+namespace stmg {
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so neighbouring rows share an L2.
+__device__ inline int xcd_remap(int bid, int nblocks) {
+  const int x = bid & 7, idx = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+__device__ inline double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum (256 threads) in a fixed order; result valid in thread 0.
+__device__ inline double block_sum(double v) {
+  __shared__ double part[BLOCK / 64];
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BLOCK / 64; ++i) s += part[i];
+  __syncthreads();
+  return s;
+}
+
+// Values per lane for a row of W doubles: at least q, and W/64 when the row
+// is wider than a wavefront.
+inline int lane_chunk(int W, int q) {
+  int c = W / 64;
+  return c < q ? q : c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- residual
+// r_n = b_n - (K_t (x) M + M_t (x) K) x_n + (N_t (x) M) x_{n-1}
+// q = 1: r = b - M(x_n - x_{n-1}) - tau K x_n
+// q = 2: with E_{n-1} = (M x)_{n-1,0} + (M x)_{n-1,1} (end value of slab n-1):
+//   r0 = b0 - (Mx0 + Mx1) + E_{n-1} - tau K x0
+//   r1 = b1 + Mx0 - Mx1 - E_{n-1} - (tau/3) K x1
+// Slab-solve right-hand side (mode 1), q = 2: w = (1/2 + i sqrt2/4) r0 - (3 i sqrt2/4) r1
+// stored as (re, im) in the two slots of slab n; q = 1: w = r.
+template <int C, int Q>
+__global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
+  constexpr int S = C / Q;
+  const int W = a.N * Q;
+  const int LPR = W / C;
+  const int rpw = 64 / LPR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane % LPR, sub = lane / LPR;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int row = (blk * (BLOCK / 64) + wave) * rpw + sub;
+  const bool active = row < a.n_rows;
+  double am[C], ak[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) am[j] = ak[j] = 0.0;
+  if (active && a.x) {
+    const int64_t k1 = a.ptr[row + 1];
+    for (int64_t k = a.ptr[row]; k < k1; ++k) {
+      const int c = a.col[k];
+      const double mv = a.mval[k], kv = a.kval[k];
+      const double *xr = a.x + (int64_t)c * W + li * C;
+      if constexpr (C % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < C; j += 2) {
+          const double2 v = *reinterpret_cast<const double2 *>(xr + j);
+          am[j] += mv * v.x;
+          am[j + 1] += mv * v.y;
+          ak[j] += kv * v.x;
+          ak[j + 1] += kv * v.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          am[j] += mv * xr[j];
+          ak[j] += kv * xr[j];
+        }
+      }
+    }
+  }
+  // end value of the lane's last slab, passed to the next lane
+  double elast = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) elast += am[(S - 1) * Q + k];
+  double eprev = __shfl_up(elast, 1, LPR);
+  if (li == 0) eprev = 0.0;
+  double ss = 0.0;
+  if (active) {
+    const int64_t base = (int64_t)row * W + li * C;
+    double bv[C], out[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) bv[j] = a.b[base + j];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if constexpr (Q == 1) {
+        const double r = bv[s] - am[s] + eprev - a.tau * ak[s];
+        eprev = am[s];
+        out[s] = r;
+        ss += r * r;
+      } else {
+        const double m0 = am[2 * s], m1 = am[2 * s + 1];
+        const double r0 = bv[2 * s] - (m0 + m1) + eprev - a.tau * ak[2 * s];
+        const double r1 = bv[2 * s + 1] + m0 - m1 - eprev - (a.tau / 3.0) * ak[2 * s + 1];
+        eprev = m0 + m1;
+        ss += r0 * r0 + r1 * r1;
+        if (a.mode == RES_OUT_SLABRHS) {
+          const double s2 = 1.4142135623730951;
+          out[2 * s] = 0.5 * r0;
+          out[2 * s + 1] = 0.25 * s2 * r0 - 0.75 * s2 * r1;
+        } else {
+          out[2 * s] = r0;
+          out[2 * s + 1] = r1;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) a.out[base + j] = out[j];
+  }
+  if (a.partial) {
+    const double t = block_sum(ss);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = t;
+  }
+}
+
+int residual_blocks(int32_t n_rows, int32_t W, int32_t q) {
+  const int C = lane_chunk(W, q);
+  const int LPR = W / C;
+  const int rows_per_block = (64 / LPR) * (BLOCK / 64);
+  return (n_rows + rows_per_block - 1) / rows_per_block;
+}
+
+template <int C, int Q>
+static void launch_res_cq(const ResidualArgs &a, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual<C, Q>), dim3(nblocks), dim3(BLOCK), 0, s, a);
+}
+
+void launch_residual(const ResidualArgs &a, hipStream_t s) {
+  const int W = a.N * a.q;
+  const int C = lane_chunk(W, a.q);
+  const int nb = residual_blocks(a.n_rows, W, a.q);
+  if (nb == 0) return;
+#define RES_CASE(CC, QQ) \
+  if (C == CC && a.q == QQ) return launch_res_cq<CC, QQ>(a, nb, s);
+  RES_CASE(1, 1)
+  RES_CASE(2, 1)
+  RES_CASE(4, 1)
+  RES_CASE(8, 1)
+  RES_CASE(16, 1)
+  RES_CASE(2, 2)
+  RES_CASE(4, 2)
+  RES_CASE(8, 2)
+  RES_CASE(16, 2)
+#undef RES_CASE
+  fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", W, a.q);
+}
+
+// --------------------------------------------------------------- reductions
+__global__ __launch_bounds__(BLOCK) void k_sum(const double *p, int32_t n, double *out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += BLOCK) s += p[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+void launch_sum(const double *partial, int32_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(BLOCK), 0, s, partial, n, out);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sumsq(const double *v, int64_t n, double *partial) {
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) s += v[i] * v[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+int launch_sumsq(const double *v, int64_t n, double *partial, hipStream_t s) {
+  int nb = (int)std::min<int64_t>(2048, (n + BLOCK - 1) / BLOCK);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(BLOCK), 0, s, v, n, partial);
+  return nb;
+}
+
+// ---------------------------------------------------------- Jacobi update
+__global__ __launch_bounds__(BLOCK) void k_slab_update(int64_t n, int32_t q, double omega,
+                                                       const double *z, double *x, int assign) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (row, slab)
+  if (i >= n) return;
+  if (q == 2) {
+    const double zr = z[2 * i], zi = z[2 * i + 1];
+    const double d0 = omega * 2.0 * zr, d1 = omega * 2.0 * (zr - 1.4142135623730951 * zi);
+    if (assign) {
+      x[2 * i] = d0;
+      x[2 * i + 1] = d1;
+    } else {
+      x[2 * i] += d0;
+      x[2 * i + 1] += d1;
+    }
+  } else {
+    const double d = omega * z[i];
+    x[i] = assign ? d : x[i] + d;
+  }
+}
+
+void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const double *z,
+                        double *x, int assign, hipStream_t s) {
+  const int64_t n = (int64_t)n_rows * N;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_slab_update, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q,
+                     omega, z, x, assign);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_slab_rhs(int64_t n, int32_t q, const double *r, double *w) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  if (q == 2) {
+    const double s2 = 1.4142135623730951;
+    const double r0 = r[2 * i], r1 = r[2 * i + 1];
+    w[2 * i] = 0.5 * r0;
+    w[2 * i + 1] = 0.25 * s2 * r0 - 0.75 * s2 * r1;
+  } else {
+    w[i] = r[i];
+  }
+}
+
+void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const double *r, double *w, hipStream_t s) {
+  const int64_t n = (int64_t)n_rows * N;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_slab_rhs, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q, r, w);
+}
+
+// ------------------------------------------------------- nodal correction
+// g[v][c] = sum over edges e at v of sign(e, v) r[e][c]  (G^T, entries +-1)
+__global__ __launch_bounds__(BLOCK) void k_gradT(int32_t n_v, int32_t W, const int64_t *ptr,
+                                                 const int32_t *edge, const int8_t *sign,
+                                                 const double *r, double *g) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= (int64_t)n_v * W) return;
+  const int32_t v = (int32_t)(i / W), c = (int32_t)(i % W);
+  double acc = 0.0;
+  for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+    const double t = r[(int64_t)edge[k] * W + c];
+    acc += sign[k] > 0 ? t : -t;
+  }
+  g[i] = acc;
+}
+
+void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edge, const int8_t *sign,
+                  const double *r, double *g, hipStream_t s) {
+  const int64_t n = (int64_t)n_v * W;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gradT, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_v, W, ptr,
+                     edge, sign, r, g);
+}
+
+// Inverse of the time operator on the gradient subspace (K_t on the diagonal,
+// -N_t below), per vertex row, in place:
+//   q = 1: y_n = sum_{m <= n} g_m (the running sum of eq. (8));
+//   q = 2: e_n = sum_{m <= n} g_{m,0}; y_{n,0} = e_{n-1} + (g0 - g1)/2, y_{n,1} = (g0 + g1)/2.
+template <int C, int Q>
+__global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, double *g) {
+  constexpr int S = C / Q;
+  const int W = N * Q;
+  const int LPR = W / C;
+  const int rpw = 64 / LPR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane % LPR, sub = lane / LPR;
+  const int row = (blockIdx.x * (BLOCK / 64) + wave) * rpw + sub;
+  const bool active = row < n_v;
+  double v[C];
+  double local = 0.0;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = g[(int64_t)row * W + li * C + j];
+#pragma unroll
+    for (int s = 0; s < S; ++s) local += v[s * Q];
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = 0.0;
+  }
+  // exclusive scan of `local` over the lanes of this row (Hillis-Steele)
+  double incl = local;
+  for (int o = 1; o < LPR; o <<= 1) {
+    const double t = __shfl_up(incl, o, LPR);
+    if (li >= o) incl += t;
+  }
+  double e = incl - local;  // sum over earlier lanes
+  if (active) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if constexpr (Q == 1) {
+        e += v[s];
+        v[s] = e;
+      } else {
+        const double g0 = v[2 * s], g1 = v[2 * s + 1];
+        v[2 * s] = e + 0.5 * (g0 - g1);
+        v[2 * s + 1] = 0.5 * (g0 + g1);
+        e += g0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) g[(int64_t)row * W + li * C + j] = v[j];
+  }
+}
+
+void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t s) {
+  const int W = N * q;
+  const int C = lane_chunk(W, q);
+  const int LPR = W / C;
+  const int rows_per_block = (64 / LPR) * (BLOCK / 64);
+  const int nb = (n_v + rows_per_block - 1) / rows_per_block;
+  if (nb == 0) return;
+#define SCAN_CASE(CC, QQ)                                                                      \
+  if (C == CC && q == QQ) {                                                                    \
+    hipLaunchKernelGGL((k_time_scan<CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, n_v, N, g);         \
+    return;                                                                                    \
+  }
+  SCAN_CASE(1, 1)
+  SCAN_CASE(2, 1)
+  SCAN_CASE(4, 1)
+  SCAN_CASE(8, 1)
+  SCAN_CASE(16, 1)
+  SCAN_CASE(2, 2)
+  SCAN_CASE(4, 2)
+  SCAN_CASE(8, 2)
+  SCAN_CASE(16, 2)
+#undef SCAN_CASE
+  fprintf(stderr, "stmg: unsupported scan shape W=%d q=%d\n", W, q);
+}
+
+// x[e][c] += y[head(e)][c] - y[tail(e)][c]  (G, boundary vertices dropped)
+__global__ __launch_bounds__(BLOCK) void k_grad_add(int32_t n_e, int32_t W, const int32_t *head,
+                                                    const int32_t *tail, const double *y, double *x) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= (int64_t)n_e * W) return;
+  const int32_t e = (int32_t)(i / W), c = (int32_t)(i % W);
+  double d = 0.0;
+  const int32_t h = head[e], t = tail[e];
+  if (h >= 0) d += y[(int64_t)h * W + c];
+  if (t >= 0) d -= y[(int64_t)t * W + c];
+  x[i] += d;
+}
+
+void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const double *y,
+                     double *x, hipStream_t s) {
+  const int64_t n = (int64_t)n_e * W;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_grad_add, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_e, W,
+                     head, tail, y, x);
+}
+
+// ---------------------------------------------------------------- transfers
+// Time prolongation of one coarse slab (coefficients c0, c1) to its halves:
+//   first half (c0 - c1/2, c1/2), second half (c0 + c1/2, c1/2); degree 0: (c, c).
+// Restriction is its transpose.
+__device__ inline void time_restrict(int q, const double *rf, double *out) {
+  // rf: [2][q] fine values of the two halves
+  if (q == 1) {
+    out[0] = rf[0] + rf[1];
+  } else {
+    out[0] = rf[0] + rf[2];
+    out[1] = 0.5 * (-rf[0] + rf[1] + rf[2] + rf[3]);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr,
+                                                    const int32_t *col, const double *val,
+                                                    const double *rf, double *rc) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (coarse row, coarse slab)
+  if (i >= (int64_t)n_c * Nc) return;
+  const int32_t row = (int32_t)(i / Nc), m = (int32_t)(i % Nc);
+  const int Wf = 2 * Nc * q;
+  double acc[2] = {0.0, 0.0};
+  if (ptr) {
+    for (int64_t k = ptr[row]; k < ptr[row + 1]; ++k) {
+      double t[2];
+      time_restrict(q, rf + (int64_t)col[k] * Wf + 2 * m * q, t);
+      acc[0] += val[k] * t[0];
+      if (q == 2) acc[1] += val[k] * t[1];
+    }
+  } else {
+    time_restrict(q, rf + (int64_t)row * Wf + 2 * m * q, acc);
+  }
+  rc[i * q] = acc[0];
+  if (q == 2) rc[i * q + 1] = acc[1];
+}
+
+void launch_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
+                     const double *val, const double *r_f, double *r_c, hipStream_t s) {
+  const int64_t n = (int64_t)n_c * Nc;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_c, Nc, q,
+                     ptr, col, val, r_f, r_c);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(int32_t n_f, int32_t Nc, int32_t q,
+                                                       const int64_t *ptr, const int32_t *col,
+                                                       const double *val, const double *ec,
+                                                       double *xf) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (fine row, coarse slab)
+  if (i >= (int64_t)n_f * Nc) return;
+  const int32_t row = (int32_t)(i / Nc), m = (int32_t)(i % Nc);
+  const int Wc = Nc * q;
+  double c[2] = {0.0, 0.0};
+  if (ptr) {
+    for (int64_t k = ptr[row]; k < ptr[row + 1]; ++k) {
+      const double *e = ec + (int64_t)col[k] * Wc + m * q;
+      c[0] += val[k] * e[0];
+      if (q == 2) c[1] += val[k] * e[1];
+    }
+  } else {
+    const double *e = ec + (int64_t)row * Wc + m * q;
+    c[0] = e[0];
+    if (q == 2) c[1] = e[1];
+  }
+  double *x = xf + (int64_t)row * (2 * Wc) + 2 * m * q;
+  if (q == 1) {
+    x[0] += c[0];
+    x[1] += c[0];
+  } else {
+    x[0] += c[0] - 0.5 * c[1];
+    x[1] += 0.5 * c[1];
+    x[2] += c[0] + 0.5 * c[1];
+    x[3] += 0.5 * c[1];
+  }
+}
+
+void launch_prolong_add(int32_t n_f, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
+                        const double *val, const double *e_c, double *x_f, hipStream_t s) {
+  const int64_t n = (int64_t)n_f * Nc;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_prolong_add, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_f, Nc,
+                     q, ptr, col, val, e_c, x_f);
+}
+
+// ------------------------------------------------------------------ layout
+__global__ __launch_bounds__(BLOCK) void k_abi_to_internal(int32_t n_rows, int32_t W, int32_t ncols,
+                                                           const int32_t *map, const double *in,
+                                                           double *out) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= (int64_t)n_rows * W) return;
+  const int32_t row = (int32_t)(i / W), c = (int32_t)(i % W);
+  out[i] = in[(int64_t)c * ncols + map[row]];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_internal_to_abi(int32_t n_rows, int32_t W, int32_t ncols,
+                                                           const int32_t *map, const double *in,
+                                                           double *out) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= (int64_t)n_rows * W) return;
+  const int32_t row = (int32_t)(i / W), c = (int32_t)(i % W);
+  out[(int64_t)c * ncols + map[row]] = in[i];
+}
+
+void launch_abi_to_internal(int32_t n_rows, int32_t N, int32_t q, int32_t ncols, const int32_t *map,
+                            const double *in, double *out, hipStream_t s) {
+  const int64_t n = (int64_t)n_rows * N * q;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_abi_to_internal, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                     n_rows, N * q, ncols, map, in, out);
+}
+
+void launch_internal_to_abi(int32_t n_rows, int32_t N, int32_t q, int32_t ncols, const int32_t *map,
+                            const double *in, double *out, hipStream_t s) {
+  const int64_t n = (int64_t)n_rows * N * q;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_internal_to_abi, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                     n_rows, N * q, ncols, map, in, out);
+}
+
+// b[row][0][k] += psi_k(0) (M u0)[row], psi_0(0) = 1, psi_1(0) = -1
+__global__ __launch_bounds__(BLOCK) void k_fold_initial(int32_t n_rows, int32_t W, int32_t q,
+                                                        const int64_t *ptr, const int32_t *col,
+                                                        const double *mval, const int32_t *map,
+                                                        const double *u0, double *b) {
+  const int32_t row = blockIdx.x * BLOCK + threadIdx.x;
+  if (row >= n_rows) return;
+  double acc = 0.0;
+  for (int64_t k = ptr[row]; k < ptr[row + 1]; ++k) acc += mval[k] * u0[map[col[k]]];
+  b[(int64_t)row * W] += acc;
+  if (q == 2) b[(int64_t)row * W + 1] -= acc;
+}
+
+void launch_fold_initial(int32_t n_rows, int32_t N, int32_t q, const int64_t *ptr, const int32_t *col,
+                         const double *mval, const int32_t *map, const double *u0_abi, double *b,
+                         hipStream_t s) {
+  if (n_rows == 0) return;
+  hipLaunchKernelGGL(k_fold_initial, dim3((n_rows + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n_rows, N * q,
+                     q, ptr, col, mval, map, u0_abi, b);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill(double *p, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(BLOCK), 0, s, p, n, v);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_axpy(int64_t n, double a, const double *x, double *y) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) y[i] += a * x[i];
+}
+
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(BLOCK), 0, s, n, a, x, y);
+}
+
+// ------------------------------------------------------ triangular solves
+namespace {
+
+__device__ inline double sc_zero(double) { return 0.0; }
+__device__ inline cd sc_zero(cd) { return {0.0, 0.0}; }
+__device__ inline void sc_fma(double &acc, double a, double b) { acc += a * b; }
+__device__ inline void sc_fma(cd &acc, cd a, cd b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+__device__ inline void sc_sub(double &y, double a) { y -= a; }
+__device__ inline void sc_sub(cd &y, cd a) {
+  y.re -= a.re;
+  y.im -= a.im;
+}
+__device__ inline void sc_add(double &y, double a) { y += a; }
+__device__ inline void sc_add(cd &y, cd a) {
+  y.re += a.re;
+  y.im += a.im;
+}
+
+template <typename T>
+struct Tile {
+  static constexpr int TC = sizeof(T) == 8 ? 32 : 16;  // right-hand-side columns per tile
+};
+
+__device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].tile_begin <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+// Forward assembly (extend-add): each target row of a front receives the
+// children's update rows in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int64_t *src, int32_t nc, T *X,
+                                                T *U) {
+  const AsmTarget t = tgt[blockIdx.x];
+  const int64_t s1 = tgt[blockIdx.x + 1].src_begin;
+  for (int c = threadIdx.x; c < nc; c += 64) {
+    T acc = sc_zero(T{});
+    for (int64_t k = t.src_begin; k < s1; ++k) sc_add(acc, U[src[k] * nc + c]);
+    if (t.dst >= 0)
+      sc_add(X[t.dst * nc + c], acc);
+    else
+      U[(-1 - t.dst) * nc + c] = acc;
+  }
+}
+
+// Forward step k of a batch of supernodes: Y_k = inv(L_kk) F_k (written to Z
+// by the first row tile), then F[rows below block k] -= L[rows, k-block] Y_k,
+// rows below being the supernode's remaining columns (rows of X) and its
+// structure R_s (rows of its U block).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fwd_step(FactorDev f, int32_t k, const SolveTask *tasks,
+                                                    int32_t n_tasks, int32_t nc, T *X, T *Z, T *U) {
+  constexpr int TC = Tile<T>::TC;
+  __shared__ T Fk[NB][TC];
+  __shared__ T Y[NB][TC];
+  const int ti = find_task(tasks, n_tasks, blockIdx.x);
+  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
+  const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
+  const int k0 = k * NB, kb = min(NB, w - k0);
+  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
+  const T *D = reinterpret_cast<const T *>(f.dinv) + f.dinv_off[s] + (int64_t)k * NB * NB;
+  const int cb = blockIdx.y * TC;
+  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+    const int t = idx / TC, j = idx % TC;
+    Fk[t][j] = (t < kb && cb + j < nc) ? X[(int64_t)(c0 + k0 + t) * nc + cb + j] : sc_zero(T{});
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+    const int t = idx / TC, j = idx % TC;
+    T acc = sc_zero(T{});
+    if (t < kb)
+      for (int u = 0; u <= t; ++u) sc_fma(acc, D[t + u * NB], Fk[u][j]);
+    Y[t][j] = acc;
+  }
+  __syncthreads();
+  if (rt == 0)
+    for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+      const int t = idx / TC, j = idx % TC;
+      if (t < kb && cb + j < nc) Z[(int64_t)(c0 + k0 + t) * nc + cb + j] = Y[t][j];
+    }
+  constexpr int JG = TC / 4;
+  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  const int rho = k0 + kb + rt * 64 + i;
+  if (rho < m) {
+    T acc[JG];
+#pragma unroll
+    for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
+    for (int t = 0; t < kb; ++t) {
+      const T a = P[(int64_t)(k0 + t) * m + rho];
+#pragma unroll
+      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Y[t][jg * JG + j]);
+    }
+    T *dst = rho < w ? X + (int64_t)(c0 + rho) * nc : U + (f.uoff[s] + (rho - w)) * nc;
+#pragma unroll
+    for (int j = 0; j < JG; ++j) {
+      const int c = cb + jg * JG + j;
+      if (c < nc) sc_sub(dst[c], acc[j]);
+    }
+  }
+}
+
+// Backward initialisation: Z[C_s] -= L_{R_s,s}^T X[R_s] (X holds final
+// values of the ancestors' rows).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bwd_init(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+                                                    int32_t nc, const T *X, T *Z) {
+  constexpr int TC = Tile<T>::TC;
+  constexpr int KC = 32;  // rows of R_s per chunk
+  __shared__ T Lt[KC][65];
+  __shared__ T Xc[KC][TC];
+  const int ti = find_task(tasks, n_tasks, blockIdx.x);
+  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
+  const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s], r = m - w;
+  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
+  const int32_t *R = f.rows + f.rptr[s];
+  const int cb = blockIdx.y * TC;
+  constexpr int JG = TC / 4;
+  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  const int col = rt * 64 + i;  // column of the supernode (row of Z)
+  T acc[JG];
+#pragma unroll
+  for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
+  for (int j0 = 0; j0 < r; j0 += KC) {
+    const int kc = min(KC, r - j0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < KC * 64; idx += BLOCK) {
+      const int jj = idx % KC, ii = idx / KC;  // jj fastest: contiguous in the panel
+      const int cc = rt * 64 + ii;
+      Lt[jj][ii] = (jj < kc && cc < w) ? P[(int64_t)cc * m + w + j0 + jj] : sc_zero(T{});
+    }
+    for (int idx = threadIdx.x; idx < KC * TC; idx += BLOCK) {
+      const int jj = idx / TC, c = idx % TC;
+      Xc[jj][c] = (jj < kc && cb + c < nc) ? X[(int64_t)R[j0 + jj] * nc + cb + c] : sc_zero(T{});
+    }
+    __syncthreads();
+    for (int jj = 0; jj < kc; ++jj) {
+      const T a = Lt[jj][i];
+#pragma unroll
+      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Xc[jj][jg * JG + j]);
+    }
+  }
+  if (col < w) {
+#pragma unroll
+    for (int j = 0; j < JG; ++j) {
+      const int c = cb + jg * JG + j;
+      if (c < nc) sc_sub(Z[(int64_t)(c0 + col) * nc + c], acc[j]);
+    }
+  }
+}
+
+// Backward step k: z_k = inv(L_kk)^T F_k (written to X by the first row
+// tile), then F[rows < k0] -= L[k-block, rows]^T z_k (rows of Z).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bwd_step(FactorDev f, int32_t k, const SolveTask *tasks,
+                                                    int32_t n_tasks, int32_t nc, T *X, T *Z) {
+  constexpr int TC = Tile<T>::TC;
+  __shared__ T Fk[NB][TC];
+  __shared__ T Yz[NB][TC];
+  __shared__ T Lb[NB][65];
+  const int ti = find_task(tasks, n_tasks, blockIdx.x);
+  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
+  const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
+  const int k0 = k * NB, kb = min(NB, w - k0);
+  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
+  const T *D = reinterpret_cast<const T *>(f.dinv) + f.dinv_off[s] + (int64_t)k * NB * NB;
+  const int cb = blockIdx.y * TC;
+  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+    const int t = idx / TC, j = idx % TC;
+    Fk[t][j] = (t < kb && cb + j < nc) ? Z[(int64_t)(c0 + k0 + t) * nc + cb + j] : sc_zero(T{});
+  }
+  // L block rows k0..k0+kb, columns rt*64 .. rt*64+63 (< k0): Lb[t][jj]
+  for (int idx = threadIdx.x; idx < NB * 64; idx += BLOCK) {
+    const int t = idx % NB, jj = idx / NB;  // t fastest: contiguous in the panel
+    const int cc = rt * 64 + jj;
+    Lb[t][jj] = (t < kb && cc < k0) ? P[(int64_t)cc * m + k0 + t] : sc_zero(T{});
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+    const int t = idx / TC, j = idx % TC;
+    T acc = sc_zero(T{});
+    if (t < kb)
+      for (int u = t; u < kb; ++u) sc_fma(acc, D[u + t * NB], Fk[u][j]);
+    Yz[t][j] = acc;
+  }
+  __syncthreads();
+  if (rt == 0)
+    for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
+      const int t = idx / TC, j = idx % TC;
+      if (t < kb && cb + j < nc) X[(int64_t)(c0 + k0 + t) * nc + cb + j] = Yz[t][j];
+    }
+  constexpr int JG = TC / 4;
+  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  const int row = rt * 64 + i;
+  if (row < k0) {
+    T acc[JG];
+#pragma unroll
+    for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
+    for (int t = 0; t < kb; ++t) {
+      const T a = Lb[t][i];
+#pragma unroll
+      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Yz[t][jg * JG + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < JG; ++j) {
+      const int c = cb + jg * JG + j;
+      if (c < nc) sc_sub(Z[(int64_t)(c0 + row) * nc + c], acc[j]);
+    }
+  }
+}
+
+template <typename T>
+void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, T *U, hipStream_t s) {
+  constexpr int TC = Tile<T>::TC;
+  const unsigned ctiles = (unsigned)((nc + TC - 1) / TC);
+  for (int h = 0; h < p.n_heights; ++h) {
+    const int64_t t0 = p.h_tgt_off[h], t1 = p.h_tgt_off[h + 1];
+    if (t1 > t0)
+      hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)(t1 - t0)), dim3(64), 0, s, p.tgt + t0, p.src, nc,
+                         X, U);
+    for (int l = p.h_fwd_begin[h]; l < p.h_fwd_begin[h + 1]; ++l) {
+      const SolvePlan::Launch &L = p.fwd[l];
+      hipLaunchKernelGGL((k_fwd_step<T>), dim3((unsigned)L.n_tiles, ctiles), dim3(BLOCK), 0, s, f, L.k,
+                         L.tasks, L.n_tasks, nc, X, Z, U);
+    }
+  }
+}
+
+template <typename T>
+void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s) {
+  constexpr int TC = Tile<T>::TC;
+  const unsigned ctiles = (unsigned)((nc + TC - 1) / TC);
+  for (int h = p.n_heights - 1; h >= 0; --h) {
+    const SolvePlan::Launch &I = p.bwd_init[h];
+    if (I.n_tasks > 0)
+      hipLaunchKernelGGL((k_bwd_init<T>), dim3((unsigned)I.n_tiles, ctiles), dim3(BLOCK), 0, s, f, I.tasks,
+                         I.n_tasks, nc, X, Z);
+    for (int l = p.h_bwd_begin[h]; l < p.h_bwd_begin[h + 1]; ++l) {
+      const SolvePlan::Launch &L = p.bwd[l];
+      hipLaunchKernelGGL((k_bwd_step<T>), dim3((unsigned)L.n_tiles, ctiles), dim3(BLOCK), 0, s, f, L.k,
+                         L.tasks, L.n_tasks, nc, X, Z);
+    }
+  }
+}
+
+template void solve_forward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,
+                                    double *, hipStream_t);
+template void solve_forward<cd>(const FactorDev &, const SolvePlan &, int32_t, cd *, cd *, cd *, hipStream_t);
+template void solve_backward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,
+                                     hipStream_t);
+template void solve_backward<cd>(const FactorDev &, const SolvePlan &, int32_t, cd *, cd *, hipStream_t);
+
+}  // namespace stmg

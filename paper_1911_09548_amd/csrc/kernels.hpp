@@ -1,0 +1,129 @@
+// Device kernels of the space-time V-cycle (launch wrappers, host side).
+//
+// Internal vector layout: row-major [row][slab][component]; a row holds all
+// N*q coefficients of one spatial DOF (an interior edge or vertex), numbered
+// in the nested-dissection order of that level's factor. Slab-solve vectors
+// hold one scalar per slab (complex for DG degree 1, real for degree 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stmg {
+
+struct cd {  // complex double, 16-byte aligned
+  double re, im;
+};
+
+// Space-time residual of one level (fused SpMM with M and K on their shared
+// pattern + DG coupling to the previous slab in the same row).
+struct ResidualArgs {
+  int32_t n_rows;
+  int32_t N, q;                 // slabs, components
+  const int64_t *ptr;
+  const int32_t *col;
+  const double *mval, *kval;
+  double tau;
+  const double *x;              // may be null: x = 0
+  const double *b;
+  double *out;
+  double *partial;              // may be null: per-block sum of squares of r
+  int32_t mode;                 // 0: out = r; 1: out = slab-solve right-hand side
+};
+enum { RES_OUT_R = 0, RES_OUT_SLABRHS = 1 };
+int residual_blocks(int32_t n_rows, int32_t W, int32_t q);
+void launch_residual(const ResidualArgs &a, hipStream_t s);
+
+// Sum of `n` doubles in fixed order (deterministic), result at out[0].
+void launch_sum(const double *partial, int32_t n, double *out, hipStream_t s);
+// Sum of squares of v[0..n) into partial[blocks]; returns number of blocks.
+int launch_sumsq(const double *v, int64_t n, double *partial, hipStream_t s);
+
+// Jacobi update x += omega * (time back-transform of z) (eq. (2)).
+// q = 2: x0 += omega 2 Re z, x1 += omega 2 (Re z - sqrt2 Im z); q = 1: x += omega z.
+// assign != 0: x = (...) instead of +=.
+void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const double *z,
+                        double *x, int assign, hipStream_t s);
+// Slab-solve right-hand side from a residual-layout vector r (no SpMV).
+void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const double *r, double *w, hipStream_t s);
+
+// Nodal correction pieces (eq. (8)).
+void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edge, const int8_t *sign,
+                  const double *r, double *g, hipStream_t s);
+void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t s);
+void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const double *y,
+                     double *x, hipStream_t s);
+
+// Space-time transfers. P_s given as CSR (rows: coarse for restrict = P^T,
+// fine for prolong = P); identity when ptr == nullptr (then map gives the row
+// correspondence... rows coincide).
+void launch_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
+                     const double *val, const double *r_f, double *r_c, hipStream_t s);
+void launch_prolong_add(int32_t n_f, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
+                        const double *val, const double *e_c, double *x_f, hipStream_t s);
+
+// Layout changes between ABI vectors [N][q][ncols] and internal [row][N][q];
+// map[row] = ABI column of the internal row.
+void launch_abi_to_internal(int32_t n_rows, int32_t N, int32_t q, int32_t ncols, const int32_t *map,
+                            const double *in, double *out, hipStream_t s);
+void launch_internal_to_abi(int32_t n_rows, int32_t N, int32_t q, int32_t ncols, const int32_t *map,
+                            const double *in, double *out, hipStream_t s);
+// out[0][k][map[e]] += psi_k(0) * (M u0)[e] for the first slab; Mu0 computed
+// from u0 given in ABI column order.
+void launch_fold_initial(int32_t n_rows, int32_t N, int32_t q, const int64_t *ptr, const int32_t *col,
+                         const double *mval, const int32_t *map, const double *u0_abi, double *b,
+                         hipStream_t s);
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+
+// ------------------------------------------------------------------ solves
+// Multifrontal forward/backward solves with a supernodal L (L L^T = A) for
+// `nc` right-hand sides stored as rows of X (one row per matrix row).
+struct FactorDev {
+  int32_t ns, n;
+  const int32_t *col0;     // [ns+1]
+  const int32_t *m;        // [ns] w + r
+  const int64_t *rptr;     // [ns+1]
+  const int32_t *rows;
+  const int64_t *panel_off, *dinv_off;
+  const int64_t *uoff;     // [ns] first U row of each supernode
+  const void *panel, *dinv;
+};
+struct SolveTask {
+  int32_t s;
+  int32_t tile_begin;      // prefix of row tiles
+};
+struct AsmTarget {
+  int64_t dst;             // >= 0: X row; < 0: U row (-1 - index)
+  int64_t src_begin;       // into asm_src
+};
+// Kernel launch plan of one factor (all arrays on device, built on the host).
+struct SolvePlan {
+  // forward assembly per height: targets [tgt_off[h], tgt_off[h+1]); each
+  // target's sources [src_begin, next src_begin)
+  int32_t n_heights;
+  const int64_t *h_tgt_off;      // host [H+1]
+  const AsmTarget *tgt;          // device [n_tgt + 1] (sentinel)
+  const int64_t *src;            // device U rows
+  // step launches: host descriptors, device task arrays
+  struct Launch {
+    int32_t k;                   // diagonal block index
+    int32_t n_tasks, n_tiles;
+    const SolveTask *tasks;      // device
+  };
+  // forward: per height, steps k = 0..; backward init per height; backward steps
+  const int32_t *h_fwd_begin;    // host [H+1] into fwd
+  const Launch *fwd;             // host array
+  const Launch *bwd_init;        // host [H] (k unused)
+  const int32_t *h_bwd_begin;    // host [H+1] into bwd (k descending within a height)
+  const Launch *bwd;             // host array
+};
+
+template <typename T>
+void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, T *U, hipStream_t s);
+template <typename T>
+void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s);
+
+}  // namespace stmg

@@ -1,0 +1,881 @@
+// The stmg C ABI: setup of the space-time hierarchy, device uploads and the
+// V-cycle driver (sections 2-4 of the paper; see include/stmg.h).
+#include "solver.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <numeric>
+
+using namespace stmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guard(F &&fn) {
+  try {
+    fn();
+    return STMG_OK;
+  } catch (const StmgError &e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return STMG_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return STMG_EINVAL;
+  }
+}
+
+void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory) ? STMG_ENOMEM : STMG_EHIP;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+T *dev_alloc(stmg_handle *h, size_t count) {
+  if (count == 0) count = 1;
+  void *p = nullptr;
+  hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  h->bufs.push_back({p, count * sizeof(T)});
+  h->device_bytes += (int64_t)(count * sizeof(T));
+  return static_cast<T *>(p);
+}
+
+template <typename T>
+T *dev_upload(stmg_handle *h, const T *src, size_t count) {
+  T *p = dev_alloc<T>(h, count);
+  if (count) hip_check(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return p;
+}
+
+template <typename T>
+T *dev_upload(stmg_handle *h, const std::vector<T> &v) {
+  return dev_upload(h, v.data(), v.size());
+}
+
+// ------------------------------------------------------------- solve plans
+void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
+  const int32_t ns = S.ns, H = S.n_heights;
+  std::vector<int64_t> uoff(ns, 0);
+  int64_t u = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    uoff[s] = u;
+    u += S.nrows(s);
+  }
+  D.u_rows = u;
+  std::vector<std::vector<int32_t>> kids(ns), by_h(H);
+  for (int32_t s = 0; s < ns; ++s) {
+    if (S.parent[s] >= 0) kids[S.parent[s]].push_back(s);
+    by_h[S.height[s]].push_back(s);
+  }
+  // forward assembly targets
+  std::vector<AsmTarget> tgt;
+  std::vector<int64_t> src;
+  D.h_tgt_off.assign(H + 1, 0);
+  std::vector<int32_t> pos(S.n, -1);
+  for (int32_t hh = 0; hh < H; ++hh) {
+    D.h_tgt_off[hh] = (int64_t)tgt.size();
+    for (int32_t s : by_h[hh]) {
+      const int32_t c0 = S.col0[s], w = S.width(s), r = S.nrows(s), m = w + r;
+      for (int32_t j = 0; j < w; ++j) pos[c0 + j] = j;
+      for (int32_t i = 0; i < r; ++i) pos[S.rows[S.rptr[s] + i]] = w + i;
+      std::vector<std::vector<int64_t>> srcs(m);
+      for (int32_t ch : kids[s])
+        for (int32_t i = 0; i < S.nrows(ch); ++i) srcs[pos[S.rows[S.rptr[ch] + i]]].push_back(uoff[ch] + i);
+      for (int32_t t = 0; t < m; ++t) {
+        if (t < w && srcs[t].empty()) continue;
+        AsmTarget a;
+        a.dst = t < w ? (int64_t)(c0 + t) : -1 - (uoff[s] + (t - w));
+        a.src_begin = (int64_t)src.size();
+        tgt.push_back(a);
+        src.insert(src.end(), srcs[t].begin(), srcs[t].end());
+      }
+    }
+  }
+  D.h_tgt_off[H] = (int64_t)tgt.size();
+  tgt.push_back({0, (int64_t)src.size()});  // sentinel
+  // step launches
+  std::vector<SolveTask> tasks;
+  struct Pending {
+    int32_t k;
+    size_t off, n;
+    int32_t tiles;
+  };
+  std::vector<Pending> pf, pbi, pb;
+  D.h_fwd_begin.assign(H + 1, 0);
+  D.h_bwd_begin.assign(H + 1, 0);
+  auto nblk = [&](int32_t s) { return (int32_t)n_diag_blocks(S.width(s)); };
+  for (int32_t hh = 0; hh < H; ++hh) {
+    int32_t kmax = 0;
+    for (int32_t s : by_h[hh]) kmax = std::max(kmax, nblk(s));
+    D.h_fwd_begin[hh] = (int32_t)pf.size();
+    for (int32_t k = 0; k < kmax; ++k) {
+      Pending p{k, tasks.size(), 0, 0};
+      for (int32_t s : by_h[hh]) {
+        if (nblk(s) <= k) continue;
+        const int32_t w = S.width(s), m = w + S.nrows(s);
+        const int32_t k0 = k * NB, kb = std::min(NB, w - k0);
+        const int32_t below = m - k0 - kb;
+        tasks.push_back({s, p.tiles});
+        p.tiles += std::max(1, (below + 63) / 64);
+      }
+      p.n = tasks.size() - p.off;
+      pf.push_back(p);
+    }
+    // backward init
+    {
+      Pending p{0, tasks.size(), 0, 0};
+      for (int32_t s : by_h[hh]) {
+        if (S.nrows(s) == 0) continue;
+        tasks.push_back({s, p.tiles});
+        p.tiles += (S.width(s) + 63) / 64;
+      }
+      p.n = tasks.size() - p.off;
+      pbi.push_back(p);
+    }
+    D.h_bwd_begin[hh] = (int32_t)pb.size();
+    for (int32_t k = kmax - 1; k >= 0; --k) {
+      Pending p{k, tasks.size(), 0, 0};
+      for (int32_t s : by_h[hh]) {
+        if (nblk(s) <= k) continue;
+        tasks.push_back({s, p.tiles});
+        p.tiles += std::max(1, (k * NB + 63) / 64);
+      }
+      p.n = tasks.size() - p.off;
+      pb.push_back(p);
+    }
+  }
+  D.h_fwd_begin[H] = (int32_t)pf.size();
+  D.h_bwd_begin[H] = (int32_t)pb.size();
+  SolveTask *dt = dev_upload(h, tasks);
+  AsmTarget *dtg = dev_upload(h, tgt);
+  int64_t *dsrc = dev_upload(h, src);
+  auto mk = [&](const Pending &p) {
+    SolvePlan::Launch L;
+    L.k = p.k;
+    L.n_tasks = (int32_t)p.n;
+    L.n_tiles = p.tiles;
+    L.tasks = dt + p.off;
+    return L;
+  };
+  for (auto &p : pf) D.fwd.push_back(mk(p));
+  for (auto &p : pbi) D.bwd_init.push_back(mk(p));
+  for (auto &p : pb) D.bwd.push_back(mk(p));
+  // factor metadata
+  std::vector<int32_t> m(ns);
+  for (int32_t s = 0; s < ns; ++s) m[s] = S.width(s) + S.nrows(s);
+  D.f.ns = ns;
+  D.f.n = S.n;
+  D.f.col0 = dev_upload(h, S.col0);
+  D.f.m = dev_upload(h, m);
+  D.f.rptr = dev_upload(h, S.rptr);
+  D.f.rows = dev_upload(h, S.rows);
+  D.f.uoff = dev_upload(h, uoff);
+  D.plan.n_heights = H;
+  D.plan.h_tgt_off = D.h_tgt_off.data();
+  D.plan.tgt = dtg;
+  D.plan.src = dsrc;
+  D.plan.h_fwd_begin = D.h_fwd_begin.data();
+  D.plan.fwd = D.fwd.data();
+  D.plan.bwd_init = D.bwd_init.data();
+  D.plan.h_bwd_begin = D.h_bwd_begin.data();
+  D.plan.bwd = D.bwd.data();
+}
+
+template <typename T, typename TH>
+void upload_factor(stmg_handle *h, const HostFactor<TH> &F, DevFactor &D) {
+  static_assert(sizeof(T) == sizeof(TH), "scalar size mismatch");
+  D.f.panel = dev_upload(h, reinterpret_cast<const T *>(F.panel.data()), F.panel.size());
+  D.f.dinv = dev_upload(h, reinterpret_cast<const T *>(F.dinv.data()), F.dinv.size());
+  D.f.panel_off = dev_upload(h, F.panel_off);
+  D.f.dinv_off = dev_upload(h, F.dinv_off);
+  D.factor_bytes = (int64_t)((F.panel.size() + F.dinv.size()) * sizeof(T));
+  h->factor_bytes += D.factor_bytes;
+}
+
+// ------------------------------------------------------------ level setup
+void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
+  SpaceLevel &S = *md.S;
+  const Topo &T = S.topo;
+  md.nd = nested_dissection(T, h->opt.leaf_size);
+  md.sym_e = symbolic_from_tree(md.nd, edge_nodes(T, md.nd), S.M);
+  const bool has_nodal = T.n_int_verts() > 0;
+  if (has_nodal) {
+    md.sym_v = symbolic_from_tree(md.nd, vertex_nodes(T, md.nd), S.Kn);
+    md.nodal_host = std::make_unique<HostFactor<double>>();
+    factor_host<double>(md.sym_v, S.Kn, S.Kn.val, *md.nodal_host);
+  }
+  md.Mp = csr_permute_sym(S.M, md.sym_e.perm);
+  md.Kp = csr_permute_sym(S.K, md.sym_e.perm);
+  if (!device) return;
+  md.d_ptr = dev_upload(h, md.Mp.ptr);
+  md.d_col = dev_upload(h, md.Mp.col);
+  md.d_mval = dev_upload(h, md.Mp.val);
+  md.d_kval = dev_upload(h, md.Kp.val);
+  const int32_t ne = T.n_int_edges(), nv = T.n_int_verts();
+  // G in internal numberings
+  std::vector<int32_t> head(ne, -1), tail(ne, -1);
+  std::vector<int32_t> vi(nv, 0);
+  if (has_nodal) vi = md.sym_v.iperm;
+  for (int32_t r = 0; r < ne; ++r) {
+    const int32_t asc = md.sym_e.perm[r];
+    for (int64_t k = S.G.ptr[asc]; k < S.G.ptr[asc + 1]; ++k) {
+      const int32_t v = vi[S.G.col[k]];
+      if (S.G.val[k] > 0)
+        head[r] = v;
+      else
+        tail[r] = v;
+    }
+  }
+  md.d_head = dev_upload(h, head);
+  md.d_tail = dev_upload(h, tail);
+  std::vector<int64_t> gptr(nv + 1, 0);
+  for (int32_t r = 0; r < ne; ++r) {
+    if (head[r] >= 0) gptr[head[r] + 1]++;
+    if (tail[r] >= 0) gptr[tail[r] + 1]++;
+  }
+  for (int32_t v = 0; v < nv; ++v) gptr[v + 1] += gptr[v];
+  std::vector<int32_t> gedge(gptr[nv]);
+  std::vector<int8_t> gsign(gptr[nv]);
+  {
+    std::vector<int64_t> nx(gptr.begin(), gptr.end() - 1);
+    for (int32_t r = 0; r < ne; ++r) {  // ascending edge order within each vertex row
+      if (head[r] >= 0) {
+        gedge[nx[head[r]]] = r;
+        gsign[nx[head[r]]++] = 1;
+      }
+      if (tail[r] >= 0) {
+        gedge[nx[tail[r]]] = r;
+        gsign[nx[tail[r]]++] = -1;
+      }
+    }
+  }
+  md.d_gt_ptr = dev_upload(h, gptr);
+  md.d_gt_edge = dev_upload(h, gedge);
+  md.d_gt_sign = dev_upload(h, gsign);
+  md.d_map_level = dev_upload(h, md.sym_e.perm);
+  if (md.index == 0) {
+    std::vector<int32_t> abi(ne);
+    for (int32_t r = 0; r < ne; ++r) abi[r] = T.int_edges[md.sym_e.perm[r]];
+    md.d_map_abi = dev_upload(h, abi);
+  }
+  if (has_nodal) {
+    build_plan(h, md.sym_v, md.nodal);
+    upload_factor<double>(h, *md.nodal_host, md.nodal);
+    if (!h->opt.host_only) md.nodal_host.reset();
+  }
+}
+
+void setup_transfer(stmg_handle *h, MeshData &fine, MeshData &coarse) {
+  // P_e (finer interior asc x coarse interior asc) -> internal numberings
+  const Csr &P = coarse.S->Pe;
+  Csr Pi;
+  Pi.n_rows = P.n_rows;
+  Pi.n_cols = P.n_cols;
+  Pi.ptr.assign(P.n_rows + 1, 0);
+  for (int32_t r = 0; r < P.n_rows; ++r) {
+    const int32_t o = fine.sym_e.perm[r];
+    Pi.ptr[r + 1] = Pi.ptr[r] + (P.ptr[o + 1] - P.ptr[o]);
+  }
+  for (int32_t r = 0; r < P.n_rows; ++r) {
+    const int32_t o = fine.sym_e.perm[r];
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t k = P.ptr[o]; k < P.ptr[o + 1]; ++k) row.push_back({coarse.sym_e.iperm[P.col[k]], P.val[k]});
+    std::sort(row.begin(), row.end());
+    for (auto &e : row) {
+      Pi.col.push_back(e.first);
+      Pi.val.push_back(e.second);
+    }
+  }
+  Csr Pt = csr_transpose(Pi);
+  coarse.d_p_ptr = dev_upload(h, Pi.ptr);
+  coarse.d_p_col = dev_upload(h, Pi.col);
+  coarse.d_p_val = dev_upload(h, Pi.val);
+  coarse.d_pt_ptr = dev_upload(h, Pt.ptr);
+  coarse.d_pt_col = dev_upload(h, Pt.col);
+  coarse.d_pt_val = dev_upload(h, Pt.val);
+}
+
+void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
+  MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+  const SpaceLevel &S = *md.S;
+  const int64_t nnz = S.M.nnz();
+  if (h->pt == 1) {
+    std::vector<cplx> v(nnz);
+    const double s2 = std::sqrt(2.0);
+    for (int64_t k = 0; k < nnz; ++k) v[k] = {2.0 * S.M.val[k] + L.tau * S.K.val[k], s2 * S.M.val[k]};
+    L.slab_host_c = std::make_unique<HostFactor<cplx>>();
+    factor_host<cplx>(md.sym_e, S.M, v, *L.slab_host_c);
+    if (device) {
+      L.slab.is_complex = true;
+      build_plan(h, md.sym_e, L.slab);
+      upload_factor<cd>(h, *L.slab_host_c, L.slab);
+      if (!h->opt.host_only) L.slab_host_c.reset();
+    }
+  } else {
+    std::vector<double> v(nnz);
+    for (int64_t k = 0; k < nnz; ++k) v[k] = S.M.val[k] + L.tau * S.K.val[k];
+    L.slab_host_r = std::make_unique<HostFactor<double>>();
+    factor_host<double>(md.sym_e, S.M, v, *L.slab_host_r);
+    if (device) {
+      build_plan(h, md.sym_e, L.slab);
+      upload_factor<double>(h, *L.slab_host_r, L.slab);
+      if (!h->opt.host_only) L.slab_host_r.reset();
+    }
+  }
+}
+
+void alloc_level_vectors(stmg_handle *h, LevelData &L) {
+  MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+  const int64_t ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
+  const int64_t W = (int64_t)L.N * h->q;
+  L.x = dev_alloc<double>(h, ne * W);
+  L.b = dev_alloc<double>(h, ne * W);
+  L.w = dev_alloc<double>(h, ne * W);
+  L.z = dev_alloc<double>(h, ne * W);
+  L.u = dev_alloc<double>(h, std::max<int64_t>(1, L.slab.u_rows * W));
+  if (nv > 0) {
+    L.g = dev_alloc<double>(h, nv * W);
+    L.zn = dev_alloc<double>(h, nv * W);
+    L.un = dev_alloc<double>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
+  }
+}
+
+// --------------------------------------------------------------- operators
+struct Ops {
+  stmg_handle *h;
+  hipStream_t s;
+
+  MeshData &mesh(int l) { return h->meshes[h->mesh_slot[h->levels[l].mesh]]; }
+  int32_t ne(int l) { return mesh(l).S->topo.n_int_edges(); }
+  int32_t nv(int l) { return mesh(l).S->topo.n_int_verts(); }
+  int32_t W(int l) { return h->levels[l].N * h->q; }
+
+  void residual(int l, const double *x, const double *b, double *out, int mode, double *partial) {
+    MeshData &md = mesh(l);
+    ResidualArgs a;
+    a.n_rows = ne(l);
+    a.N = h->levels[l].N;
+    a.q = h->q;
+    a.ptr = md.d_ptr;
+    a.col = md.d_col;
+    a.mval = md.d_mval;
+    a.kval = md.d_kval;
+    a.tau = h->levels[l].tau;
+    a.x = x;
+    a.b = b;
+    a.out = out;
+    a.partial = partial;
+    a.mode = mode;
+    launch_residual(a, s);
+  }
+
+  // w <- A_l^{-1} w in place (slab right-hand-side layout)
+  void slab_solve(int l, double *w) {
+    LevelData &L = h->levels[l];
+    const int32_t nc = L.N;
+    if (L.slab.is_complex) {
+      solve_forward<cd>(L.slab.f, L.slab.plan, nc, (cd *)w, (cd *)L.z, (cd *)L.u, s);
+      solve_backward<cd>(L.slab.f, L.slab.plan, nc, (cd *)w, (cd *)L.z, s);
+    } else {
+      solve_forward<double>(L.slab.f, L.slab.plan, nc, w, L.z, L.u, s);
+      solve_backward<double>(L.slab.f, L.slab.plan, nc, w, L.z, s);
+    }
+  }
+
+  void smooth_S(int l, double *x, const double *b) {
+    LevelData &L = h->levels[l];
+    residual(l, x, b, L.w, RES_OUT_SLABRHS, nullptr);
+    slab_solve(l, L.w);
+    launch_slab_update(ne(l), L.N, h->q, h->opt.omega, L.w, x, 0, s);
+  }
+
+  void nodal_A(int l, double *x, const double *b) {
+    LevelData &L = h->levels[l];
+    MeshData &md = mesh(l);
+    if (nv(l) == 0) return;
+    const int32_t w = W(l);
+    residual(l, x, b, L.w, RES_OUT_R, nullptr);
+    launch_gradT(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, L.w, L.g, s);
+    solve_forward<double>(md.nodal.f, md.nodal.plan, w, L.g, L.zn, L.un, s);
+    solve_backward<double>(md.nodal.f, md.nodal.plan, w, L.g, L.zn, s);
+    launch_time_scan(nv(l), L.N, h->q, L.g, s);
+    launch_grad_add(ne(l), w, md.d_head, md.d_tail, L.g, x, s);
+  }
+
+  void hybrid(int l, double *x, const double *b) {
+    smooth_S(l, x, b);
+    if (h->opt.smoother == STMG_SMOOTH_SAS) nodal_A(l, x, b);
+    smooth_S(l, x, b);
+  }
+
+  void exact(int l, double *x, const double *b) {
+    LevelData &L = h->levels[l];
+    launch_slab_rhs(ne(l), L.N, h->q, b, L.w, s);
+    slab_solve(l, L.w);
+    launch_slab_update(ne(l), L.N, h->q, 1.0, L.w, x, 1, s);
+  }
+
+  void restrict_to(int l, const double *rf, double *rc) {
+    LevelData &C = h->levels[l + 1];
+    if (C.mesh != h->levels[l].mesh) {
+      MeshData &mc = mesh(l + 1);
+      launch_restrict(ne(l + 1), C.N, h->q, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, rf, rc, s);
+    } else {
+      launch_restrict(ne(l + 1), C.N, h->q, nullptr, nullptr, nullptr, rf, rc, s);
+    }
+  }
+
+  void prolong_add(int l, const double *ec, double *xf) {
+    // from level l+1 to level l
+    LevelData &C = h->levels[l + 1];
+    if (C.mesh != h->levels[l].mesh) {
+      MeshData &mc = mesh(l + 1);
+      launch_prolong_add(ne(l), C.N, h->q, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, ec, xf, s);
+    } else {
+      launch_prolong_add(ne(l), C.N, h->q, nullptr, nullptr, nullptr, ec, xf, s);
+    }
+  }
+
+  void vcycle(int l, double *x, const double *b) {
+    LevelData &L = h->levels[l];
+    if (L.N == 1) {
+      exact(l, x, b);
+      return;
+    }
+    hybrid(l, x, b);
+    residual(l, x, b, L.w, RES_OUT_R, nullptr);
+    LevelData &C = h->levels[l + 1];
+    restrict_to(l, L.w, C.b);
+    launch_fill(C.x, (int64_t)ne(l + 1) * W(l + 1), 0.0, s);
+    vcycle(l + 1, C.x, C.b);
+    prolong_add(l, C.x, x);
+    hybrid(l, x, b);
+  }
+
+  // ||b - L x||^2 into d_scalar[slot] (device)
+  void residual_norm2(int l, const double *x, const double *b, double *dst) {
+    residual(l, x, b, h->levels[l].w, RES_OUT_R, h->d_partial);
+    launch_sum(h->d_partial, residual_blocks(ne(l), W(l), h->q), dst, s);
+  }
+};
+
+void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
+
+void require_device(const stmg_handle *h) {
+  STMG_REQUIRE(h, STMG_EINVAL, "null handle");
+  STMG_REQUIRE(!h->opt.host_only, STMG_ENOSYS, "handle was built with host_only");
+}
+
+double *tmp_buf(stmg_handle *h, int i) {
+  if (!h->d_tmp[i]) {
+    const LevelData &L = h->levels[0];
+    const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    h->d_tmp[i] = dev_alloc<double>(h, (size_t)md.S->topo.n_int_edges() * L.N * h->q);
+  }
+  return h->d_tmp[i];
+}
+
+void destroy_handle(stmg_handle *h) {
+  if (!h) return;
+  for (auto &b : h->bufs) (void)hipFree(b.p);
+  delete h;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *stmg_strerror(int code) {
+  switch (code) {
+    case STMG_OK: return "ok";
+    case STMG_EINVAL: return "invalid argument";
+    case STMG_ENOMEM: return "out of memory";
+    case STMG_ENOTCONV: return "not converged";
+    case STMG_ENUMERIC: return "numerical breakdown";
+    case STMG_EHIP: return "HIP runtime error";
+    case STMG_EAGAIN: return "not ready";
+    case STMG_ENOSYS: return "not available";
+    default: return "unknown error";
+  }
+}
+
+const char *stmg_last_error_message(void) { return g_err.c_str(); }
+
+void stmg_default_options(stmg_options *o) {
+  if (!o) return;
+  o->omega = 0.5;
+  o->lambda_crit = 0.1;
+  o->allow_space_coarsening = 1;
+  o->smoother = STMG_SMOOTH_SAS;
+  o->precision = STMG_FP64;
+  o->rtol = 1e-8;
+  o->max_cycles = 100;
+  o->host_only = 0;
+  o->factor_on_device = 0;
+  o->leaf_size = 8;
+}
+
+int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
+  if (out) *out = nullptr;
+  stmg_handle *h = nullptr;
+  int rc = guard([&] {
+    STMG_REQUIRE(prob && out, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(prob->Nt >= 1 && (prob->Nt & (prob->Nt - 1)) == 0, STMG_EINVAL, "Nt must be a power of two");
+    STMG_REQUIRE(prob->pt == 0 || prob->pt == 1, STMG_EINVAL, "pt must be 0 or 1");
+    STMG_REQUIRE(prob->T > 0 && std::isfinite(prob->T), STMG_EINVAL, "T must be > 0");
+    const double t0 = wall_time();
+    h = new stmg_handle();
+    if (opt)
+      h->opt = *opt;
+    else
+      stmg_default_options(&h->opt);
+    STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
+    STMG_REQUIRE(h->opt.precision == STMG_FP64, STMG_ENOSYS, "precision form not available yet");
+    if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
+    if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->pt = prob->pt;
+    h->q = prob->pt + 1;
+    h->Nt = prob->Nt;
+    h->T = prob->T;
+    const bool device = !h->opt.host_only;
+    if (device) {
+      int ndev = 0;
+      hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+      STMG_REQUIRE(ndev > 0, STMG_EHIP, "no HIP device");
+    }
+    h->space = build_space_levels(*prob);
+    // space-time levels: halve N; coarsen space where eq. (3) holds
+    LevelData L0;
+    L0.mesh = 0;
+    L0.N = prob->Nt;
+    L0.tau = prob->T / prob->Nt;
+    h->levels.push_back(std::move(L0));
+    while (h->levels.back().N > 1) {
+      LevelData &c = h->levels.back();
+      c.lambda = h->space[c.mesh].anisotropy(c.tau);
+      const bool sp = h->opt.allow_space_coarsening && c.mesh + 1 < (int32_t)h->space.size() &&
+                      c.lambda >= h->opt.lambda_crit;
+      LevelData n;
+      n.mesh = sp ? c.mesh + 1 : c.mesh;
+      n.N = c.N / 2;
+      n.tau = 2.0 * c.tau;
+      h->levels.push_back(std::move(n));
+    }
+    h->levels.back().lambda = h->space[h->levels.back().mesh].anisotropy(h->levels.back().tau);
+    const int32_t used = h->levels.back().mesh + 1;
+    h->mesh_slot.assign(h->space.size(), -1);
+    h->meshes.resize(used);
+    for (int32_t j = 0; j < used; ++j) {
+      h->mesh_slot[j] = j;
+      h->meshes[j].index = j;
+      h->meshes[j].S = &h->space[j];
+      setup_mesh(h, h->meshes[j], device);
+      if (device && j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
+    }
+    for (auto &L : h->levels) {
+      setup_level_factor(h, L, device);
+      if (device) alloc_level_vectors(h, L);
+    }
+    if (device) {
+      const LevelData &L = h->levels[0];
+      h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L.N * h->q, h->q) + 4096;
+      h->d_partial = dev_alloc<double>(h, h->n_partial);
+      h->d_scalar = dev_alloc<double>(h, 8192);
+      hip_check(hipDeviceSynchronize(), "setup");
+    }
+    h->setup_s = wall_time() - t0;
+  });
+  if (rc != STMG_OK) {
+    destroy_handle(h);
+    return rc;
+  }
+  *out = h;
+  return STMG_OK;
+}
+
+void stmg_destroy(stmg_handle *h) { destroy_handle(h); }
+
+int stmg_info(const stmg_handle *h, stmg_info_t *info) {
+  return guard([&] {
+    STMG_REQUIRE(h && info, STMG_EINVAL, "null argument");
+    info->n_edges = h->space[0].topo.ne;
+    info->n_levels = (int32_t)h->levels.size();
+    info->pt = h->pt;
+    info->device_bytes = h->device_bytes;
+    info->factor_bytes = h->factor_bytes;
+  });
+}
+
+int stmg_level_info(const stmg_handle *h, int32_t level, stmg_level_info_t *info) {
+  return guard([&] {
+    STMG_REQUIRE(h && info, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
+    const LevelData &L = h->levels[level];
+    const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    info->mesh = L.mesh;
+    info->N = L.N;
+    info->tau = L.tau;
+    info->n_e = md.S->topo.n_int_edges();
+    info->n_v = md.S->topo.n_int_verts();
+    info->nnz_pattern = md.S->M.nnz();
+    info->factor_nnz_slab = md.sym_e.nnz_L;
+    info->factor_nnz_nodal = md.sym_v.nnz_L;
+    info->n_supernodes_slab = md.sym_e.ns;
+    info->lambda = L.lambda;
+  });
+}
+
+int stmg_edges(const stmg_handle *h, int32_t *n_edges, const int32_t **edge_vertices) {
+  return guard([&] {
+    STMG_REQUIRE(h && n_edges && edge_vertices, STMG_EINVAL, "null argument");
+    *n_edges = h->space[0].topo.ne;
+    *edge_vertices = h->space[0].topo.edges.data();
+  });
+}
+
+int stmg_load(stmg_handle *h, const double *rhs_dev, const double *u0_dev, const double *x0_dev,
+              double *bnorm) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(rhs_dev, STMG_EINVAL, "rhs is null");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    MeshData &md = op.mesh(0);
+    const int32_t ne = op.ne(0), E = md.S->topo.ne;
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, rhs_dev, L.b, h->stream);
+    if (u0_dev)
+      launch_fold_initial(ne, L.N, h->q, md.d_ptr, md.d_col, md.d_mval, md.d_map_abi, u0_dev, L.b, h->stream);
+    if (x0_dev)
+      launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, x0_dev, L.x, h->stream);
+    else
+      launch_fill(L.x, (int64_t)ne * op.W(0), 0.0, h->stream);
+    const int nb = launch_sumsq(L.b, (int64_t)ne * op.W(0), h->d_partial, h->stream);
+    launch_sum(h->d_partial, nb, h->d_scalar, h->stream);
+    check_launch();
+    double b2 = 0.0;
+    hip_check(hipMemcpyAsync(&b2, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    STMG_REQUIRE(std::isfinite(b2), STMG_ENUMERIC, "non-finite right-hand side");
+    h->bnorm = std::sqrt(b2);
+    h->history.clear();
+    h->cycles = 0;
+    if (bnorm) *bnorm = h->bnorm;
+  });
+}
+
+int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(n_cycles >= 0 && n_cycles <= 8192, STMG_EINVAL, "n_cycles out of range");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    for (int32_t i = 0; i < n_cycles; ++i) {
+      op.vcycle(0, L.x, L.b);
+      op.residual_norm2(0, L.x, L.b, h->d_scalar + i);
+    }
+    check_launch();
+    if (res_host && n_cycles > 0) {
+      std::vector<double> r2(n_cycles);
+      hip_check(hipMemcpyAsync(r2.data(), h->d_scalar, n_cycles * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream),
+                "copy");
+      hip_check(hipStreamSynchronize(h->stream), "sync");
+      for (int32_t i = 0; i < n_cycles; ++i) {
+        res_host[i] = std::sqrt(r2[i]) / (h->bnorm > 0 ? h->bnorm : 1.0);
+        h->history.push_back(res_host[i]);
+      }
+    }
+    h->cycles += n_cycles;
+  });
+}
+
+int stmg_store(stmg_handle *h, double *x_dev) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(x_dev, STMG_EINVAL, "x is null");
+    Ops op{h, h->stream};
+    MeshData &md = op.mesh(0);
+    const int32_t E = md.S->topo.ne;
+    launch_fill(x_dev, (int64_t)E * op.W(0), 0.0, h->stream);
+    launch_internal_to_abi(op.ne(0), h->levels[0].N, h->q, E, md.d_map_abi, h->levels[0].x, x_dev, h->stream);
+    check_launch();
+  });
+}
+
+int stmg_solve(stmg_handle *h, const double *rhs_dev, const double *u0_dev, const double *x0_dev,
+               double *x_dev, stmg_report *rep) {
+  int status = STMG_OK;
+  int rc = guard([&] {
+    require_device(h);
+    const double t0 = wall_time();
+    double bn = 0.0;
+    int e = stmg_load(h, rhs_dev, u0_dev, x0_dev, &bn);
+    if (e != STMG_OK) fail(e, g_err);
+    h->history.clear();
+    h->rel_res = 0.0;
+    h->cycles = 0;
+    if (bn > 0.0) {
+      Ops op{h, h->stream};
+      LevelData &L = h->levels[0];
+      status = STMG_ENOTCONV;
+      for (int32_t c = 0; c < h->opt.max_cycles; ++c) {
+        op.vcycle(0, L.x, L.b);
+        op.residual_norm2(0, L.x, L.b, h->d_scalar);
+        check_launch();
+        double r2 = 0.0;
+        hip_check(hipMemcpyAsync(&r2, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        ++h->cycles;
+        h->rel_res = std::sqrt(r2) / bn;
+        h->history.push_back(h->rel_res);
+        if (!std::isfinite(h->rel_res)) {
+          status = STMG_ENUMERIC;
+          break;
+        }
+        if (h->rel_res <= h->opt.rtol) {
+          status = STMG_OK;
+          break;
+        }
+      }
+    }
+    e = stmg_store(h, x_dev);
+    if (e != STMG_OK) fail(e, g_err);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    h->solve_s = wall_time() - t0;
+    if (rep) {
+      rep->cycles = h->cycles;
+      rep->rel_res = h->rel_res;
+      rep->setup_s = h->setup_s;
+      rep->solve_s = h->solve_s;
+      rep->res_history = h->history.data();
+    }
+  });
+  if (rc != STMG_OK) return rc;
+  if (status == STMG_ENOTCONV) g_err = "max_cycles reached before rtol";
+  if (status == STMG_ENUMERIC) g_err = "non-finite residual";
+  return status;
+}
+
+int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev, const double *u0_dev,
+                  double *r_dev) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(x_dev && rhs_dev && r_dev, STMG_EINVAL, "null argument");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    MeshData &md = op.mesh(0);
+    const int32_t ne = op.ne(0), E = md.S->topo.ne;
+    double *tb = tmp_buf(h, 0), *tx = tmp_buf(h, 1), *tr = tmp_buf(h, 2);
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, rhs_dev, tb, h->stream);
+    if (u0_dev)
+      launch_fold_initial(ne, L.N, h->q, md.d_ptr, md.d_col, md.d_mval, md.d_map_abi, u0_dev, tb, h->stream);
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, x_dev, tx, h->stream);
+    op.residual(0, tx, tb, tr, RES_OUT_R, nullptr);
+    launch_fill(r_dev, (int64_t)E * op.W(0), 0.0, h->stream);
+    launch_internal_to_abi(ne, L.N, h->q, E, md.d_map_abi, tr, r_dev, h->stream);
+    check_launch();
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+  });
+}
+
+int stmg_level_apply(stmg_handle *h, int32_t level, int32_t op_code, const double *in_dev,
+                     const double *in2_dev, double *out_dev) {
+  return guard([&] {
+    require_device(h);
+    const int32_t nl = (int32_t)h->levels.size();
+    STMG_REQUIRE(level >= 0 && level < nl, STMG_EINVAL, "level out of range");
+    STMG_REQUIRE(in_dev && out_dev, STMG_EINVAL, "null argument");
+    Ops op{h, h->stream};
+    hipStream_t s = h->stream;
+    LevelData &L = h->levels[level];
+    MeshData &md = op.mesh(level);
+    const int32_t ne = op.ne(level), n = ne;
+    double *t0 = tmp_buf(h, 0), *t1 = tmp_buf(h, 1), *t2 = tmp_buf(h, 2);
+    launch_abi_to_internal(n, L.N, h->q, n, md.d_map_level, in_dev, t0, s);
+    auto need_in2 = [&] {
+      STMG_REQUIRE(in2_dev, STMG_EINVAL, "in2 is null");
+      launch_abi_to_internal(n, L.N, h->q, n, md.d_map_level, in2_dev, t1, s);
+    };
+    const size_t bytes = (size_t)ne * op.W(level) * sizeof(double);
+    int out_level = level;
+    switch (op_code) {
+      case STMG_OP_RESIDUAL:
+        need_in2();
+        op.residual(level, t0, t1, t2, RES_OUT_R, nullptr);
+        break;
+      case STMG_OP_SMOOTH_S:
+      case STMG_OP_NODAL_A:
+      case STMG_OP_SAS:
+      case STMG_OP_VCYCLE:
+        need_in2();
+        hip_check(hipMemcpyAsync(t2, t0, bytes, hipMemcpyDeviceToDevice, s), "copy");
+        if (op_code == STMG_OP_SMOOTH_S) op.smooth_S(level, t2, t1);
+        if (op_code == STMG_OP_NODAL_A) op.nodal_A(level, t2, t1);
+        if (op_code == STMG_OP_SAS) op.hybrid(level, t2, t1);
+        if (op_code == STMG_OP_VCYCLE) op.vcycle(level, t2, t1);
+        break;
+      case STMG_OP_SLAB_SOLVE:
+        launch_slab_rhs(ne, L.N, h->q, t0, L.w, s);
+        op.slab_solve(level, L.w);
+        launch_slab_update(ne, L.N, h->q, 1.0, L.w, t2, 1, s);
+        break;
+      case STMG_OP_RESTRICT:
+        STMG_REQUIRE(level + 1 < nl, STMG_EINVAL, "no coarser level");
+        op.restrict_to(level, t0, t2);
+        out_level = level + 1;
+        break;
+      case STMG_OP_PROLONG: {
+        STMG_REQUIRE(level >= 1, STMG_EINVAL, "no finer level");
+        launch_fill(t2, (int64_t)op.ne(level - 1) * op.W(level - 1), 0.0, s);
+        op.prolong_add(level - 1, t0, t2);
+        out_level = level - 1;
+        break;
+      }
+      default:
+        fail(STMG_EINVAL, "unknown op");
+    }
+    MeshData &mo = op.mesh(out_level);
+    const int32_t no = op.ne(out_level);
+    launch_internal_to_abi(no, h->levels[out_level].N, h->q, no, mo.d_map_level, t2, out_dev, s);
+    check_launch();
+    hip_check(hipStreamSynchronize(s), "sync");
+  });
+}
+
+int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32_t *n_rows, int32_t *n_cols,
+                       int64_t *nnz, int64_t *row_ptr, int32_t *col, double *val) {
+  return guard([&] {
+    STMG_REQUIRE(h && n_rows && n_cols && nnz, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
+    const SpaceLevel &S = h->space[h->levels[level].mesh];
+    const Csr *A = nullptr;
+    switch (which) {
+      case 0: A = &S.M; break;
+      case 1: A = &S.K; break;
+      case 2: A = &S.G; break;
+      case 3: A = &S.Kn; break;
+      case 4:
+        STMG_REQUIRE(h->levels[level].mesh > 0, STMG_EINVAL, "level uses the finest mesh: no P_e");
+        A = &S.Pe;
+        break;
+      default: fail(STMG_EINVAL, "unknown matrix");
+    }
+    *n_rows = A->n_rows;
+    *n_cols = A->n_cols;
+    *nnz = A->nnz();
+    if (row_ptr) std::copy(A->ptr.begin(), A->ptr.end(), row_ptr);
+    if (col) std::copy(A->col.begin(), A->col.end(), col);
+    if (val) std::copy(A->val.begin(), A->val.end(), val);
+  });
+}
+
+}  // extern "C"

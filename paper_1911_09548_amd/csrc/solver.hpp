@@ -1,0 +1,97 @@
+// Handle state of the stmg library: per-mesh and per-level host and device
+// data, and the V-cycle driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "factor.hpp"
+#include "kernels.hpp"
+#include "ordering.hpp"
+#include "space.hpp"
+
+namespace stmg {
+
+// Device allocation owned by a handle.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Device copy of one factor plus its solve plan.
+struct DevFactor {
+  bool is_complex = false;
+  FactorDev f{};
+  SolvePlan plan{};
+  int64_t u_rows = 0;            // sum of r_s
+  int64_t factor_bytes = 0;
+  // host-side plan storage (descriptors point into device arrays)
+  std::vector<int64_t> h_tgt_off;
+  std::vector<int32_t> h_fwd_begin, h_bwd_begin;
+  std::vector<SolvePlan::Launch> fwd, bwd_init, bwd;
+};
+
+struct MeshData {
+  int32_t index = 0;
+  SpaceLevel *S = nullptr;
+  NdTree nd;
+  Symbolic sym_e, sym_v;
+  Csr Mp, Kp;                    // M, K in factor (internal) numbering
+  // device
+  int64_t *d_ptr = nullptr;
+  int32_t *d_col = nullptr;
+  double *d_mval = nullptr, *d_kval = nullptr;
+  int32_t *d_head = nullptr, *d_tail = nullptr;  // G: edge -> vertex (internal), -1 boundary
+  int64_t *d_gt_ptr = nullptr;                   // G^T CSR over internal vertices
+  int32_t *d_gt_edge = nullptr;
+  int8_t *d_gt_sign = nullptr;
+  int32_t *d_map_level = nullptr;  // internal edge row -> ascending interior index
+  int32_t *d_map_abi = nullptr;    // internal edge row -> global edge id (mesh 0)
+  // transfer from the finer mesh (index-1) to this one, internal numberings
+  int64_t *d_pt_ptr = nullptr;     // P_e^T rows (this mesh's edges)
+  int32_t *d_pt_col = nullptr;
+  double *d_pt_val = nullptr;
+  int64_t *d_p_ptr = nullptr;      // P_e rows (finer mesh's edges)
+  int32_t *d_p_col = nullptr;
+  double *d_p_val = nullptr;
+  std::unique_ptr<HostFactor<double>> nodal_host;
+  DevFactor nodal;
+};
+
+struct LevelData {
+  int32_t mesh = 0, N = 0;
+  double tau = 0.0;
+  double lambda = 0.0;
+  std::unique_ptr<HostFactor<double>> slab_host_r;
+  std::unique_ptr<HostFactor<cplx>> slab_host_c;
+  DevFactor slab;
+  // device vectors (internal layout)
+  double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *u = nullptr;
+  double *g = nullptr, *zn = nullptr, *un = nullptr;
+};
+
+}  // namespace stmg
+
+struct stmg_handle {
+  stmg_options opt{};
+  hipStream_t stream = nullptr;
+  int32_t pt = 1, q = 2, Nt = 1;
+  double T = 1.0;
+  std::vector<stmg::SpaceLevel> space;
+  std::vector<stmg::MeshData> meshes;   // one per mesh used by some level
+  std::vector<int32_t> mesh_slot;       // problem mesh index -> meshes[] slot (-1 unused)
+  std::vector<stmg::LevelData> levels;
+  std::vector<stmg::DevBuf> bufs;
+  int64_t device_bytes = 0, factor_bytes = 0;
+  double *d_partial = nullptr, *d_scalar = nullptr;
+  int32_t n_partial = 0;
+  double *d_tmp[3] = {nullptr, nullptr, nullptr};
+  double bnorm = 0.0;
+  std::vector<double> history;
+  double setup_s = 0.0, solve_s = 0.0;
+  int32_t cycles = 0;
+  double rel_res = 0.0;
+};
