@@ -1,0 +1,160 @@
+"""Benchmark: space-time DOF-updates/s per V-cycle on one MI355X.
+
+Workload (default): unit cube, 32^3 hexes x 6 Kuhn tetrahedra, N_t = 256
+slabs, DG degree 1 in time, sigma in [1, 1e3] and nu in [1, 100] log-uniform
+on 8^3-hex blocks (seed 1), Gaussian right-hand side (seed 2), T = 1; FP64.
+A step is one solver iteration: a full V-cycle over all levels (SAS
+smoothing, nodal auxiliary correction, coarse-grid correction) followed by
+the fine-level residual norm. Inputs are resident in HBM when timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 32 --Nt 256 --pt 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(args):
+    """Time the oracle on a bounded sample (runs in a child process, 1 thread)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-sample",
+           "--sample-n", str(args.sample_n), "--sample-Nt", str(args.sample_Nt), "--pt", str(args.pt)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        log(r.stderr[-2000:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def oracle_sample(args):
+    """Child: oracle V-cycles on the same material recipe at a smaller mesh."""
+    import numpy as np
+    from paper_1911_09548_amd import inputs
+    from oracle.vcycle import SpaceTimeMultigrid
+    prob = inputs.config_block_random(n=args.sample_n, Nt=args.sample_Nt, pt=args.pt, seed=1,
+                                      block_hexes=max(1, args.sample_n // 4))
+    t0 = time.perf_counter()
+    ora = SpaceTimeMultigrid(prob, slab_solver="complex" if args.pt == 1 else "real")
+    setup = time.perf_counter() - t0
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal((prob.Nt, prob.pt + 1, ora.fine.n_e))
+    x = np.zeros_like(b)
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 2 or (time.perf_counter() - t_start < 10.0 and len(times) < 5):
+        t = time.perf_counter()
+        x = ora.vcycle(0, x, b)
+        np.linalg.norm(ora.levels[0].residual(x, b))
+        times.append(time.perf_counter() - t)
+    t_cycle = float(np.median(times))
+    dofs = ora.fine.n_e * prob.Nt * (prob.pt + 1)
+    print(json.dumps({"value": dofs / t_cycle, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+                      "sample": (f"oracle V-cycle + residual norm, median of {len(times)} cycles, "
+                                 f"{args.sample_n}^3 Kuhn mesh ({ora.fine.n_e} interior edges), "
+                                 f"N_t={prob.Nt}, p_t={prob.pt}, same block-random material recipe; "
+                                 f"setup {setup:.1f}s excluded; 1 thread (SuperLU, scipy)"),
+                      "s_per_cycle": t_cycle}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--Nt", type=int, default=256)
+    ap.add_argument("--pt", type=int, default=1)
+    ap.add_argument("--sample-n", type=int, default=8)
+    ap.add_argument("--sample-Nt", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
+    ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.oracle_sample:
+        oracle_sample(args)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the multi-GPU time sharding is a design "
+              "note, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1911_09548_amd import inputs, stmg
+
+    torch.cuda.set_device(0)
+    prob = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
+    log(f"[bench] setup n={args.n} Nt={args.Nt} pt={args.pt}")
+    t0 = time.perf_counter()
+    solver = stmg.Solver(prob, rtol=1e-8, max_cycles=100)
+    setup_s = time.perf_counter() - t0
+    levels = [solver.level_info(l) for l in range(solver.n_levels)]
+    log(f"[bench] setup {setup_s:.1f}s, levels " +
+        ", ".join(f"(mesh {li.mesh}, N {li.N})" for li in levels))
+    q = args.pt + 1
+    rng = np.random.default_rng(2)
+    rhs = torch.from_numpy(rng.standard_normal((args.Nt, q, solver.n_edges))).cuda()
+    n_e = levels[0].n_e
+    dofs = n_e * args.Nt * q
+
+    solver.load(rhs)
+    solver.cycles(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    res = solver.cycles(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] {ms:.2f} ms per V-cycle, residuals {res[-1]:.2e}")
+
+    extra = {}
+    if not args.no_solve:
+        t = time.perf_counter()
+        _, rep = solver.solve(rhs)
+        torch.cuda.synchronize()
+        extra = {"time_to_1e-8_s": time.perf_counter() - t, "cycles_to_1e-8": rep["cycles"],
+                 "final_rel_res": rep["rel_res"]}
+        log(f"[bench] solve to 1e-8: {extra['time_to_1e-8_s']:.2f}s in {rep['cycles']} cycles")
+
+    out = {
+        "metric": "space-time DOF-updates/s per V-cycle",
+        "value": dofs / (ms * 1e-3),
+        "unit": "DOF-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"eddy-current space-time V-cycle, {args.n}^3x6 Kuhn tets, N_t={args.Nt}, "
+                                f"p_t={args.pt}, block-random sigma in [1,1e3], nu in [1,100], Gaussian rhs"),
+                   "n_interior_edges": n_e, "space_time_dofs": dofs, "levels": len(levels),
+                   "setup_s": setup_s, **extra},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        cb = cpu_baseline(args)
+        if cb:
+            cb.pop("s_per_cycle", None)
+            out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <new>
 #include <numeric>
 
@@ -468,6 +469,12 @@ struct Ops {
 
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
+// Setup progress on stderr when STMG_VERBOSE is set (long factorisations).
+bool verbose() {
+  static const bool v = getenv("STMG_VERBOSE") && getenv("STMG_VERBOSE")[0] != '0';
+  return v;
+}
+
 void require_device(const stmg_handle *h) {
   STMG_REQUIRE(h, STMG_EINVAL, "null handle");
   STMG_REQUIRE(!h->opt.host_only, STMG_ENOSYS, "handle was built with host_only");
@@ -574,16 +581,25 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
     const int32_t used = h->levels.back().mesh + 1;
     h->mesh_slot.assign(h->space.size(), -1);
     h->meshes.resize(used);
+    if (verbose()) fprintf(stderr, "[stmg] assembly and hierarchy %.2fs\n", wall_time() - t0);
     for (int32_t j = 0; j < used; ++j) {
       h->mesh_slot[j] = j;
       h->meshes[j].index = j;
       h->meshes[j].S = &h->space[j];
       setup_mesh(h, h->meshes[j], device);
       if (device && j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
+      if (verbose())
+        fprintf(stderr, "[stmg] mesh %d: %d edges, slab nnz(L) %.3e, %d supernodes (%.2fs)\n", j,
+                h->meshes[j].S->topo.n_int_edges(), (double)h->meshes[j].sym_e.nnz_L, h->meshes[j].sym_e.ns,
+                wall_time() - t0);
     }
-    for (auto &L : h->levels) {
+    for (size_t l = 0; l < h->levels.size(); ++l) {
+      LevelData &L = h->levels[l];
       setup_level_factor(h, L, device);
       if (device) alloc_level_vectors(h, L);
+      if (verbose())
+        fprintf(stderr, "[stmg] level %zu (mesh %d, N %d, tau %.4g, lambda %.3g) factored (%.2fs)\n", l, L.mesh,
+                L.N, L.tau, L.lambda, wall_time() - t0);
     }
     if (device) {
       const LevelData &L = h->levels[0];
