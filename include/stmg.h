@@ -207,6 +207,18 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
                        int32_t *n_cols, int64_t *nnz, int64_t *row_ptr, int32_t *col,
                        double *val);
 
+/* Host copy of a level's factor (host_only handles): which = 0 slab block
+ * (complex for pt = 1: values interleaved re, im), 1 nodal matrix K_n.
+ * Layout as used by the solves: DOF new = perm^{-1}(old) in nested-dissection
+ * order; supernode s owns columns [col0[s], col0[s+1]), below-diagonal rows
+ * rows[rptr[s] .. rptr[s+1]) (new numbering) and the column-major panel
+ * P_s = [inv(L_ss); -L_{R,s} inv(L_ss)] at panel + panel_off[s] (scalars).
+ * Pass NULL arrays to query sizes. Returns STMG_ENOSYS on device handles
+ * (their factors live only in HBM). */
+int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32_t *n, int32_t *ns,
+                       int64_t *n_rows_total, int64_t *n_panel, int32_t *is_complex, int32_t *perm,
+                       int32_t *col0, int64_t *rptr, int32_t *rows, int64_t *panel_off, double *panel);
+
 #ifdef __cplusplus
 }
 #endif

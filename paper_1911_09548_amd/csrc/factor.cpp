@@ -99,31 +99,44 @@ void partial_factor(int64_t m, int64_t w, T *F) {
   }
 }
 
-// Inverse of the lower-triangular kb x kb block L (ld = ldl) into D (ld = NB).
+// Replace the panel [L11; L21] (m x w, ld = m) by [inv(L11); -L21 inv(L11)].
+// Column c of inv(L11) is L11^{-1} e_c (column-oriented forward
+// substitution); then W21 = -L21 inv(L11) column by column:
+// W21[:, j] = -sum_{k >= j} L21[:, k] inv(L11)[k, j].
 template <typename T>
-void tri_inverse(int64_t kb, const T *L, int64_t ldl, T *D) {
-  for (int64_t c = 0; c < kb; ++c) {
-    // solve L x = e_c, x[i] = 0 for i < c
-    T *x = D + c * NB;
-    for (int64_t i = 0; i < NB; ++i) x[i] = zero(T{});
-    x[c] = recip(L[c + c * ldl]);
-    for (int64_t i = c + 1; i < kb; ++i) {
-      T s = zero(T{});
-      for (int64_t k = c; k < i; ++k) add_to(s, mul(L[i + k * ldl], x[k]));
-      x[i] = mul(neg(s), recip(L[i + i * ldl]));
+void invert_panel(int64_t m, int64_t w, T *P) {
+  std::vector<T> Li(w * w, zero(T{}));
+#pragma omp parallel for schedule(dynamic, 4) if (w > 96)
+  for (int64_t c = 0; c < w; ++c) {
+    T *x = Li.data() + c * w;
+    x[c] = recip(P[c + c * m]);
+    for (int64_t j = c; j < w; ++j) {
+      if (j > c) x[j] = mul(x[j], recip(P[j + j * m]));
+      // x[j+1:w] -= x_j * L[j+1:w, j]
+      const T xj = x[j];
+      axpy_sub(w - j - 1, P + j * m + j + 1, xj, x + j + 1);
     }
+  }
+  const int64_t r = m - w;
+  std::vector<T> W(r * w, zero(T{}));
+#pragma omp parallel for schedule(dynamic, 4) if (r * w > 4096)
+  for (int64_t j = 0; j < w; ++j) {
+    T *y = W.data() + j * r;
+    for (int64_t k = j; k < w; ++k) axpy_sub(r, P + k * m + w, Li[k + j * w], y);  // y -= L21[:,k] Li[k,j]
+  }
+  for (int64_t j = 0; j < w; ++j) {
+    std::copy(Li.begin() + j * w, Li.begin() + (j + 1) * w, P + j * m);
+    std::copy(W.begin() + j * r, W.begin() + (j + 1) * r, P + j * m + w);
   }
 }
 
 }  // namespace
 
-void factor_layout(const Symbolic &S, std::vector<int64_t> &panel_off, std::vector<int64_t> &dinv_off) {
+void factor_layout(const Symbolic &S, std::vector<int64_t> &panel_off) {
   panel_off.assign(S.ns + 1, 0);
-  dinv_off.assign(S.ns + 1, 0);
   for (int32_t s = 0; s < S.ns; ++s) {
     int64_t w = S.width(s), m = w + S.nrows(s);
     panel_off[s + 1] = panel_off[s] + m * w;
-    dinv_off[s + 1] = dinv_off[s] + n_diag_blocks((int32_t)w) * NB * NB;
   }
 }
 
@@ -131,9 +144,8 @@ template <typename T>
 void factor_host(const Symbolic &S, const Csr &A, const std::vector<T> &vals, HostFactor<T> &Fo) {
   STMG_REQUIRE((int64_t)vals.size() == A.nnz(), STMG_EINVAL, "factor: value count mismatch");
   Fo.sym = &S;
-  factor_layout(S, Fo.panel_off, Fo.dinv_off);
+  factor_layout(S, Fo.panel_off);
   Fo.panel.assign(Fo.panel_off[S.ns], zero(T{}));
-  Fo.dinv.assign(Fo.dinv_off[S.ns], zero(T{}));
   std::vector<std::vector<T>> U(S.ns);   // update matrices waiting for their parent
   std::vector<std::vector<int32_t>> kids(S.ns);
   for (int32_t s = 0; s < S.ns; ++s)
@@ -172,11 +184,7 @@ void factor_host(const Symbolic &S, const Csr &A, const std::vector<T> &vals, Ho
       for (int64_t b = 0; b < r; ++b)
         std::copy(F.begin() + (w + b) * m + w, F.begin() + (w + b) * m + m, U[s].begin() + b * r);
     }
-    T *D = Fo.dinv.data() + Fo.dinv_off[s];
-    for (int64_t k = 0; k < n_diag_blocks((int32_t)w); ++k) {
-      int64_t k0 = k * NB, kb = std::min<int64_t>(NB, w - k0);
-      tri_inverse<T>(kb, P + k0 * m + k0, m, D + k * NB * NB);
-    }
+    invert_panel<T>(m, w, P);
   }
 }
 

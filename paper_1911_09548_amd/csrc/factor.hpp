@@ -7,11 +7,12 @@
 // and imaginary part sqrt(2) M are SPD, so every leading principal minor is
 // nonzero and the factorisation exists.
 //
-// Storage per supernode s (w columns, r below-diagonal rows, m = w + r): a
-// dense column-major panel of m rows x w columns (ld = m) whose top w x w
-// block holds L_ss (lower triangle) and whose last r rows hold L_{R_s,s};
-// and the inverses of its NB x NB diagonal sub-blocks (column-major, ld = NB,
-// zero padded), used by the triangular solves.
+// Storage per supernode s (w columns, r below-diagonal rows, m = w + r): the
+// supernode's elimination operator in inverted form (selective inversion),
+//   P_s = [ inv(L_ss) ; -L_{R_s,s} inv(L_ss) ]     (m x w, column-major, ld = m),
+// zero above the diagonal of the top block. The forward solve of the
+// supernode is then one product P_s F (its columns' values and the update
+// to its ancestors' rows), and the backward solve one product P_s^T [y; x_R].
 #pragma once
 
 #include <vector>
@@ -21,18 +22,14 @@
 
 namespace stmg {
 
-constexpr int NB = 64;  // diagonal sub-block size of the solves
+constexpr int NB = 64;  // column block of the dense partial factorisation
 
 template <typename T>
 struct HostFactor {
   const Symbolic *sym = nullptr;
-  std::vector<T> panel;
+  std::vector<T> panel;            // P_s of every supernode
   std::vector<int64_t> panel_off;  // [ns+1]
-  std::vector<T> dinv;
-  std::vector<int64_t> dinv_off;   // [ns+1]
 };
-
-inline int64_t n_diag_blocks(int32_t w) { return (w + NB - 1) / NB; }
 
 // Factor the matrix whose entries on the pattern of A (ascending interior
 // numbering) are vals[k] (T per nonzero). Throws STMG_ENUMERIC on a zero or
@@ -40,7 +37,7 @@ inline int64_t n_diag_blocks(int32_t w) { return (w + NB - 1) / NB; }
 template <typename T>
 void factor_host(const Symbolic &S, const Csr &A, const std::vector<T> &vals, HostFactor<T> &F);
 
-// Offsets of panels and diagonal inverses for a symbolic structure.
-void factor_layout(const Symbolic &S, std::vector<int64_t> &panel_off, std::vector<int64_t> &dinv_off);
+// Offsets of the panels for a symbolic structure.
+void factor_layout(const Symbolic &S, std::vector<int64_t> &panel_off);
 
 }  // namespace stmg

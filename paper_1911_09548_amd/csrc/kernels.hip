@@ -535,30 +535,40 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 }
 
 // ------------------------------------------------------ triangular solves
+// Each supernode s stores P_s = [inv(L_ss); -L_{R,s} inv(L_ss)] (m x w,
+// column-major). Per tree height, one batched launch does for every
+// supernode of that height
+//   forward:  [Z[C_s]; U_s] (+)= P_s X[C_s]          (U_s += : update rows)
+//   backward: X[C_s] = P_s^T [Z[C_s]; X[R_s]]
+// as a GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64; complex products as four
+// real MFMAs). Work items are (supernode, 64-row tile, column tile), the
+// column tile varying fastest so the tiles sharing a block of P_s run
+// together and read it through L2 once.
 namespace {
 
-__device__ inline double sc_zero(double) { return 0.0; }
-__device__ inline cd sc_zero(cd) { return {0.0, 0.0}; }
-__device__ inline void sc_fma(double &acc, double a, double b) { acc += a * b; }
-__device__ inline void sc_fma(cd &acc, cd a, cd b) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
-}
-__device__ inline void sc_sub(double &y, double a) { y -= a; }
-__device__ inline void sc_sub(cd &y, cd a) {
-  y.re -= a.re;
-  y.im -= a.im;
-}
-__device__ inline void sc_add(double &y, double a) { y += a; }
-__device__ inline void sc_add(cd &y, cd a) {
-  y.re += a.re;
-  y.im += a.im;
-}
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename T>
-struct Tile {
-  static constexpr int TC = sizeof(T) == 8 ? 32 : 16;  // right-hand-side columns per tile
+struct Scalar;
+template <>
+struct Scalar<double> {
+  static constexpr bool cpx = false;
 };
+template <>
+struct Scalar<cd> {
+  static constexpr bool cpx = true;
+};
+
+__device__ inline void split(double v, double &re, double &im) {
+  re = v;
+  im = 0.0;
+}
+__device__ inline void split(cd v, double &re, double &im) {
+  re = v.re;
+  im = v.im;
+}
+__device__ inline void make(double re, double, double &out) { out = re; }
+__device__ inline void make(double re, double im, cd &out) { out = {re, im}; }
 
 __device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
   int lo = 0, hi = n - 1;
@@ -582,212 +592,168 @@ __global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int6
   const AsmTarget t = tgt[blockIdx.x];
   const int64_t s1 = tgt[blockIdx.x + 1].src_begin;
   for (int c = threadIdx.x; c < nc; c += 64) {
-    T acc = sc_zero(T{});
-    for (int64_t k = t.src_begin; k < s1; ++k) sc_add(acc, U[src[k] * nc + c]);
-    if (t.dst >= 0)
-      sc_add(X[t.dst * nc + c], acc);
-    else
-      U[(-1 - t.dst) * nc + c] = acc;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t k = t.src_begin; k < s1; ++k) {
+      double r, i;
+      split(U[src[k] * nc + c], r, i);
+      ar += r;
+      ai += i;
+    }
+    if (t.dst >= 0) {
+      double r, i;
+      split(X[t.dst * nc + c], r, i);
+      make(r + ar, i + ai, X[t.dst * nc + c]);
+    } else {
+      make(ar, ai, U[(-1 - t.dst) * nc + c]);
+    }
   }
 }
 
-// Forward step k of a batch of supernodes: Y_k = inv(L_kk) F_k (written to Z
-// by the first row tile), then F[rows below block k] -= L[rows, k-block] Y_k,
-// rows below being the supernode's remaining columns (rows of X) and its
-// structure R_s (rows of its U block).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_fwd_step(FactorDev f, int32_t k, const SolveTask *tasks,
-                                                    int32_t n_tasks, int32_t nc, T *X, T *Z, T *U) {
-  constexpr int TC = Tile<T>::TC;
-  __shared__ T Fk[NB][TC];
-  __shared__ T Y[NB][TC];
-  const int ti = find_task(tasks, n_tasks, blockIdx.x);
-  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
+template <typename T, int BN, int DIR>
+__global__ __launch_bounds__(BLOCK) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+                                                   int32_t nc, int32_t ctiles, T *X, T *Z, T *U) {
+  constexpr bool CPX = Scalar<T>::cpx;
+  constexpr int BM = 64, KC = 16;
+  constexpr int WN = BN >= 32 ? 2 : 1, WM = 4 / WN;
+  constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+  __shared__ double As[CPX ? 2 : 1][KC][BM];
+  __shared__ double Bs[CPX ? 2 : 1][KC][BN];
+  const int rowtile = blockIdx.x / ctiles, ct = blockIdx.x % ctiles;
+  const int ti = find_task(tasks, n_tasks, rowtile);
+  const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
-  const int k0 = k * NB, kb = min(NB, w - k0);
-  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
-  const T *D = reinterpret_cast<const T *>(f.dinv) + f.dinv_off[s] + (int64_t)k * NB * NB;
-  const int cb = blockIdx.y * TC;
-  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-    const int t = idx / TC, j = idx % TC;
-    Fk[t][j] = (t < kb && cb + j < nc) ? X[(int64_t)(c0 + k0 + t) * nc + cb + j] : sc_zero(T{});
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-    const int t = idx / TC, j = idx % TC;
-    T acc = sc_zero(T{});
-    if (t < kb)
-      for (int u = 0; u <= t; ++u) sc_fma(acc, D[t + u * NB], Fk[u][j]);
-    Y[t][j] = acc;
-  }
-  __syncthreads();
-  if (rt == 0)
-    for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-      const int t = idx / TC, j = idx % TC;
-      if (t < kb && cb + j < nc) Z[(int64_t)(c0 + k0 + t) * nc + cb + j] = Y[t][j];
-    }
-  constexpr int JG = TC / 4;
-  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  const int rho = k0 + kb + rt * 64 + i;
-  if (rho < m) {
-    T acc[JG];
-#pragma unroll
-    for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
-    for (int t = 0; t < kb; ++t) {
-      const T a = P[(int64_t)(k0 + t) * m + rho];
-#pragma unroll
-      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Y[t][jg * JG + j]);
-    }
-    T *dst = rho < w ? X + (int64_t)(c0 + rho) * nc : U + (f.uoff[s] + (rho - w)) * nc;
-#pragma unroll
-    for (int j = 0; j < JG; ++j) {
-      const int c = cb + jg * JG + j;
-      if (c < nc) sc_sub(dst[c], acc[j]);
-    }
-  }
-}
-
-// Backward initialisation: Z[C_s] -= L_{R_s,s}^T X[R_s] (X holds final
-// values of the ancestors' rows).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bwd_init(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
-                                                    int32_t nc, const T *X, T *Z) {
-  constexpr int TC = Tile<T>::TC;
-  constexpr int KC = 32;  // rows of R_s per chunk
-  __shared__ T Lt[KC][65];
-  __shared__ T Xc[KC][TC];
-  const int ti = find_task(tasks, n_tasks, blockIdx.x);
-  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
-  const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s], r = m - w;
   const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
   const int32_t *R = f.rows + f.rptr[s];
-  const int cb = blockIdx.y * TC;
-  constexpr int JG = TC / 4;
-  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  const int col = rt * 64 + i;  // column of the supernode (row of Z)
-  T acc[JG];
+  const int i0 = rt * BM, j0 = ct * BN;
+  const int rows = DIR == 0 ? m : w;
+  const int kbeg = DIR == 0 ? 0 : i0;
+  const int kend = DIR == 0 ? (i0 < w ? min(w, i0 + BM) : w) : m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave / WN) * (BM / WM), wc = (wave % WN) * (BN / WN);
+  v4d acc[CPX ? 2 : 1][MI][NI];
 #pragma unroll
-  for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
-  for (int j0 = 0; j0 < r; j0 += KC) {
-    const int kc = min(KC, r - j0);
+  for (int c = 0; c < (CPX ? 2 : 1); ++c)
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+      for (int b = 0; b < NI; ++b) acc[c][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    // A tile (BM x KC) of P (forward) or P^T (backward)
+    for (int e = threadIdx.x; e < BM * KC; e += BLOCK) {
+      int i, k;
+      if (DIR == 0) {
+        i = e % BM;
+        k = e / BM;
+      } else {
+        k = e % KC;
+        i = e / KC;
+      }
+      const int gi = i0 + i, gk = k0 + k;
+      double re = 0.0, im = 0.0;
+      if (gi < rows && gk < kend) split(DIR == 0 ? P[gi + (int64_t)gk * m] : P[gk + (int64_t)gi * m], re, im);
+      As[0][k][i] = re;
+      if (CPX) As[CPX ? 1 : 0][k][i] = im;
+    }
+    // B tile (KC x BN): rows of the right-hand sides
+    for (int e = threadIdx.x; e < KC * BN; e += BLOCK) {
+      const int j = e % BN, k = e / BN;
+      const int gk = k0 + k, gj = j0 + j;
+      double re = 0.0, im = 0.0;
+      if (gk < kend && gj < nc) {
+        const T *row;
+        if (DIR == 0)
+          row = X + (int64_t)(c0 + gk) * nc;
+        else
+          row = gk < w ? Z + (int64_t)(c0 + gk) * nc : X + (int64_t)R[gk - w] * nc;
+        split(row[gj], re, im);
+      }
+      Bs[0][k][j] = re;
+      if (CPX) Bs[CPX ? 1 : 0][k][j] = im;
+    }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < KC * 64; idx += BLOCK) {
-      const int jj = idx % KC, ii = idx / KC;  // jj fastest: contiguous in the panel
-      const int cc = rt * 64 + ii;
-      Lt[jj][ii] = (jj < kc && cc < w) ? P[(int64_t)cc * m + w + j0 + jj] : sc_zero(T{});
-    }
-    for (int idx = threadIdx.x; idx < KC * TC; idx += BLOCK) {
-      const int jj = idx / TC, c = idx % TC;
-      Xc[jj][c] = (jj < kc && cb + c < nc) ? X[(int64_t)R[j0 + jj] * nc + cb + c] : sc_zero(T{});
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + lane / 16;
+      double ar[MI], ai[MI], br[NI], bi[NI];
+#pragma unroll
+      for (int a = 0; a < MI; ++a) {
+        ar[a] = As[0][kr][wr + a * 16 + (lane & 15)];
+        if (CPX) ai[a] = As[CPX ? 1 : 0][kr][wr + a * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int b = 0; b < NI; ++b) {
+        br[b] = Bs[0][kr][wc + b * 16 + (lane & 15)];
+        if (CPX) bi[b] = Bs[CPX ? 1 : 0][kr][wc + b * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) {
+          acc[0][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc[0][a][b], 0, 0, 0);
+          if constexpr (CPX) {
+            acc[0][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], acc[0][a][b], 0, 0, 0);
+            acc[1][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc[1][a][b], 0, 0, 0);
+            acc[1][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc[1][a][b], 0, 0, 0);
+          }
+        }
     }
     __syncthreads();
-    for (int jj = 0; jj < kc; ++jj) {
-      const T a = Lt[jj][i];
-#pragma unroll
-      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Xc[jj][jg * JG + j]);
-    }
   }
-  if (col < w) {
+  // epilogue: lane holds rows 4r + lane/16 of column lane%16 of each block
 #pragma unroll
-    for (int j = 0; j < JG; ++j) {
-      const int c = cb + jg * JG + j;
-      if (c < nc) sc_sub(Z[(int64_t)(c0 + col) * nc + c], acc[j]);
-    }
-  }
+  for (int a = 0; a < MI; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wr + a * 16 + 4 * r + lane / 16;
+        const int col = j0 + wc + b * 16 + (lane & 15);
+        if (row >= rows || col >= nc) continue;
+        const double vr = acc[0][a][b][r], vi = CPX ? acc[CPX ? 1 : 0][a][b][r] : 0.0;
+        if (DIR == 0) {
+          if (row < w) {
+            make(vr, vi, Z[(int64_t)(c0 + row) * nc + col]);
+          } else {
+            T *u = U + (f.uoff[s] + (row - w)) * nc + col;
+            double ur, ui;
+            split(*u, ur, ui);
+            make(ur + vr, ui + vi, *u);
+          }
+        } else {
+          make(vr, vi, X[(int64_t)(c0 + row) * nc + col]);
+        }
+      }
 }
 
-// Backward step k: z_k = inv(L_kk)^T F_k (written to X by the first row
-// tile), then F[rows < k0] -= L[k-block, rows]^T z_k (rows of Z).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bwd_step(FactorDev f, int32_t k, const SolveTask *tasks,
-                                                    int32_t n_tasks, int32_t nc, T *X, T *Z) {
-  constexpr int TC = Tile<T>::TC;
-  __shared__ T Fk[NB][TC];
-  __shared__ T Yz[NB][TC];
-  __shared__ T Lb[NB][65];
-  const int ti = find_task(tasks, n_tasks, blockIdx.x);
-  const int s = tasks[ti].s, rt = blockIdx.x - tasks[ti].tile_begin;
-  const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
-  const int k0 = k * NB, kb = min(NB, w - k0);
-  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
-  const T *D = reinterpret_cast<const T *>(f.dinv) + f.dinv_off[s] + (int64_t)k * NB * NB;
-  const int cb = blockIdx.y * TC;
-  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-    const int t = idx / TC, j = idx % TC;
-    Fk[t][j] = (t < kb && cb + j < nc) ? Z[(int64_t)(c0 + k0 + t) * nc + cb + j] : sc_zero(T{});
-  }
-  // L block rows k0..k0+kb, columns rt*64 .. rt*64+63 (< k0): Lb[t][jj]
-  for (int idx = threadIdx.x; idx < NB * 64; idx += BLOCK) {
-    const int t = idx % NB, jj = idx / NB;  // t fastest: contiguous in the panel
-    const int cc = rt * 64 + jj;
-    Lb[t][jj] = (t < kb && cc < k0) ? P[(int64_t)cc * m + k0 + t] : sc_zero(T{});
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-    const int t = idx / TC, j = idx % TC;
-    T acc = sc_zero(T{});
-    if (t < kb)
-      for (int u = t; u < kb; ++u) sc_fma(acc, D[u + t * NB], Fk[u][j]);
-    Yz[t][j] = acc;
-  }
-  __syncthreads();
-  if (rt == 0)
-    for (int idx = threadIdx.x; idx < NB * TC; idx += BLOCK) {
-      const int t = idx / TC, j = idx % TC;
-      if (t < kb && cb + j < nc) X[(int64_t)(c0 + k0 + t) * nc + cb + j] = Yz[t][j];
-    }
-  constexpr int JG = TC / 4;
-  const int i = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  const int row = rt * 64 + i;
-  if (row < k0) {
-    T acc[JG];
-#pragma unroll
-    for (int j = 0; j < JG; ++j) acc[j] = sc_zero(T{});
-    for (int t = 0; t < kb; ++t) {
-      const T a = Lb[t][i];
-#pragma unroll
-      for (int j = 0; j < JG; ++j) sc_fma(acc[j], a, Yz[t][jg * JG + j]);
-    }
-#pragma unroll
-    for (int j = 0; j < JG; ++j) {
-      const int c = cb + jg * JG + j;
-      if (c < nc) sc_sub(Z[(int64_t)(c0 + row) * nc + c], acc[j]);
-    }
+template <typename T, int DIR>
+static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t nc, T *X, T *Z, T *U,
+                           hipStream_t s) {
+  if (L.n_tasks == 0) return;
+  if (nc > 16) {
+    const int ct = (nc + 63) / 64;
+    hipLaunchKernelGGL((k_sn_gemm<T, 64, DIR>), dim3((unsigned)(L.n_tiles * ct)), dim3(BLOCK), 0, s, f, L.tasks,
+                       L.n_tasks, nc, ct, X, Z, U);
+  } else {
+    hipLaunchKernelGGL((k_sn_gemm<T, 16, DIR>), dim3((unsigned)L.n_tiles), dim3(BLOCK), 0, s, f, L.tasks,
+                       L.n_tasks, nc, 1, X, Z, U);
   }
 }
 
 template <typename T>
 void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, T *U, hipStream_t s) {
-  constexpr int TC = Tile<T>::TC;
-  const unsigned ctiles = (unsigned)((nc + TC - 1) / TC);
   for (int h = 0; h < p.n_heights; ++h) {
     const int64_t t0 = p.h_tgt_off[h], t1 = p.h_tgt_off[h + 1];
     if (t1 > t0)
       hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)(t1 - t0)), dim3(64), 0, s, p.tgt + t0, p.src, nc,
                          X, U);
-    for (int l = p.h_fwd_begin[h]; l < p.h_fwd_begin[h + 1]; ++l) {
-      const SolvePlan::Launch &L = p.fwd[l];
-      hipLaunchKernelGGL((k_fwd_step<T>), dim3((unsigned)L.n_tiles, ctiles), dim3(BLOCK), 0, s, f, L.k,
-                         L.tasks, L.n_tasks, nc, X, Z, U);
-    }
+    launch_sn_gemm<T, 0>(f, p.fwd[h], nc, X, Z, U, s);
   }
 }
 
 template <typename T>
 void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s) {
-  constexpr int TC = Tile<T>::TC;
-  const unsigned ctiles = (unsigned)((nc + TC - 1) / TC);
-  for (int h = p.n_heights - 1; h >= 0; --h) {
-    const SolvePlan::Launch &I = p.bwd_init[h];
-    if (I.n_tasks > 0)
-      hipLaunchKernelGGL((k_bwd_init<T>), dim3((unsigned)I.n_tiles, ctiles), dim3(BLOCK), 0, s, f, I.tasks,
-                         I.n_tasks, nc, X, Z);
-    for (int l = p.h_bwd_begin[h]; l < p.h_bwd_begin[h + 1]; ++l) {
-      const SolvePlan::Launch &L = p.bwd[l];
-      hipLaunchKernelGGL((k_bwd_step<T>), dim3((unsigned)L.n_tiles, ctiles), dim3(BLOCK), 0, s, f, L.k,
-                         L.tasks, L.n_tasks, nc, X, Z);
-    }
-  }
+  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], nc, X, Z, nullptr, s);
 }
 
 template void solve_forward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,

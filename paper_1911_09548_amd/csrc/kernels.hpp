@@ -87,9 +87,9 @@ struct FactorDev {
   const int32_t *m;        // [ns] w + r
   const int64_t *rptr;     // [ns+1]
   const int32_t *rows;
-  const int64_t *panel_off, *dinv_off;
+  const int64_t *panel_off;
   const int64_t *uoff;     // [ns] first U row of each supernode
-  const void *panel, *dinv;
+  const void *panel;       // P_s = [inv(L_ss); -L_{R,s} inv(L_ss)], column-major
 };
 struct SolveTask {
   int32_t s;
@@ -107,18 +107,13 @@ struct SolvePlan {
   const int64_t *h_tgt_off;      // host [H+1]
   const AsmTarget *tgt;          // device [n_tgt + 1] (sentinel)
   const int64_t *src;            // device U rows
-  // step launches: host descriptors, device task arrays
+  // one GEMM launch per height and direction: host descriptors, device tasks
   struct Launch {
-    int32_t k;                   // diagonal block index
-    int32_t n_tasks, n_tiles;
+    int32_t n_tasks, n_tiles;    // supernodes, 64-row tiles
     const SolveTask *tasks;      // device
   };
-  // forward: per height, steps k = 0..; backward init per height; backward steps
-  const int32_t *h_fwd_begin;    // host [H+1] into fwd
-  const Launch *fwd;             // host array
-  const Launch *bwd_init;        // host [H] (k unused)
-  const int32_t *h_bwd_begin;    // host [H+1] into bwd (k descending within a height)
-  const Launch *bwd;             // host array
+  const Launch *fwd;             // host [H]: row tiles over m = w + r
+  const Launch *bwd;             // host [H]: row tiles over w
 };
 
 template <typename T>

@@ -101,72 +101,40 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   }
   D.h_tgt_off[H] = (int64_t)tgt.size();
   tgt.push_back({0, (int64_t)src.size()});  // sentinel
-  // step launches
+  // one forward and one backward GEMM launch per height
   std::vector<SolveTask> tasks;
   struct Pending {
-    int32_t k;
     size_t off, n;
     int32_t tiles;
   };
-  std::vector<Pending> pf, pbi, pb;
-  D.h_fwd_begin.assign(H + 1, 0);
-  D.h_bwd_begin.assign(H + 1, 0);
-  auto nblk = [&](int32_t s) { return (int32_t)n_diag_blocks(S.width(s)); };
+  std::vector<Pending> pf(H), pb(H);
   for (int32_t hh = 0; hh < H; ++hh) {
-    int32_t kmax = 0;
-    for (int32_t s : by_h[hh]) kmax = std::max(kmax, nblk(s));
-    D.h_fwd_begin[hh] = (int32_t)pf.size();
-    for (int32_t k = 0; k < kmax; ++k) {
-      Pending p{k, tasks.size(), 0, 0};
-      for (int32_t s : by_h[hh]) {
-        if (nblk(s) <= k) continue;
-        const int32_t w = S.width(s), m = w + S.nrows(s);
-        const int32_t k0 = k * NB, kb = std::min(NB, w - k0);
-        const int32_t below = m - k0 - kb;
-        tasks.push_back({s, p.tiles});
-        p.tiles += std::max(1, (below + 63) / 64);
-      }
-      p.n = tasks.size() - p.off;
-      pf.push_back(p);
+    Pending p{tasks.size(), 0, 0};
+    for (int32_t s : by_h[hh]) {
+      tasks.push_back({s, p.tiles});
+      p.tiles += (S.width(s) + S.nrows(s) + 63) / 64;
     }
-    // backward init
-    {
-      Pending p{0, tasks.size(), 0, 0};
-      for (int32_t s : by_h[hh]) {
-        if (S.nrows(s) == 0) continue;
-        tasks.push_back({s, p.tiles});
-        p.tiles += (S.width(s) + 63) / 64;
-      }
-      p.n = tasks.size() - p.off;
-      pbi.push_back(p);
+    p.n = tasks.size() - p.off;
+    pf[hh] = p;
+    Pending q{tasks.size(), 0, 0};
+    for (int32_t s : by_h[hh]) {
+      tasks.push_back({s, q.tiles});
+      q.tiles += (S.width(s) + 63) / 64;
     }
-    D.h_bwd_begin[hh] = (int32_t)pb.size();
-    for (int32_t k = kmax - 1; k >= 0; --k) {
-      Pending p{k, tasks.size(), 0, 0};
-      for (int32_t s : by_h[hh]) {
-        if (nblk(s) <= k) continue;
-        tasks.push_back({s, p.tiles});
-        p.tiles += std::max(1, (k * NB + 63) / 64);
-      }
-      p.n = tasks.size() - p.off;
-      pb.push_back(p);
-    }
+    q.n = tasks.size() - q.off;
+    pb[hh] = q;
   }
-  D.h_fwd_begin[H] = (int32_t)pf.size();
-  D.h_bwd_begin[H] = (int32_t)pb.size();
   SolveTask *dt = dev_upload(h, tasks);
   AsmTarget *dtg = dev_upload(h, tgt);
   int64_t *dsrc = dev_upload(h, src);
   auto mk = [&](const Pending &p) {
     SolvePlan::Launch L;
-    L.k = p.k;
     L.n_tasks = (int32_t)p.n;
     L.n_tiles = p.tiles;
     L.tasks = dt + p.off;
     return L;
   };
   for (auto &p : pf) D.fwd.push_back(mk(p));
-  for (auto &p : pbi) D.bwd_init.push_back(mk(p));
   for (auto &p : pb) D.bwd.push_back(mk(p));
   // factor metadata
   std::vector<int32_t> m(ns);
@@ -182,10 +150,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.plan.h_tgt_off = D.h_tgt_off.data();
   D.plan.tgt = dtg;
   D.plan.src = dsrc;
-  D.plan.h_fwd_begin = D.h_fwd_begin.data();
   D.plan.fwd = D.fwd.data();
-  D.plan.bwd_init = D.bwd_init.data();
-  D.plan.h_bwd_begin = D.h_bwd_begin.data();
   D.plan.bwd = D.bwd.data();
 }
 
@@ -193,10 +158,8 @@ template <typename T, typename TH>
 void upload_factor(stmg_handle *h, const HostFactor<TH> &F, DevFactor &D) {
   static_assert(sizeof(T) == sizeof(TH), "scalar size mismatch");
   D.f.panel = dev_upload(h, reinterpret_cast<const T *>(F.panel.data()), F.panel.size());
-  D.f.dinv = dev_upload(h, reinterpret_cast<const T *>(F.dinv.data()), F.dinv.size());
   D.f.panel_off = dev_upload(h, F.panel_off);
-  D.f.dinv_off = dev_upload(h, F.dinv_off);
-  D.factor_bytes = (int64_t)((F.panel.size() + F.dinv.size()) * sizeof(T));
+  D.factor_bytes = (int64_t)(F.panel.size() * sizeof(T));
   h->factor_bytes += D.factor_bytes;
 }
 
@@ -891,6 +854,56 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
     if (row_ptr) std::copy(A->ptr.begin(), A->ptr.end(), row_ptr);
     if (col) std::copy(A->col.begin(), A->col.end(), col);
     if (val) std::copy(A->val.begin(), A->val.end(), val);
+  });
+}
+
+int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32_t *n, int32_t *ns,
+                       int64_t *n_rows_total, int64_t *n_panel, int32_t *is_complex, int32_t *perm,
+                       int32_t *col0, int64_t *rptr, int32_t *rows, int64_t *panel_off, double *panel) {
+  return guard([&] {
+    STMG_REQUIRE(h && n && ns && n_rows_total && n_panel && is_complex, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
+    STMG_REQUIRE(h->opt.host_only, STMG_ENOSYS, "factors of device handles live only in HBM");
+    const LevelData &L = h->levels[level];
+    const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    const Symbolic *S = nullptr;
+    const std::vector<int64_t> *off = nullptr;
+    const double *vals = nullptr;
+    size_t nvals = 0;
+    int cpx = 0;
+    if (which == 0) {
+      S = &md.sym_e;
+      if (L.slab_host_c) {
+        off = &L.slab_host_c->panel_off;
+        vals = reinterpret_cast<const double *>(L.slab_host_c->panel.data());
+        nvals = 2 * L.slab_host_c->panel.size();
+        cpx = 1;
+      } else {
+        STMG_REQUIRE(L.slab_host_r != nullptr, STMG_EINVAL, "no slab factor");
+        off = &L.slab_host_r->panel_off;
+        vals = L.slab_host_r->panel.data();
+        nvals = L.slab_host_r->panel.size();
+      }
+    } else if (which == 1) {
+      STMG_REQUIRE(md.nodal_host != nullptr, STMG_EINVAL, "no nodal factor");
+      S = &md.sym_v;
+      off = &md.nodal_host->panel_off;
+      vals = md.nodal_host->panel.data();
+      nvals = md.nodal_host->panel.size();
+    } else {
+      fail(STMG_EINVAL, "which must be 0 or 1");
+    }
+    *n = S->n;
+    *ns = S->ns;
+    *n_rows_total = (int64_t)S->rows.size();
+    *n_panel = (int64_t)(*off)[S->ns];
+    *is_complex = cpx;
+    if (perm) std::copy(S->perm.begin(), S->perm.end(), perm);
+    if (col0) std::copy(S->col0.begin(), S->col0.end(), col0);
+    if (rptr) std::copy(S->rptr.begin(), S->rptr.end(), rptr);
+    if (rows) std::copy(S->rows.begin(), S->rows.end(), rows);
+    if (panel_off) std::copy(off->begin(), off->end(), panel_off);
+    if (panel) std::copy(vals, vals + nvals, panel);
   });
 }
 

@@ -30,8 +30,7 @@ struct DevFactor {
   int64_t factor_bytes = 0;
   // host-side plan storage (descriptors point into device arrays)
   std::vector<int64_t> h_tgt_off;
-  std::vector<int32_t> h_fwd_begin, h_bwd_begin;
-  std::vector<SolvePlan::Launch> fwd, bwd_init, bwd;
+  std::vector<SolvePlan::Launch> fwd, bwd;
 };
 
 struct MeshData {

@@ -99,9 +99,10 @@ def lib():
         L.stmg_level_apply.argtypes = [vp, ip, ip, vp, vp, vp]
         L.stmg_export_matrix.argtypes = [vp, ip, ip, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), vp, vp, vp]
+        L.stmg_export_factor.argtypes = [vp, ip, ip] + [vp] * 11
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_residual", "stmg_level_apply",
-                     "stmg_export_matrix"):
+                     "stmg_export_matrix", "stmg_export_factor"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +213,22 @@ class Solver:
                                         C.c_void_p(ptr.ctypes.data), C.c_void_p(col.ctypes.data),
                                         C.c_void_p(val.ctypes.data)))
         return sp.csr_matrix((val, col, ptr), shape=(nr.value, ncl.value))
+
+    def export_factor(self, level, which):
+        """Host copy of a factor (host_only handles): dict of numpy arrays."""
+        n, ns, nr, npan, cpx = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
+        refs = [C.byref(x) for x in (n, ns, nr, npan, cpx)]
+        _check(lib().stmg_export_factor(self._h, level, which, *refs, *([None] * 6)))
+        out = dict(perm=np.zeros(n.value, np.int32), col0=np.zeros(ns.value + 1, np.int32),
+                   rptr=np.zeros(ns.value + 1, np.int64), rows=np.zeros(nr.value, np.int32),
+                   panel_off=np.zeros(ns.value + 1, np.int64),
+                   panel=np.zeros(npan.value * (2 if cpx.value else 1), np.float64))
+        ptrs = [C.c_void_p(out[k].ctypes.data) for k in ("perm", "col0", "rptr", "rows", "panel_off", "panel")]
+        _check(lib().stmg_export_factor(self._h, level, which, *refs, *ptrs))
+        if cpx.value:
+            out["panel"] = out["panel"].view(np.complex128)
+        out["complex"] = bool(cpx.value)
+        return out
 
     # -- solving ---------------------------------------------------------
     def _full(self):

@@ -1,0 +1,190 @@
+"""CPU tests of the library's host side (no GPU): the C ABI loads and exports
+every declared symbol, the host setup reproduces the oracle's assembly,
+hierarchy and transfers, the factors it would upload solve the oracle's slab
+and nodal systems, and invalid inputs are rejected with the documented codes.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1911_09548_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def stmg():
+    from paper_1911_09548_amd import stmg as m
+    m.lib()
+    return m
+
+
+def test_every_declared_symbol_is_exported(stmg):
+    header = open(os.path.join(ROOT, "include", "stmg.h")).read()
+    names = sorted(set(re.findall(r"\b(stmg_[a-z_]+)\s*\(", header)))
+    assert len(names) >= 15
+    L = stmg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+CASES = {
+    "block_n8_N16_p1": lambda: inputs.config_block_random(n=8, Nt=16, pt=1, seed=3, block_hexes=4),
+    "block_n4_N8_p0": lambda: inputs.config_block_random(n=4, Nt=8, pt=0, seed=4, block_hexes=2),
+    "jitter_n4_N4_p1": lambda: inputs.config_core_box(n=4, Nt=4, pt=1, seed=1, jitter=0.2),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request, stmg):
+    from oracle.vcycle import SpaceTimeMultigrid
+    prob = CASES[request.param]()
+    lib = stmg.Solver(prob, host_only=1)
+    ora = SpaceTimeMultigrid(prob)
+    yield request.param, prob, lib, ora
+    lib.close()
+
+
+def test_hierarchy(pair):
+    name, prob, lib, ora = pair
+    assert lib.n_levels == len(ora.specs)
+    for l, spec in enumerate(ora.specs):
+        li = lib.level_info(l)
+        assert (li.mesh, li.N) == (spec.space, spec.N)
+        assert li.tau == pytest.approx(spec.tau, rel=1e-15)
+        assert li.n_e == ora.space[spec.space].n_e
+        if spec.N > 1:
+            assert li.lambda_ == pytest.approx(ora.space[spec.space].anisotropy(spec.tau), rel=1e-12)
+
+
+def test_matrices_match_oracle(pair, stmg):
+    name, prob, lib, ora = pair
+    for l, spec in enumerate(ora.specs):
+        sd = ora.space[spec.space]
+        mats = [(stmg.MAT_M, sd.M), (stmg.MAT_K, sd.K), (stmg.MAT_G, sd.G), (stmg.MAT_KN, sd.Kn)]
+        if spec.space > 0:
+            mats.append((stmg.MAT_PE, sd.Pe))
+        for which, ref in mats:
+            A = lib.export_matrix(l, which)
+            assert A.shape == ref.shape
+            assert sp.linalg.norm(A - ref) <= 1e-13 * sp.linalg.norm(ref), (name, l, which)
+
+
+def _apply_factor(F, b):
+    """x = A^{-1} b from the exported panels P_s = [inv(L11); -L21 inv(L11)]."""
+    n = F["perm"].size
+    X = np.zeros((n,) + b.shape[1:], dtype=F["panel"].dtype)
+    X[:] = b[F["perm"]]                      # new numbering
+    ns = F["col0"].size - 1
+    blocks = []
+    for s in range(ns):
+        c0, c1 = F["col0"][s], F["col0"][s + 1]
+        w = c1 - c0
+        R = F["rows"][F["rptr"][s]:F["rptr"][s + 1]]
+        m = w + R.size
+        P = F["panel"][F["panel_off"][s]:F["panel_off"][s + 1]].reshape(w, m).T   # column-major
+        blocks.append((c0, c1, R, P[:w], P[w:]))
+    for c0, c1, R, Li, W in blocks:          # forward, post-order
+        top = X[c0:c1].copy()
+        X[R] += W @ top
+        X[c0:c1] = Li @ top
+    for c0, c1, R, Li, W in reversed(blocks):  # backward
+        X[c0:c1] = Li.T @ X[c0:c1] + W.T @ X[R]
+    out = np.empty_like(X)
+    out[F["perm"]] = X
+    return out
+
+
+def test_factors_solve_oracle_systems(pair):
+    name, prob, lib, ora = pair
+    rng = np.random.default_rng(7)
+    for l, lev in enumerate(ora.levels):
+        sd = lev.space
+        F = lib.export_factor(l, 0)
+        if prob.pt == 1:
+            A = (2 + 1j * np.sqrt(2)) * sd.M + lev.tau * sd.K
+            assert F["complex"]
+        else:
+            A = sd.M + lev.tau * sd.K
+            assert not F["complex"]
+        b = rng.standard_normal((sd.n_e, 3)) + (1j * rng.standard_normal((sd.n_e, 3)) if prob.pt else 0)
+        x = _apply_factor(F, b)
+        assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b) * 1e2, (name, l)
+        if sd.n_v > 0:
+            Fn = lib.export_factor(l, 1)
+            bn = rng.standard_normal((sd.n_v, 2))
+            xn = _apply_factor(Fn, bn)
+            ref = sp.linalg.spsolve(sd.Kn.tocsc(), bn)
+            assert np.linalg.norm(xn - ref) <= 1e-10 * np.linalg.norm(ref), (name, l)
+
+
+def test_supernode_rows_belong_to_ancestors(pair):
+    name, prob, lib, ora = pair
+    F = lib.export_factor(0, 0)
+    col0, rptr, rows = F["col0"], F["rptr"], F["rows"]
+    # every below-diagonal row lies after the supernode's columns, ascending
+    for s in range(col0.size - 1):
+        R = rows[rptr[s]:rptr[s + 1]]
+        assert np.all(np.diff(R) > 0)
+        assert R.size == 0 or R[0] >= col0[s + 1]
+
+
+def _setup_rc(stmg, prob, **opt):
+    h = None
+    try:
+        h = stmg.Solver(prob, host_only=1, **opt)
+        return stmg.STMG_OK
+    except stmg.StmgError as e:
+        return e.code
+    finally:
+        if h is not None:
+            h.close()
+
+
+def test_invalid_inputs_are_rejected(stmg):
+    good = inputs.config_unit_manufactured(2, 4, 1)
+    assert _setup_rc(stmg, good) == stmg.STMG_OK
+    bad_nt = inputs.config_unit_manufactured(2, 4, 1)
+    bad_nt.Nt = 6
+    assert _setup_rc(stmg, bad_nt) == stmg.STMG_EINVAL
+    bad_pt = inputs.config_unit_manufactured(2, 4, 1)
+    bad_pt.pt = 2
+    assert _setup_rc(stmg, bad_pt) == stmg.STMG_EINVAL
+    bad_sigma = inputs.config_unit_manufactured(2, 4, 1)
+    bad_sigma.sigma = bad_sigma.sigma.copy()
+    bad_sigma.sigma[3] = 0.0
+    assert _setup_rc(stmg, bad_sigma) == stmg.STMG_EINVAL
+    bad_nu = inputs.config_unit_manufactured(2, 4, 1)
+    bad_nu.nu = -bad_nu.nu
+    assert _setup_rc(stmg, bad_nu) == stmg.STMG_EINVAL
+    bad_T = inputs.config_unit_manufactured(2, 4, 1)
+    bad_T.T = 0.0
+    assert _setup_rc(stmg, bad_T) == stmg.STMG_EINVAL
+    degenerate = inputs.config_unit_manufactured(2, 4, 1)
+    lev0 = degenerate.levels[0]
+    lev0.tets = lev0.tets.copy()
+    lev0.tets[0, 1] = lev0.tets[0, 0]
+    assert _setup_rc(stmg, degenerate) == stmg.STMG_EINVAL
+    bad_parent = inputs.config_unit_manufactured(4, 4, 1)
+    bad_parent.levels[1].vertex_parent = bad_parent.levels[1].vertex_parent.copy()
+    bad_parent.levels[1].vertex_parent[5] = [10**6, 0]
+    assert _setup_rc(stmg, bad_parent) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, omega=0.0) == stmg.STMG_EINVAL
+
+
+def test_device_entry_points_refuse_host_only(stmg):
+    prob = inputs.config_unit_manufactured(2, 4, 1)
+    h = stmg.Solver(prob, host_only=1)
+    rc = stmg.lib().stmg_cycles(h._h, 1, None)
+    assert rc == stmg.STMG_ENOSYS
+    h.close()
+
+
+def test_error_strings(stmg):
+    L = stmg.lib()
+    for code in range(8):
+        assert len(L.stmg_strerror(code)) > 0
