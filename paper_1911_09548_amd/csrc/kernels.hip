@@ -609,15 +609,23 @@ __global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int6
   }
 }
 
+// Tiles: BM = 64 rows x BN columns of the output, K in chunks of KC = 16.
+// LDS holds A as [row][k] and B as [col][k] with a row stride of KC + 1
+// doubles, which keeps the stores of both load orders and the MFMA operand
+// reads free of bank conflicts. Complex products use three real MFMAs
+// (re = ArBr - AiBi, im = (Ar+Ai)(Br+Bi) - ArBr - AiBi). The next chunk is
+// fetched into registers while the current one is multiplied.
 template <typename T, int BN, int DIR>
-__global__ __launch_bounds__(BLOCK) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
                                                    int32_t nc, int32_t ctiles, T *X, T *Z, T *U) {
   constexpr bool CPX = Scalar<T>::cpx;
-  constexpr int BM = 64, KC = 16;
+  constexpr int NP = CPX ? 3 : 1;  // planes: re, im, re + im
+  constexpr int BM = 64, KC = 16, LD = KC + 1;
   constexpr int WN = BN >= 32 ? 2 : 1, WM = 4 / WN;
   constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
-  __shared__ double As[CPX ? 2 : 1][KC][BM];
-  __shared__ double Bs[CPX ? 2 : 1][KC][BN];
+  constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
+  __shared__ double As[NP][BM * LD];
+  __shared__ double Bs[NP][BN * LD];
   const int rowtile = blockIdx.x / ctiles, ct = blockIdx.x % ctiles;
   const int ti = find_task(tasks, n_tasks, rowtile);
   const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
@@ -630,73 +638,95 @@ __global__ __launch_bounds__(BLOCK) void k_sn_gemm(FactorDev f, const SolveTask 
   const int kend = DIR == 0 ? (i0 < w ? min(w, i0 + BM) : w) : m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave / WN) * (BM / WM), wc = (wave % WN) * (BN / WN);
-  v4d acc[CPX ? 2 : 1][MI][NI];
-#pragma unroll
-  for (int c = 0; c < (CPX ? 2 : 1); ++c)
-#pragma unroll
-    for (int a = 0; a < MI; ++a)
-#pragma unroll
-      for (int b = 0; b < NI; ++b) acc[c][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += KC) {
-    // A tile (BM x KC) of P (forward) or P^T (backward)
-    for (int e = threadIdx.x; e < BM * KC; e += BLOCK) {
+  double ra[AE][2], rb[BE][2];  // prefetch registers (re, im)
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
       int i, k;
-      if (DIR == 0) {
+      if (DIR == 0) {  // P column segments: rows contiguous
         i = e % BM;
         k = e / BM;
-      } else {
+      } else {         // P^T rows are P columns: k contiguous
         k = e % KC;
         i = e / KC;
       }
       const int gi = i0 + i, gk = k0 + k;
-      double re = 0.0, im = 0.0;
-      if (gi < rows && gk < kend) split(DIR == 0 ? P[gi + (int64_t)gk * m] : P[gk + (int64_t)gi * m], re, im);
-      As[0][k][i] = re;
-      if (CPX) As[CPX ? 1 : 0][k][i] = im;
+      ra[q][0] = ra[q][1] = 0.0;
+      if (gi < rows && gk < kend)
+        split(DIR == 0 ? P[gi + (int64_t)gk * m] : P[gk + (int64_t)gi * m], ra[q][0], ra[q][1]);
     }
-    // B tile (KC x BN): rows of the right-hand sides
-    for (int e = threadIdx.x; e < KC * BN; e += BLOCK) {
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
       const int j = e % BN, k = e / BN;
       const int gk = k0 + k, gj = j0 + j;
-      double re = 0.0, im = 0.0;
-      if (gk < kend && gj < nc) {
+      rb[q][0] = rb[q][1] = 0.0;
+      if (k < KC && gk < kend && gj < nc) {
         const T *row;
         if (DIR == 0)
           row = X + (int64_t)(c0 + gk) * nc;
         else
           row = gk < w ? Z + (int64_t)(c0 + gk) * nc : X + (int64_t)R[gk - w] * nc;
-        split(row[gj], re, im);
+        split(row[gj], rb[q][0], rb[q][1]);
       }
-      Bs[0][k][j] = re;
-      if (CPX) Bs[CPX ? 1 : 0][k][j] = im;
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      const int i = DIR == 0 ? e % BM : e / KC, k = DIR == 0 ? e / BM : e % KC;
+      As[0][i * LD + k] = ra[q][0];
+      if constexpr (CPX) {
+        As[1][i * LD + k] = ra[q][1];
+        As[2][i * LD + k] = ra[q][0] + ra[q][1];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      const int j = e % BN, k = e / BN;
+      if (k < KC) {
+        Bs[0][j * LD + k] = rb[q][0];
+        if constexpr (CPX) {
+          Bs[1][j * LD + k] = rb[q][1];
+          Bs[2][j * LD + k] = rb[q][0] + rb[q][1];
+        }
+      }
+    }
+  };
+
+  v4d acc[NP][MI][NI];
+#pragma unroll
+  for (int c = 0; c < NP; ++c)
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+      for (int b = 0; b < NI; ++b) acc[c][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    stash();
     __syncthreads();
+    if (k0 + KC < kend) fetch(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + lane / 16;
-      double ar[MI], ai[MI], br[NI], bi[NI];
 #pragma unroll
-      for (int a = 0; a < MI; ++a) {
-        ar[a] = As[0][kr][wr + a * 16 + (lane & 15)];
-        if (CPX) ai[a] = As[CPX ? 1 : 0][kr][wr + a * 16 + (lane & 15)];
+      for (int pl = 0; pl < NP; ++pl) {
+        double av[MI], bv[NI];
+#pragma unroll
+        for (int a = 0; a < MI; ++a) av[a] = As[pl][(wr + a * 16 + (lane & 15)) * LD + kr];
+#pragma unroll
+        for (int b = 0; b < NI; ++b) bv[b] = Bs[pl][(wc + b * 16 + (lane & 15)) * LD + kr];
+#pragma unroll
+        for (int a = 0; a < MI; ++a)
+#pragma unroll
+          for (int b = 0; b < NI; ++b)
+            acc[pl][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[pl][a][b], 0, 0, 0);
       }
-#pragma unroll
-      for (int b = 0; b < NI; ++b) {
-        br[b] = Bs[0][kr][wc + b * 16 + (lane & 15)];
-        if (CPX) bi[b] = Bs[CPX ? 1 : 0][kr][wc + b * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int a = 0; a < MI; ++a)
-#pragma unroll
-        for (int b = 0; b < NI; ++b) {
-          acc[0][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc[0][a][b], 0, 0, 0);
-          if constexpr (CPX) {
-            acc[0][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], acc[0][a][b], 0, 0, 0);
-            acc[1][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc[1][a][b], 0, 0, 0);
-            acc[1][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc[1][a][b], 0, 0, 0);
-          }
-        }
     }
     __syncthreads();
   }
@@ -710,7 +740,14 @@ __global__ __launch_bounds__(BLOCK) void k_sn_gemm(FactorDev f, const SolveTask 
         const int row = i0 + wr + a * 16 + 4 * r + lane / 16;
         const int col = j0 + wc + b * 16 + (lane & 15);
         if (row >= rows || col >= nc) continue;
-        const double vr = acc[0][a][b][r], vi = CPX ? acc[CPX ? 1 : 0][a][b][r] : 0.0;
+        double vr, vi = 0.0;
+        if constexpr (CPX) {
+          const double p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
+          vr = p1 - p2;
+          vi = p3 - p1 - p2;
+        } else {
+          vr = acc[0][a][b][r];
+        }
         if (DIR == 0) {
           if (row < w) {
             make(vr, vi, Z[(int64_t)(c0 + row) * nc + col]);
