@@ -101,6 +101,7 @@ typedef struct {
   int32_t host_only;             /* 1: build host data only (no device), for tests */
   int32_t factor_on_device;      /* 1 (default): numeric factorisation on the GPU */
   int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
+  int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */
 } stmg_options;
 
 typedef struct {

@@ -615,13 +615,14 @@ __global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int6
 // reads free of bank conflicts. Complex products use three real MFMAs
 // (re = ArBr - AiBi, im = (Ar+Ai)(Br+Bi) - ArBr - AiBi). The next chunk is
 // fetched into registers while the current one is multiplied.
-template <typename T, int BN, int DIR>
+template <typename T, int BM, int BN, int DIR>
 __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
                                                    int32_t nc, int32_t ctiles, T *X, T *Z, T *U) {
   constexpr bool CPX = Scalar<T>::cpx;
   constexpr int NP = CPX ? 3 : 1;  // planes: re, im, re + im
-  constexpr int BM = 64, KC = 16, LD = KC + 1;
+  constexpr int KC = 16, LD = KC + 1;
   constexpr int WN = BN >= 32 ? 2 : 1, WM = 4 / WN;
+  static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile shape");
   constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
   constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
   __shared__ double As[NP][BM * LD];
@@ -763,18 +764,37 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       }
 }
 
+// Tile shape per launch: BN from the right-hand-side width; 32-row tiles when
+// 64-row tiles would leave the GPU short of work items or pad many rows.
 template <typename T, int DIR>
-static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t nc, T *X, T *Z, T *U,
-                           hipStream_t s) {
+static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t nc, T *X,
+                           T *Z, T *U, hipStream_t s) {
   if (L.n_tasks == 0) return;
-  if (nc > 16) {
-    const int ct = (nc + 63) / 64;
-    hipLaunchKernelGGL((k_sn_gemm<T, 64, DIR>), dim3((unsigned)(L.n_tiles * ct)), dim3(BLOCK), 0, s, f, L.tasks,
-                       L.n_tasks, nc, ct, X, Z, U);
-  } else {
-    hipLaunchKernelGGL((k_sn_gemm<T, 16, DIR>), dim3((unsigned)L.n_tiles), dim3(BLOCK), 0, s, f, L.tasks,
-                       L.n_tasks, nc, 1, X, Z, U);
+  int bn = nc > 32 ? 64 : (nc > 16 ? 32 : 16);
+  const int64_t ct64 = (nc + bn - 1) / bn;
+  bool bm32 = false;
+  if (bn >= 32) {
+    const double eff64 = (double)L.rows / (64.0 * L.n_tiles), eff32 = (double)L.rows / (32.0 * L.n_tiles32);
+    bm32 = (int64_t)L.n_tiles * ct64 < 1024 || eff32 > eff64 + 0.15;
+    if (policy == 64) bm32 = false;
+    if (policy == 32) bm32 = true;
+    if (bm32 && bn == 64 && policy == 0 && (int64_t)L.n_tiles32 * ct64 < 512) bn = 32;
   }
+  const int ct = (nc + bn - 1) / bn;
+  const SolveTask *tasks = bm32 ? L.tasks32 : L.tasks;
+  const unsigned grid = (unsigned)((bm32 ? L.n_tiles32 : L.n_tiles) * ct);
+#define SN_CASE(BMV, BNV)                                                                                  \
+  if ((bm32 ? 32 : 64) == BMV && bn == BNV) {                                                              \
+    hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, nc, \
+                       ct, X, Z, U);                                                                       \
+    return;                                                                                                \
+  }
+  SN_CASE(64, 64)
+  SN_CASE(64, 32)
+  SN_CASE(64, 16)
+  SN_CASE(32, 64)
+  SN_CASE(32, 32)
+#undef SN_CASE
 }
 
 template <typename T>
@@ -784,13 +804,13 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
     if (t1 > t0)
       hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)(t1 - t0)), dim3(64), 0, s, p.tgt + t0, p.src, nc,
                          X, U);
-    launch_sn_gemm<T, 0>(f, p.fwd[h], nc, X, Z, U, s);
+    launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, nc, X, Z, U, s);
   }
 }
 
 template <typename T>
 void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s) {
-  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], nc, X, Z, nullptr, s);
+  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], p.tile_rows, nc, X, Z, nullptr, s);
 }
 
 template void solve_forward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,

@@ -109,9 +109,13 @@ struct SolvePlan {
   const int64_t *src;            // device U rows
   // one GEMM launch per height and direction: host descriptors, device tasks
   struct Launch {
-    int32_t n_tasks, n_tiles;    // supernodes, 64-row tiles
-    const SolveTask *tasks;      // device
+    int32_t n_tasks;             // supernodes
+    int32_t n_tiles, n_tiles32;  // 64-row and 32-row tiles
+    int64_t rows;                // output rows over all supernodes
+    const SolveTask *tasks;      // device, prefix over 64-row tiles
+    const SolveTask *tasks32;    // device, prefix over 32-row tiles
   };
+  int32_t tile_rows;             // 0: choose per launch; 64 or 32: forced
   const Launch *fwd;             // host [H]: row tiles over m = w + r
   const Launch *bwd;             // host [H]: row tiles over w
 };

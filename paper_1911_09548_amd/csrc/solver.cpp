@@ -101,28 +101,35 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   }
   D.h_tgt_off[H] = (int64_t)tgt.size();
   tgt.push_back({0, (int64_t)src.size()});  // sentinel
-  // one forward and one backward GEMM launch per height
+  // one forward and one backward GEMM launch per height; task prefixes for
+  // 64-row and 32-row tiles
   std::vector<SolveTask> tasks;
   struct Pending {
-    size_t off, n;
-    int32_t tiles;
+    size_t off64, off32, n;
+    int32_t tiles64, tiles32;
+    int64_t rows;
+  };
+  auto make_pending = [&](int32_t hh, bool fwd) {
+    Pending p{tasks.size(), 0, 0, 0, 0, 0};
+    for (int32_t s : by_h[hh]) {
+      const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
+      tasks.push_back({s, p.tiles64});
+      p.tiles64 += (rows + 63) / 64;
+      p.rows += rows;
+    }
+    p.n = tasks.size() - p.off64;
+    p.off32 = tasks.size();
+    for (int32_t s : by_h[hh]) {
+      const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
+      tasks.push_back({s, p.tiles32});
+      p.tiles32 += (rows + 31) / 32;
+    }
+    return p;
   };
   std::vector<Pending> pf(H), pb(H);
   for (int32_t hh = 0; hh < H; ++hh) {
-    Pending p{tasks.size(), 0, 0};
-    for (int32_t s : by_h[hh]) {
-      tasks.push_back({s, p.tiles});
-      p.tiles += (S.width(s) + S.nrows(s) + 63) / 64;
-    }
-    p.n = tasks.size() - p.off;
-    pf[hh] = p;
-    Pending q{tasks.size(), 0, 0};
-    for (int32_t s : by_h[hh]) {
-      tasks.push_back({s, q.tiles});
-      q.tiles += (S.width(s) + 63) / 64;
-    }
-    q.n = tasks.size() - q.off;
-    pb[hh] = q;
+    pf[hh] = make_pending(hh, true);
+    pb[hh] = make_pending(hh, false);
   }
   SolveTask *dt = dev_upload(h, tasks);
   AsmTarget *dtg = dev_upload(h, tgt);
@@ -130,8 +137,11 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   auto mk = [&](const Pending &p) {
     SolvePlan::Launch L;
     L.n_tasks = (int32_t)p.n;
-    L.n_tiles = p.tiles;
-    L.tasks = dt + p.off;
+    L.n_tiles = p.tiles64;
+    L.n_tiles32 = p.tiles32;
+    L.rows = p.rows;
+    L.tasks = dt + p.off64;
+    L.tasks32 = dt + p.off32;
     return L;
   };
   for (auto &p : pf) D.fwd.push_back(mk(p));
@@ -147,6 +157,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.f.rows = dev_upload(h, S.rows);
   D.f.uoff = dev_upload(h, uoff);
   D.plan.n_heights = H;
+  D.plan.tile_rows = h->opt.gemm_rows;
   D.plan.h_tgt_off = D.h_tgt_off.data();
   D.plan.tgt = dtg;
   D.plan.src = dsrc;
@@ -491,6 +502,7 @@ void stmg_default_options(stmg_options *o) {
   o->host_only = 0;
   o->factor_on_device = 0;
   o->leaf_size = 8;
+  o->gemm_rows = 0;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -510,6 +522,8 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
     STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
     STMG_REQUIRE(h->opt.precision == STMG_FP64, STMG_ENOSYS, "precision form not available yet");
     if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
+    STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
+                 "gemm_rows must be 0, 32 or 64");
     if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
     h->stream = static_cast<hipStream_t>(stream);
     h->pt = prob->pt;

@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("allow_space_coarsening", C.c_int32), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("host_only", C.c_int32), ("factor_on_device", C.c_int32),
-                ("leaf_size", C.c_int32)]
+                ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32)]
 
 
 class Report(C.Structure):

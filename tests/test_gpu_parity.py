@@ -66,7 +66,12 @@ CASES = {
     "block_n8_N32_p1": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=5, block_hexes=4),
     "block_n8_N8_p0": lambda: inputs.config_block_random(n=8, Nt=8, pt=0, seed=6, block_hexes=4),
     "jitter_n6_N16_p1": lambda: inputs.config_core_box(n=6, Nt=16, pt=1, seed=2, jitter=0.2),
+    # forced 64-row GEMM tiles (the per-launch choice picks 32 rows on small meshes)
+    "block_n8_N64_p1_rows64": lambda: inputs.config_block_random(n=8, Nt=64, pt=1, seed=8, block_hexes=4),
+    "block_n8_N16_p0_rows64": lambda: inputs.config_block_random(n=8, Nt=16, pt=0, seed=9, block_hexes=4),
 }
+OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
+        "block_n8_N32_p1": dict(gemm_rows=32)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -75,7 +80,7 @@ def pair(request):
     from oracle.vcycle import SpaceTimeMultigrid
     prob = CASES[request.param]()
     print(f"\n[case] {request.param}", flush=True)
-    gpu = stmg.Solver(prob)
+    gpu = stmg.Solver(prob, **OPTS.get(request.param, {}))
     ora = SpaceTimeMultigrid(prob)
     _ORACLES[request.param] = ora
     yield request.param, prob, gpu, ora
