@@ -117,14 +117,38 @@ def main():
     solver.load(rhs)
     solver.cycles(args.warmup)
     torch.cuda.synchronize()
+    # the library runs on torch's current stream: events on it bracket the
+    # timed region; per-launch events inside the library give each kernel's
+    # duration on that same stream
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    solver.profile(True)
     e0.record(stream)
     res = solver.cycles(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    kernels = solver.profile_report()
+    solver.profile(False)
     log(f"[bench] {ms:.2f} ms per V-cycle, residuals {res[-1]:.2e}")
+    for k in kernels[:8]:
+        log(f"[bench]   {k['kernel']:28s} {k['ms'] / args.steps:8.2f} ms/step {k['launches'] // args.steps:5d} launches/step "
+            f"{k['flops'] / (k['ms'] * 1e-3) / 1e12:7.2f} TFLOP/s {k['bytes'] / (k['ms'] * 1e-3) / 1e9:8.1f} GB/s")
+    top = kernels[0]
+    avg_s = top["ms"] * 1e-3 / top["launches"]
+    if top["kernel"].startswith("k_sn_gemm"):
+        achieved = top["flops"] / top["launches"] / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    else:
+        achieved = top["bytes"] / top["launches"] / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": top["kernel"], "avg_launch_us": avg_s * 1e6, "launches": top["launches"]})
+    breakdown = [{"kernel": k["kernel"], "ms_per_step": k["ms"] / args.steps,
+                  "launches_per_step": k["launches"] // args.steps,
+                  "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12,
+                  "gbs": k["bytes"] / (k["ms"] * 1e-3) / 1e9} for k in kernels[:12]]
 
     extra = {}
     if not args.no_solve:
@@ -146,6 +170,8 @@ def main():
                                 f"p_t={args.pt}, block-random sigma in [1,1e3], nu in [1,100], Gaussian rhs"),
                    "n_interior_edges": n_e, "space_time_dofs": dofs, "levels": len(levels),
                    "setup_s": setup_s, **extra},
+        "roofline": roof,
+        "kernels": breakdown,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")

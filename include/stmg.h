@@ -102,6 +102,8 @@ typedef struct {
   int32_t factor_on_device;      /* 1 (default): numeric factorisation on the GPU */
   int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
   int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */
+  int32_t factor_transpose;      /* also keep P^T for the backward solves: -1 auto, 0 never, 1 always */
+  int32_t gemm_splitk;           /* backward K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
 } stmg_options;
 
 typedef struct {
@@ -207,6 +209,21 @@ int stmg_level_apply(stmg_handle *h, int32_t level, int32_t op, const double *in
 int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32_t *n_rows,
                        int32_t *n_cols, int64_t *nnz, int64_t *row_ptr, int32_t *col,
                        double *val);
+
+/* Launch timing for roofline accounting. stmg_profile(h, 1) clears the
+ * counters and brackets every subsequent supernode-GEMM and residual launch
+ * with HIP events recorded on the handle's stream; stmg_profile(h, 0) stops.
+ * stmg_profile_count synchronises the stream and aggregates per kernel
+ * (instantiation names as "k_sn_gemm<cd,64,64,bwd>", "k_residual<8,2>");
+ * stmg_profile_get returns kernel i's name, launch count, summed duration
+ * and summed algorithmic work: flops (one multiply-add per factor entry and
+ * right-hand side for the solves; two per nonzero and column for M and K in
+ * the residual) and bytes (each operand read once, each result written
+ * once). Timing adds no synchronisation inside a cycle. */
+int stmg_profile(stmg_handle *h, int32_t enable);
+int stmg_profile_count(stmg_handle *h, int32_t *n_kernels);
+int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
+                     double *total_ms, double *flops, double *bytes);
 
 /* Host copy of a level's factor (host_only handles): which = 0 slab block
  * (complex for pt = 1: values interleaved re, im), 1 nodal matrix K_n.

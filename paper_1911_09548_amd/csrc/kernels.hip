@@ -78,26 +78,51 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
 #pragma unroll
   for (int j = 0; j < C; ++j) am[j] = ak[j] = 0.0;
   if (active && a.x) {
+    // four nonzeros per step: their column indices, values and x rows are
+    // all requested before any is used, keeping 4*C loads in flight per lane
     const int64_t k1 = a.ptr[row + 1];
-    for (int64_t k = a.ptr[row]; k < k1; ++k) {
+    int64_t k = a.ptr[row];
+    for (; k + 4 <= k1; k += 4) {
+      int c[4];
+      double mv[4], kv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = a.col[k + u];
+        mv[u] = a.mval[k + u];
+        kv[u] = a.kval[k + u];
+      }
+      double xv[4][C];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double *xr = a.x + (int64_t)c[u] * W + li * C;
+        if constexpr (C % 2 == 0) {
+#pragma unroll
+          for (int j = 0; j < C; j += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(xr + j);
+            xv[u][j] = v.x;
+            xv[u][j + 1] = v.y;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < C; ++j) xv[u][j] = xr[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          am[j] += mv[u] * xv[u][j];
+          ak[j] += kv[u] * xv[u][j];
+        }
+    }
+    for (; k < k1; ++k) {
       const int c = a.col[k];
       const double mv = a.mval[k], kv = a.kval[k];
       const double *xr = a.x + (int64_t)c * W + li * C;
-      if constexpr (C % 2 == 0) {
 #pragma unroll
-        for (int j = 0; j < C; j += 2) {
-          const double2 v = *reinterpret_cast<const double2 *>(xr + j);
-          am[j] += mv * v.x;
-          am[j + 1] += mv * v.y;
-          ak[j] += kv * v.x;
-          ak[j + 1] += kv * v.y;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-          am[j] += mv * xr[j];
-          ak[j] += kv * xr[j];
-        }
+      for (int j = 0; j < C; ++j) {
+        am[j] += mv * xr[j];
+        ak[j] += kv * xr[j];
       }
     }
   }
@@ -157,11 +182,29 @@ static void launch_res_cq(const ResidualArgs &a, int nblocks, hipStream_t s) {
   hipLaunchKernelGGL((k_residual<C, Q>), dim3(nblocks), dim3(BLOCK), 0, s, a);
 }
 
+void launch_residual_inner(const ResidualArgs &a, int nb, int C, hipStream_t s);
+
 void launch_residual(const ResidualArgs &a, hipStream_t s) {
   const int W = a.N * a.q;
   const int C = lane_chunk(W, a.q);
   const int nb = residual_blocks(a.n_rows, W, a.q);
   if (nb == 0) return;
+  if (a.prof) {
+    // algorithmic traffic: x, b read once, out written once, the pattern and
+    // both value arrays read once; 4 flops per nonzero and column (two FMAs)
+    char name[64];
+    snprintf(name, sizeof name, "k_residual<%d,%d>", C, a.q);
+    a.prof->begin(s);
+    launch_residual_inner(a, nb, C, s);
+    const double rows = a.n_rows, cols = W;
+    const double nnz = (double)a.nnz;
+    a.prof->end(s, name, 4.0 * nnz * cols, 8.0 * rows * cols * (a.x ? 3.0 : 2.0) + 20.0 * nnz + 8.0 * (rows + 1));
+    return;
+  }
+  launch_residual_inner(a, nb, C, s);
+}
+
+void launch_residual_inner(const ResidualArgs &a, int nb, int C, hipStream_t s) {
 #define RES_CASE(CC, QQ) \
   if (C == CC && a.q == QQ) return launch_res_cq<CC, QQ>(a, nb, s);
   RES_CASE(1, 1)
@@ -174,7 +217,7 @@ void launch_residual(const ResidualArgs &a, hipStream_t s) {
   RES_CASE(8, 2)
   RES_CASE(16, 2)
 #undef RES_CASE
-  fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", W, a.q);
+  fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", a.N * a.q, a.q);
 }
 
 // --------------------------------------------------------------- reductions
@@ -585,13 +628,16 @@ __device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
 }  // namespace
 
 // Forward assembly (extend-add): each target row of a front receives the
-// children's update rows in a fixed order.
+// children's update rows in a fixed order. One wavefront per target row.
 template <typename T>
-__global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int64_t *src, int32_t nc, T *X,
-                                                T *U) {
-  const AsmTarget t = tgt[blockIdx.x];
-  const int64_t s1 = tgt[blockIdx.x + 1].src_begin;
-  for (int c = threadIdx.x; c < nc; c += 64) {
+__global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src,
+                                                   int32_t nc, T *X, T *U) {
+  const int64_t ti = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+  if (ti >= n_tgt) return;
+  const int lane = threadIdx.x & 63;
+  const AsmTarget t = tgt[ti];
+  const int64_t s1 = tgt[ti + 1].src_begin;
+  for (int c = lane; c < nc; c += 64) {
     double ar = 0.0, ai = 0.0;
     for (int64_t k = t.src_begin; k < s1; ++k) {
       double r, i;
@@ -615,9 +661,14 @@ __global__ __launch_bounds__(64) void k_fwd_asm(const AsmTarget *tgt, const int6
 // reads free of bank conflicts. Complex products use three real MFMAs
 // (re = ArBr - AiBi, im = (Ar+Ai)(Br+Bi) - ArBr - AiBi). The next chunk is
 // fetched into registers while the current one is multiplied.
+// DIR 0: forward (A = P). DIR 1: backward (A = P^T, read from P), DIR 2:
+// backward reading the stored transpose (same access pattern as forward).
+// With nsplit > 1 the K range is cut into nsplit segments of kseg and each
+// work item writes its partial tile to ws; k_sn_reduce adds them in order.
 template <typename T, int BM, int BN, int DIR>
 __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
-                                                   int32_t nc, int32_t ctiles, T *X, T *Z, T *U) {
+                                                   int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
+                                                   int32_t nsplit, int32_t kseg, T *ws) {
   constexpr bool CPX = Scalar<T>::cpx;
   constexpr int NP = CPX ? 3 : 1;  // planes: re, im, re + im
   constexpr int KC = 16, LD = KC + 1;
@@ -627,16 +678,19 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
   constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
   __shared__ double As[NP][BM * LD];
   __shared__ double Bs[NP][BN * LD];
-  const int rowtile = blockIdx.x / ctiles, ct = blockIdx.x % ctiles;
+  const int ct = blockIdx.x % ctiles, rs = blockIdx.x / ctiles;
+  const int seg = rs % nsplit, rowtile = rs / nsplit;
   const int ti = find_task(tasks, n_tasks, rowtile);
   const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
-  const T *P = reinterpret_cast<const T *>(f.panel) + f.panel_off[s];
+  const T *P = reinterpret_cast<const T *>(DIR == 2 ? f.panel_t : f.panel) + f.panel_off[s];
   const int32_t *R = f.rows + f.rptr[s];
   const int i0 = rt * BM, j0 = ct * BN;
   const int rows = DIR == 0 ? m : w;
-  const int kbeg = DIR == 0 ? 0 : i0;
-  const int kend = DIR == 0 ? (i0 < w ? min(w, i0 + BM) : w) : m;
+  const int kb0 = DIR == 0 ? 0 : i0;
+  const int ke0 = DIR == 0 ? (i0 < w ? min(w, i0 + BM) : w) : m;
+  const int kbeg = nsplit > 1 ? kb0 + seg * kseg : kb0;
+  const int kend = nsplit > 1 ? min(ke0, kbeg + kseg) : ke0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave / WN) * (BM / WM), wc = (wave % WN) * (BN / WN);
 
@@ -646,7 +700,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
     for (int q = 0; q < AE; ++q) {
       const int e = threadIdx.x + q * BLOCK;
       int i, k;
-      if (DIR == 0) {  // P column segments: rows contiguous
+      if (DIR != 1) {  // column segments of P (or of the stored P^T): rows contiguous
         i = e % BM;
         k = e / BM;
       } else {         // P^T rows are P columns: k contiguous
@@ -656,7 +710,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       const int gi = i0 + i, gk = k0 + k;
       ra[q][0] = ra[q][1] = 0.0;
       if (gi < rows && gk < kend)
-        split(DIR == 0 ? P[gi + (int64_t)gk * m] : P[gk + (int64_t)gi * m], ra[q][0], ra[q][1]);
+        split(DIR == 0 ? P[gi + (int64_t)gk * m] : (DIR == 1 ? P[gk + (int64_t)gi * m] : P[gi + (int64_t)gk * w]),
+              ra[q][0], ra[q][1]);
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
@@ -678,7 +733,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
       const int e = threadIdx.x + q * BLOCK;
-      const int i = DIR == 0 ? e % BM : e / KC, k = DIR == 0 ? e / BM : e % KC;
+      const int i = DIR != 1 ? e % BM : e / KC, k = DIR != 1 ? e / BM : e % KC;
       As[0][i * LD + k] = ra[q][0];
       if constexpr (CPX) {
         As[1][i * LD + k] = ra[q][1];
@@ -740,6 +795,19 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       for (int r = 0; r < 4; ++r) {
         const int row = i0 + wr + a * 16 + 4 * r + lane / 16;
         const int col = j0 + wc + b * 16 + (lane & 15);
+        if (nsplit > 1) {  // partial tile: (rowtile, seg) block of BM rows x nc
+          if (col >= nc) continue;
+          double pr, pi = 0.0;
+          if constexpr (CPX) {
+            const double p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
+            pr = p1 - p2;
+            pi = p3 - p1 - p2;
+          } else {
+            pr = acc[0][a][b][r];
+          }
+          make(pr, pi, ws[((int64_t)rs * BM + (row - i0)) * nc + col]);
+          continue;
+        }
         if (row >= rows || col >= nc) continue;
         double vr, vi = 0.0;
         if constexpr (CPX) {
@@ -764,11 +832,36 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       }
 }
 
+// Sum of the split-K partial tiles in segment order, then the same epilogue
+// as the unsplit kernel (backward: X[C_s] rows).
+template <typename T, int BM>
+__global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+                                                     int32_t nc, int32_t nsplit, const T *ws, T *X) {
+  const int rowtile = blockIdx.x;
+  const int ti = find_task(tasks, n_tasks, rowtile);
+  const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
+  const int c0 = f.col0[s], w = f.col0[s + 1] - c0;
+  for (int e = threadIdx.x; e < BM * nc; e += BLOCK) {
+    const int rr = e / nc, col = e % nc;
+    const int row = rt * BM + rr;
+    if (row >= w) continue;
+    double ar = 0.0, ai = 0.0;
+    for (int g = 0; g < nsplit; ++g) {
+      double r, i;
+      split(ws[(((int64_t)rowtile * nsplit + g) * BM + rr) * nc + col], r, i);
+      ar += r;
+      ai += i;
+    }
+    make(ar, ai, X[(int64_t)(c0 + row) * nc + col]);
+  }
+}
+
 // Tile shape per launch: BN from the right-hand-side width; 32-row tiles when
 // 64-row tiles would leave the GPU short of work items or pad many rows.
 template <typename T, int DIR>
-static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t nc, T *X,
-                           T *Z, T *U, hipStream_t s) {
+static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t splitk,
+                           Profiler *prof, void *ws, int64_t ws_bytes, int32_t nc, T *X, T *Z, T *U,
+                           hipStream_t s) {
   if (L.n_tasks == 0) return;
   int bn = nc > 32 ? 64 : (nc > 16 ? 32 : 16);
   const int64_t ct64 = (nc + bn - 1) / bn;
@@ -782,11 +875,47 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   }
   const int ct = (nc + bn - 1) / bn;
   const SolveTask *tasks = bm32 ? L.tasks32 : L.tasks;
-  const unsigned grid = (unsigned)((bm32 ? L.n_tiles32 : L.n_tiles) * ct);
+  const int64_t tiles = bm32 ? L.n_tiles32 : L.n_tiles;
+  // backward launches with too few work items for the GPU and long K ranges
+  // are split along K (deterministic two-pass sum)
+  int nsplit = 1, kseg = 0;
+  const int bmv = bm32 ? 32 : 64;
+  if (DIR != 0 && ws && splitk >= 0) {
+    int want = 1;
+    if (splitk >= 2)
+      want = splitk;
+    else if (tiles * ct < 2048 && L.kmax >= 512)
+      want = (int)std::min<int64_t>(8, (2048 + tiles * ct - 1) / (tiles * ct));
+    if (want > 1 && L.kmax > 16) {
+      kseg = ((L.kmax + want - 1) / want + 15) / 16 * 16;
+      nsplit = (L.kmax + kseg - 1) / kseg;
+      if (nsplit < 2 || (int64_t)tiles * nsplit * bmv * nc * (int64_t)sizeof(T) > ws_bytes) nsplit = 1;
+    }
+  }
+  const unsigned grid = (unsigned)(tiles * nsplit * ct);
+  const int dir_k = (DIR == 1 && f.panel_t) ? 2 : DIR;
+  // algorithmic work: one multiply-add per factor entry and right-hand side
+  // (8 flops complex, 2 real); traffic: the factor panels once, the
+  // right-hand-side rows in and out once
+  const double scal = Scalar<T>::cpx ? 16.0 : 8.0;
+  char name[96];
+  if (prof) {
+    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>%s", Scalar<T>::cpx ? "cd" : "double", bmv, bn,
+             DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd"), nsplit > 1 ? "+splitk" : "");
+    prof->begin(s);
+  }
 #define SN_CASE(BMV, BNV)                                                                                  \
-  if ((bm32 ? 32 : 64) == BMV && bn == BNV) {                                                              \
-    hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, nc, \
-                       ct, X, Z, U);                                                                       \
+  if (bmv == BMV && bn == BNV) {                                                                           \
+    if (dir_k == 2)                                                                                        \
+      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, 2>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, nc, \
+                         ct, X, Z, U, nsplit, kseg, (T *)ws);                                              \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
+                         nc, ct, X, Z, U, nsplit, kseg, (T *)ws);                                          \
+    if (nsplit > 1)                                                                                        \
+      hipLaunchKernelGGL((k_sn_reduce<T, BMV>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
+                         nc, nsplit, (const T *)ws, X);                                                    \
+    if (prof) prof->end(s, name, (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz * nc, scal * (L.nnz + 2.0 * L.rows * nc)); \
     return;                                                                                                \
   }
   SN_CASE(64, 64)
@@ -802,15 +931,16 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
   for (int h = 0; h < p.n_heights; ++h) {
     const int64_t t0 = p.h_tgt_off[h], t1 = p.h_tgt_off[h + 1];
     if (t1 > t0)
-      hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)(t1 - t0)), dim3(64), 0, s, p.tgt + t0, p.src, nc,
-                         X, U);
-    launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, nc, X, Z, U, s);
+      hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(BLOCK), 0, s, p.tgt + t0,
+                         t1 - t0, p.src, nc, X, U);
+    launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, p.splitk, p.prof, nullptr, 0, nc, X, Z, U, s);
   }
 }
 
 template <typename T>
 void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s) {
-  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], p.tile_rows, nc, X, Z, nullptr, s);
+  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], p.tile_rows, p.splitk, p.prof, p.splitk_ws, p.splitk_bytes, nc, X, Z,
+                         nullptr, s);
 }
 
 template void solve_forward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,

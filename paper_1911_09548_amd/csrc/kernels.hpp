@@ -12,6 +12,15 @@
 
 namespace stmg {
 
+// Optional per-launch timing: when a Profiler is attached, launches are
+// bracketed by events recorded on their own stream and tagged with their
+// kernel name and algorithmic work (implemented by the handle).
+struct Profiler {
+  void begin(hipStream_t s);
+  void end(hipStream_t s, const char *kernel, double flops, double bytes);
+  void *impl = nullptr;
+};
+
 struct cd {  // complex double, 16-byte aligned
   double re, im;
 };
@@ -30,6 +39,8 @@ struct ResidualArgs {
   double *out;
   double *partial;              // may be null: per-block sum of squares of r
   int32_t mode;                 // 0: out = r; 1: out = slab-solve right-hand side
+  int64_t nnz = 0;              // pattern nonzeros (work accounting only)
+  Profiler *prof = nullptr;
 };
 enum { RES_OUT_R = 0, RES_OUT_SLABRHS = 1 };
 int residual_blocks(int32_t n_rows, int32_t W, int32_t q);
@@ -90,6 +101,7 @@ struct FactorDev {
   const int64_t *panel_off;
   const int64_t *uoff;     // [ns] first U row of each supernode
   const void *panel;       // P_s = [inv(L_ss); -L_{R,s} inv(L_ss)], column-major
+  const void *panel_t;     // optional P_s^T (w x m, column-major) for the backward solve
 };
 struct SolveTask {
   int32_t s;
@@ -109,13 +121,19 @@ struct SolvePlan {
   const int64_t *src;            // device U rows
   // one GEMM launch per height and direction: host descriptors, device tasks
   struct Launch {
+    double nnz;                  // factor entries of its supernodes (w(w+1)/2 + r w each)
     int32_t n_tasks;             // supernodes
     int32_t n_tiles, n_tiles32;  // 64-row and 32-row tiles
     int64_t rows;                // output rows over all supernodes
+    int32_t kmax;                // longest K range (backward: max m)
     const SolveTask *tasks;      // device, prefix over 64-row tiles
     const SolveTask *tasks32;    // device, prefix over 32-row tiles
   };
   int32_t tile_rows;             // 0: choose per launch; 64 or 32: forced
+  int32_t splitk;                // 0 auto, -1 never, >= 2 forced
+  Profiler *prof;                // may be null
+  void *splitk_ws;               // split-K partial sums (device), may be null
+  int64_t splitk_bytes;
   const Launch *fwd;             // host [H]: row tiles over m = w + r
   const Launch *bwd;             // host [H]: row tiles over w
 };

@@ -108,14 +108,19 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
     size_t off64, off32, n;
     int32_t tiles64, tiles32;
     int64_t rows;
+    double nnz;
+    int32_t kmax;
   };
   auto make_pending = [&](int32_t hh, bool fwd) {
-    Pending p{tasks.size(), 0, 0, 0, 0, 0};
+    Pending p{tasks.size(), 0, 0, 0, 0, 0, 0.0, 0};
     for (int32_t s : by_h[hh]) {
       const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
       tasks.push_back({s, p.tiles64});
       p.tiles64 += (rows + 63) / 64;
       p.rows += rows;
+      const double w = S.width(s), r = S.nrows(s);
+      p.nnz += w * (w + 1) / 2 + r * w;
+      p.kmax = std::max(p.kmax, fwd ? S.width(s) : S.width(s) + S.nrows(s));
     }
     p.n = tasks.size() - p.off64;
     p.off32 = tasks.size();
@@ -136,6 +141,8 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   int64_t *dsrc = dev_upload(h, src);
   auto mk = [&](const Pending &p) {
     SolvePlan::Launch L;
+    L.nnz = p.nnz;
+    L.kmax = p.kmax;
     L.n_tasks = (int32_t)p.n;
     L.n_tiles = p.tiles64;
     L.n_tiles32 = p.tiles32;
@@ -158,6 +165,10 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.f.uoff = dev_upload(h, uoff);
   D.plan.n_heights = H;
   D.plan.tile_rows = h->opt.gemm_rows;
+  D.plan.splitk = h->opt.gemm_splitk;
+  D.plan.prof = nullptr;
+  D.plan.splitk_ws = nullptr;
+  D.plan.splitk_bytes = 0;
   D.plan.h_tgt_off = D.h_tgt_off.data();
   D.plan.tgt = dtg;
   D.plan.src = dsrc;
@@ -165,12 +176,25 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.plan.bwd = D.bwd.data();
 }
 
+// Upload P_s of every supernode; with `transpose`, also P_s^T (w x m,
+// column-major), which the backward solve then streams with unit stride.
 template <typename T, typename TH>
-void upload_factor(stmg_handle *h, const HostFactor<TH> &F, DevFactor &D) {
+void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, DevFactor &D, bool transpose) {
   static_assert(sizeof(T) == sizeof(TH), "scalar size mismatch");
   D.f.panel = dev_upload(h, reinterpret_cast<const T *>(F.panel.data()), F.panel.size());
   D.f.panel_off = dev_upload(h, F.panel_off);
   D.factor_bytes = (int64_t)(F.panel.size() * sizeof(T));
+  D.f.panel_t = nullptr;
+  if (transpose) {
+    std::vector<TH> Pt(F.panel.size());
+    for (int32_t s = 0; s < S.ns; ++s) {
+      const int64_t w = S.width(s), m = w + S.nrows(s), o = F.panel_off[s];
+      for (int64_t k = 0; k < w; ++k)
+        for (int64_t i = 0; i < m; ++i) Pt[o + k + i * w] = F.panel[o + i + k * m];
+    }
+    D.f.panel_t = dev_upload(h, reinterpret_cast<const T *>(Pt.data()), Pt.size());
+    D.factor_bytes *= 2;
+  }
   h->factor_bytes += D.factor_bytes;
 }
 
@@ -242,7 +266,7 @@ void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
   }
   if (has_nodal) {
     build_plan(h, md.sym_v, md.nodal);
-    upload_factor<double>(h, *md.nodal_host, md.nodal);
+    upload_factor<double>(h, md.sym_v, *md.nodal_host, md.nodal, true);
     if (!h->opt.host_only) md.nodal_host.reset();
   }
 }
@@ -277,6 +301,21 @@ void setup_transfer(stmg_handle *h, MeshData &fine, MeshData &coarse) {
   coarse.d_pt_val = dev_upload(h, Pt.val);
 }
 
+// Store P^T too when the whole hierarchy's factors fit twice in a budget
+// (factor_transpose = -1), always (1) or never (0); levels with few slabs
+// (solves that only stream the factor) get it under the automatic rule even
+// when the budget is exceeded.
+bool slab_transpose(const stmg_handle *h, const LevelData &L) {
+  if (h->opt.factor_transpose == 0) return false;
+  if (h->opt.factor_transpose == 1) return true;
+  int64_t total = 0;
+  for (const auto &l : h->levels) {
+    const MeshData &md = h->meshes[h->mesh_slot[l.mesh]];
+    total += md.sym_e.panel_entries * (h->pt == 1 ? 16 : 8);
+  }
+  return total <= (int64_t)40 << 30 || L.N <= 16;
+}
+
 void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   const SpaceLevel &S = *md.S;
@@ -290,7 +329,7 @@ void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
     if (device) {
       L.slab.is_complex = true;
       build_plan(h, md.sym_e, L.slab);
-      upload_factor<cd>(h, *L.slab_host_c, L.slab);
+      upload_factor<cd>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L));
       if (!h->opt.host_only) L.slab_host_c.reset();
     }
   } else {
@@ -300,7 +339,7 @@ void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
     factor_host<double>(md.sym_e, S.M, v, *L.slab_host_r);
     if (device) {
       build_plan(h, md.sym_e, L.slab);
-      upload_factor<double>(h, *L.slab_host_r, L.slab);
+      upload_factor<double>(h, md.sym_e, *L.slab_host_r, L.slab, slab_transpose(h, L));
       if (!h->opt.host_only) L.slab_host_r.reset();
     }
   }
@@ -348,6 +387,8 @@ struct Ops {
     a.out = out;
     a.partial = partial;
     a.mode = mode;
+    a.nnz = md.Mp.nnz();
+    a.prof = h->prof_state.on ? &h->prof : nullptr;
     launch_residual(a, s);
   }
 
@@ -443,6 +484,12 @@ struct Ops {
 
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
+void set_profiler(stmg_handle *h, bool on) {
+  Profiler *p = on ? &h->prof : nullptr;
+  for (auto &L : h->levels) L.slab.plan.prof = p;
+  for (auto &m : h->meshes) m.nodal.plan.prof = p;
+}
+
 // Setup progress on stderr when STMG_VERBOSE is set (long factorisations).
 bool verbose() {
   static const bool v = getenv("STMG_VERBOSE") && getenv("STMG_VERBOSE")[0] != '0';
@@ -465,10 +512,72 @@ double *tmp_buf(stmg_handle *h, int i) {
 
 void destroy_handle(stmg_handle *h) {
   if (!h) return;
+  if (!h->prof_state.recs.empty() || !h->prof_state.pool.empty()) (void)hipStreamSynchronize(h->stream);
+  for (auto &r : h->prof_state.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : h->prof_state.pool) (void)hipEventDestroy(e);
   for (auto &b : h->bufs) (void)hipFree(b.p);
   delete h;
 }
 
+}  // namespace
+
+namespace stmg {
+
+hipEvent_t ProfState::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hip_check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void Profiler::begin(hipStream_t s) {
+  auto *st = static_cast<ProfState *>(impl);
+  st->pending = st->get();
+  hip_check(hipEventRecord(st->pending, s), "hipEventRecord");
+}
+
+void Profiler::end(hipStream_t s, const char *kernel, double flops, double bytes) {
+  auto *st = static_cast<ProfState *>(impl);
+  hipEvent_t b = st->get();
+  hip_check(hipEventRecord(b, s), "hipEventRecord");
+  st->recs.push_back({st->pending, b, kernel, flops, bytes});
+  st->pending = nullptr;
+}
+
+}  // namespace stmg
+
+namespace {
+// Resolve recorded events into per-kernel sums (synchronises).
+void prof_collect(stmg_handle *h) {
+  ProfState &st = h->prof_state;
+  if (st.recs.empty()) return;
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  for (auto &r : st.recs) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    ProfState::Agg *g = nullptr;
+    for (auto &x : st.agg)
+      if (x.kernel == r.kernel) g = &x;
+    if (!g) {
+      st.agg.push_back({r.kernel});
+      g = &st.agg.back();
+    }
+    g->launches++;
+    g->ms += ms;
+    g->flops += r.flops;
+    g->bytes += r.bytes;
+    st.pool.push_back(r.a);
+    st.pool.push_back(r.b);
+  }
+  st.recs.clear();
+}
 }  // namespace
 
 // =================================================================== ABI
@@ -503,6 +612,8 @@ void stmg_default_options(stmg_options *o) {
   o->factor_on_device = 0;
   o->leaf_size = 8;
   o->gemm_rows = 0;
+  o->factor_transpose = -1;
+  o->gemm_splitk = 0;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -579,6 +690,17 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
                 L.N, L.tau, L.lambda, wall_time() - t0);
     }
     if (device) {
+      // split-K partial sums of the backward solves, shared by all factors
+      const int64_t ws_bytes = (int64_t)256 << 20;
+      void *ws = dev_alloc<char>(h, (size_t)ws_bytes);
+      for (auto &L : h->levels) {
+        L.slab.plan.splitk_ws = ws;
+        L.slab.plan.splitk_bytes = ws_bytes;
+      }
+      for (auto &m : h->meshes) {
+        m.nodal.plan.splitk_ws = ws;
+        m.nodal.plan.splitk_bytes = ws_bytes;
+      }
       const LevelData &L = h->levels[0];
       h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L.N * h->q, h->q) + 4096;
       h->d_partial = dev_alloc<double>(h, h->n_partial);
@@ -868,6 +990,43 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
     if (row_ptr) std::copy(A->ptr.begin(), A->ptr.end(), row_ptr);
     if (col) std::copy(A->col.begin(), A->col.end(), col);
     if (val) std::copy(A->val.begin(), A->val.end(), val);
+  });
+}
+
+int stmg_profile(stmg_handle *h, int32_t enable) {
+  return guard([&] {
+    require_device(h);
+    prof_collect(h);
+    h->prof.impl = &h->prof_state;
+    h->prof_state.agg.clear();
+    h->prof_state.on = enable != 0;
+    set_profiler(h, h->prof_state.on);
+  });
+}
+
+int stmg_profile_count(stmg_handle *h, int32_t *n_kernels) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(n_kernels, STMG_EINVAL, "null argument");
+    prof_collect(h);
+    *n_kernels = (int32_t)h->prof_state.agg.size();
+  });
+}
+
+int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
+                     double *total_ms, double *flops, double *bytes) {
+  return guard([&] {
+    require_device(h);
+    prof_collect(h);
+    STMG_REQUIRE(i >= 0 && i < (int32_t)h->prof_state.agg.size(), STMG_EINVAL, "kernel index out of range");
+    const auto &g = h->prof_state.agg[i];
+    if (name && name_len > 0) {
+      snprintf(name, (size_t)name_len, "%s", g.kernel.c_str());
+    }
+    if (launches) *launches = g.launches;
+    if (total_ms) *total_ms = g.ms;
+    if (flops) *flops = g.flops;
+    if (bytes) *bytes = g.bytes;
   });
 }
 

@@ -72,6 +72,26 @@ struct LevelData {
   double *g = nullptr, *zn = nullptr, *un = nullptr;
 };
 
+// Event-pair timing of individual launches (see Profiler).
+struct ProfRecord {
+  hipEvent_t a, b;
+  std::string kernel;
+  double flops, bytes;
+};
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfRecord> recs;
+  hipEvent_t pending = nullptr;
+  struct Agg {
+    std::string kernel;
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::vector<Agg> agg;
+  hipEvent_t get();
+};
+
 }  // namespace stmg
 
 struct stmg_handle {
@@ -91,6 +111,8 @@ struct stmg_handle {
   double bnorm = 0.0;
   std::vector<double> history;
   double setup_s = 0.0, solve_s = 0.0;
+  stmg::ProfState prof_state;
+  stmg::Profiler prof;
   int32_t cycles = 0;
   double rel_res = 0.0;
 };

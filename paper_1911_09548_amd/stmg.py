@@ -45,7 +45,8 @@ class Options(C.Structure):
                 ("allow_space_coarsening", C.c_int32), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("host_only", C.c_int32), ("factor_on_device", C.c_int32),
-                ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32)]
+                ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32), ("factor_transpose", C.c_int32),
+                ("gemm_splitk", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -100,9 +101,13 @@ def lib():
         L.stmg_export_matrix.argtypes = [vp, ip, ip, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), vp, vp, vp]
         L.stmg_export_factor.argtypes = [vp, ip, ip] + [vp] * 11
+        L.stmg_profile.argtypes = [vp, ip]
+        L.stmg_profile_count.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_residual", "stmg_level_apply",
-                     "stmg_export_matrix", "stmg_export_factor"):
+                     "stmg_export_matrix", "stmg_export_factor", "stmg_profile", "stmg_profile_count",
+                     "stmg_profile_get"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -213,6 +218,23 @@ class Solver:
                                         C.c_void_p(ptr.ctypes.data), C.c_void_p(col.ctypes.data),
                                         C.c_void_p(val.ctypes.data)))
         return sp.csr_matrix((val, col, ptr), shape=(nr.value, ncl.value))
+
+    def profile(self, enable=True):
+        _check(lib().stmg_profile(self._h, 1 if enable else 0))
+
+    def profile_report(self):
+        """Per-kernel launch statistics gathered since profile(True)."""
+        n = C.c_int32()
+        _check(lib().stmg_profile_count(self._h, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            name = C.create_string_buffer(128)
+            la, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            _check(lib().stmg_profile_get(self._h, i, name, 128, C.byref(la), C.byref(ms), C.byref(fl),
+                                          C.byref(by)))
+            out.append(dict(kernel=name.value.decode(), launches=la.value, ms=ms.value, flops=fl.value,
+                            bytes=by.value))
+        return sorted(out, key=lambda d: -d["ms"])
 
     def export_factor(self, level, which):
         """Host copy of a factor (host_only handles): dict of numpy arrays."""

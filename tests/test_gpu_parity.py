@@ -69,9 +69,14 @@ CASES = {
     # forced 64-row GEMM tiles (the per-launch choice picks 32 rows on small meshes)
     "block_n8_N64_p1_rows64": lambda: inputs.config_block_random(n=8, Nt=64, pt=1, seed=8, block_hexes=4),
     "block_n8_N16_p0_rows64": lambda: inputs.config_block_random(n=8, Nt=16, pt=0, seed=9, block_hexes=4),
+    # backward read from P (no stored transpose) and forced split-K backward
+    "block_n8_N32_p1_noT_split3": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=12, block_hexes=4),
+    "unit_n4_N16_p0_split2": lambda: inputs.config_unit_manufactured(4, 16, 0),
 }
 OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
-        "block_n8_N32_p1": dict(gemm_rows=32)}
+        "block_n8_N32_p1": dict(gemm_rows=32),
+        "block_n8_N32_p1_noT_split3": dict(factor_transpose=0, gemm_splitk=3),
+        "unit_n4_N16_p0_split2": dict(gemm_splitk=2)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
