@@ -78,51 +78,26 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
 #pragma unroll
   for (int j = 0; j < C; ++j) am[j] = ak[j] = 0.0;
   if (active && a.x) {
-    // four nonzeros per step: their column indices, values and x rows are
-    // all requested before any is used, keeping 4*C loads in flight per lane
     const int64_t k1 = a.ptr[row + 1];
-    int64_t k = a.ptr[row];
-    for (; k + 4 <= k1; k += 4) {
-      int c[4];
-      double mv[4], kv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        c[u] = a.col[k + u];
-        mv[u] = a.mval[k + u];
-        kv[u] = a.kval[k + u];
-      }
-      double xv[4][C];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double *xr = a.x + (int64_t)c[u] * W + li * C;
-        if constexpr (C % 2 == 0) {
-#pragma unroll
-          for (int j = 0; j < C; j += 2) {
-            const double2 v = *reinterpret_cast<const double2 *>(xr + j);
-            xv[u][j] = v.x;
-            xv[u][j + 1] = v.y;
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < C; ++j) xv[u][j] = xr[j];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-          am[j] += mv[u] * xv[u][j];
-          ak[j] += kv[u] * xv[u][j];
-        }
-    }
-    for (; k < k1; ++k) {
+    for (int64_t k = a.ptr[row]; k < k1; ++k) {
       const int c = a.col[k];
       const double mv = a.mval[k], kv = a.kval[k];
       const double *xr = a.x + (int64_t)c * W + li * C;
+      if constexpr (C % 2 == 0) {
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        am[j] += mv * xr[j];
-        ak[j] += kv * xr[j];
+        for (int j = 0; j < C; j += 2) {
+          const double2 v = *reinterpret_cast<const double2 *>(xr + j);
+          am[j] += mv * v.x;
+          am[j + 1] += mv * v.y;
+          ak[j] += kv * v.x;
+          ak[j + 1] += kv * v.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          am[j] += mv * xr[j];
+          ak[j] += kv * xr[j];
+        }
       }
     }
   }
