@@ -55,6 +55,17 @@ inline int lane_chunk(int W, int q) {
 
 }  // namespace
 
+template <typename R>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
 // ---------------------------------------------------------------- residual
 // r_n = b_n - (K_t (x) M + M_t (x) K) x_n + (N_t (x) M) x_{n-1}
 // q = 1: r = b - M(x_n - x_{n-1}) - tau K x_n
@@ -63,9 +74,11 @@ inline int lane_chunk(int W, int q) {
 //   r1 = b1 + Mx0 - Mx1 - E_{n-1} - (tau/3) K x1
 // Slab-solve right-hand side (mode 1), q = 2: w = (1/2 + i sqrt2/4) r0 - (3 i sqrt2/4) r1
 // stored as (re, im) in the two slots of slab n; q = 1: w = r.
-template <int C, int Q>
-__global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
+// The optional norm (sum of squares of r) is accumulated in FP64.
+template <typename R, int C, int Q>
+__global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a) {
   constexpr int S = C / Q;
+  using V2 = typename Vec2<R>::type;
   const int W = a.N * Q;
   const int LPR = W / C;
   const int rpw = 64 / LPR;
@@ -74,19 +87,19 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int row = (blk * (BLOCK / 64) + wave) * rpw + sub;
   const bool active = row < a.n_rows;
-  double am[C], ak[C];
+  R am[C], ak[C];
 #pragma unroll
-  for (int j = 0; j < C; ++j) am[j] = ak[j] = 0.0;
+  for (int j = 0; j < C; ++j) am[j] = ak[j] = 0;
   if (active && a.x) {
     const int64_t k1 = a.ptr[row + 1];
     for (int64_t k = a.ptr[row]; k < k1; ++k) {
       const int c = a.col[k];
-      const double mv = a.mval[k], kv = a.kval[k];
-      const double *xr = a.x + (int64_t)c * W + li * C;
+      const R mv = a.mval[k], kv = a.kval[k];
+      const R *xr = a.x + (int64_t)c * W + li * C;
       if constexpr (C % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < C; j += 2) {
-          const double2 v = *reinterpret_cast<const double2 *>(xr + j);
+          const V2 v = *reinterpret_cast<const V2 *>(xr + j);
           am[j] += mv * v.x;
           am[j + 1] += mv * v.y;
           ak[j] += kv * v.x;
@@ -102,34 +115,35 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgs a) {
     }
   }
   // end value of the lane's last slab, passed to the next lane
-  double elast = 0.0;
+  R elast = 0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) elast += am[(S - 1) * Q + k];
-  double eprev = __shfl_up(elast, 1, LPR);
-  if (li == 0) eprev = 0.0;
+  R eprev = __shfl_up(elast, 1, LPR);
+  if (li == 0) eprev = 0;
   double ss = 0.0;
+  const R tau = (R)a.tau;
   if (active) {
     const int64_t base = (int64_t)row * W + li * C;
-    double bv[C], out[C];
+    R bv[C], out[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) bv[j] = a.b[base + j];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if constexpr (Q == 1) {
-        const double r = bv[s] - am[s] + eprev - a.tau * ak[s];
+        const R r = bv[s] - am[s] + eprev - tau * ak[s];
         eprev = am[s];
         out[s] = r;
-        ss += r * r;
+        ss += (double)r * r;
       } else {
-        const double m0 = am[2 * s], m1 = am[2 * s + 1];
-        const double r0 = bv[2 * s] - (m0 + m1) + eprev - a.tau * ak[2 * s];
-        const double r1 = bv[2 * s + 1] + m0 - m1 - eprev - (a.tau / 3.0) * ak[2 * s + 1];
+        const R m0 = am[2 * s], m1 = am[2 * s + 1];
+        const R r0 = bv[2 * s] - (m0 + m1) + eprev - tau * ak[2 * s];
+        const R r1 = bv[2 * s + 1] + m0 - m1 - eprev - (tau / (R)3) * ak[2 * s + 1];
         eprev = m0 + m1;
-        ss += r0 * r0 + r1 * r1;
+        ss += (double)r0 * r0 + (double)r1 * r1;
         if (a.mode == RES_OUT_SLABRHS) {
-          const double s2 = 1.4142135623730951;
-          out[2 * s] = 0.5 * r0;
-          out[2 * s + 1] = 0.25 * s2 * r0 - 0.75 * s2 * r1;
+          const R s2 = (R)1.4142135623730951;
+          out[2 * s] = (R)0.5 * r0;
+          out[2 * s + 1] = (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1;
         } else {
           out[2 * s] = r0;
           out[2 * s + 1] = r1;
@@ -152,36 +166,13 @@ int residual_blocks(int32_t n_rows, int32_t W, int32_t q) {
   return (n_rows + rows_per_block - 1) / rows_per_block;
 }
 
-template <int C, int Q>
-static void launch_res_cq(const ResidualArgs &a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual<C, Q>), dim3(nblocks), dim3(BLOCK), 0, s, a);
-}
-
-void launch_residual_inner(const ResidualArgs &a, int nb, int C, hipStream_t s);
-
-void launch_residual(const ResidualArgs &a, hipStream_t s) {
-  const int W = a.N * a.q;
-  const int C = lane_chunk(W, a.q);
-  const int nb = residual_blocks(a.n_rows, W, a.q);
-  if (nb == 0) return;
-  if (a.prof) {
-    // algorithmic traffic: x, b read once, out written once, the pattern and
-    // both value arrays read once; 4 flops per nonzero and column (two FMAs)
-    char name[64];
-    snprintf(name, sizeof name, "k_residual<%d,%d>", C, a.q);
-    a.prof->begin(s);
-    launch_residual_inner(a, nb, C, s);
-    const double rows = a.n_rows, cols = W;
-    const double nnz = (double)a.nnz;
-    a.prof->end(s, name, 4.0 * nnz * cols, 8.0 * rows * cols * (a.x ? 3.0 : 2.0) + 20.0 * nnz + 8.0 * (rows + 1));
-    return;
+template <typename R>
+static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, int C, hipStream_t s) {
+#define RES_CASE(CC, QQ)                                                                    \
+  if (C == CC && a.q == QQ) {                                                               \
+    hipLaunchKernelGGL((k_residual<R, CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, a);            \
+    return;                                                                                 \
   }
-  launch_residual_inner(a, nb, C, s);
-}
-
-void launch_residual_inner(const ResidualArgs &a, int nb, int C, hipStream_t s) {
-#define RES_CASE(CC, QQ) \
-  if (C == CC && a.q == QQ) return launch_res_cq<CC, QQ>(a, nb, s);
   RES_CASE(1, 1)
   RES_CASE(2, 1)
   RES_CASE(4, 1)
@@ -194,6 +185,28 @@ void launch_residual_inner(const ResidualArgs &a, int nb, int C, hipStream_t s) 
 #undef RES_CASE
   fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", a.N * a.q, a.q);
 }
+
+template <typename R>
+void launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
+  const int W = a.N * a.q;
+  const int C = lane_chunk(W, a.q);
+  const int nb = residual_blocks(a.n_rows, W, a.q);
+  if (nb == 0) return;
+  if (a.prof) {
+    // algorithmic traffic: x, b read once, out written once, the pattern and
+    // both value arrays read once; 4 flops per nonzero and column (two FMAs)
+    char name[64];
+    snprintf(name, sizeof name, "k_residual<%s,%d,%d>", sizeof(R) == 8 ? "double" : "float", C, a.q);
+    a.prof->begin(s);
+    launch_residual_inner(a, nb, C, s);
+    const double rows = a.n_rows, cols = W, nnz = (double)a.nnz, sz = sizeof(R);
+    a.prof->end(s, name, 4.0 * nnz * cols, sz * rows * cols * (a.x ? 3.0 : 2.0) + (4.0 + 2.0 * sz) * nnz + 8.0 * (rows + 1));
+    return;
+  }
+  launch_residual_inner(a, nb, C, s);
+}
+template void launch_residual<double>(const ResidualArgsT<double> &, hipStream_t);
+template void launch_residual<float>(const ResidualArgsT<float> &, hipStream_t);
 
 // --------------------------------------------------------------- reductions
 __global__ __launch_bounds__(BLOCK) void k_sum(const double *p, int32_t n, double *out) {
@@ -223,13 +236,14 @@ int launch_sumsq(const double *v, int64_t n, double *partial, hipStream_t s) {
 }
 
 // ---------------------------------------------------------- Jacobi update
-__global__ __launch_bounds__(BLOCK) void k_slab_update(int64_t n, int32_t q, double omega,
-                                                       const double *z, double *x, int assign) {
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_slab_update(int64_t n, int32_t q, R omega, const R *z, R *x,
+                                                       int assign) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (row, slab)
   if (i >= n) return;
   if (q == 2) {
-    const double zr = z[2 * i], zi = z[2 * i + 1];
-    const double d0 = omega * 2.0 * zr, d1 = omega * 2.0 * (zr - 1.4142135623730951 * zi);
+    const R zr = z[2 * i], zi = z[2 * i + 1];
+    const R d0 = omega * (R)2 * zr, d1 = omega * (R)2 * (zr - (R)1.4142135623730951 * zi);
     if (assign) {
       x[2 * i] = d0;
       x[2 * i + 1] = d1;
@@ -238,59 +252,63 @@ __global__ __launch_bounds__(BLOCK) void k_slab_update(int64_t n, int32_t q, dou
       x[2 * i + 1] += d1;
     }
   } else {
-    const double d = omega * z[i];
+    const R d = omega * z[i];
     x[i] = assign ? d : x[i] + d;
   }
 }
 
-void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const double *z,
-                        double *x, int assign, hipStream_t s) {
+template <typename R>
+void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const R *z, R *x, int assign,
+                        hipStream_t s) {
   const int64_t n = (int64_t)n_rows * N;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_slab_update, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q,
-                     omega, z, x, assign);
+  hipLaunchKernelGGL(k_slab_update<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q,
+                     (R)omega, z, x, assign);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_slab_rhs(int64_t n, int32_t q, const double *r, double *w) {
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_slab_rhs(int64_t n, int32_t q, const R *r, R *w) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   if (q == 2) {
-    const double s2 = 1.4142135623730951;
-    const double r0 = r[2 * i], r1 = r[2 * i + 1];
-    w[2 * i] = 0.5 * r0;
-    w[2 * i + 1] = 0.25 * s2 * r0 - 0.75 * s2 * r1;
+    const R s2 = (R)1.4142135623730951;
+    const R r0 = r[2 * i], r1 = r[2 * i + 1];
+    w[2 * i] = (R)0.5 * r0;
+    w[2 * i + 1] = (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1;
   } else {
     w[i] = r[i];
   }
 }
 
-void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const double *r, double *w, hipStream_t s) {
+template <typename R>
+void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const R *r, R *w, hipStream_t s) {
   const int64_t n = (int64_t)n_rows * N;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_slab_rhs, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q, r, w);
+  hipLaunchKernelGGL(k_slab_rhs<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, q, r, w);
 }
 
 // ------------------------------------------------------- nodal correction
 // g[v][c] = sum over edges e at v of sign(e, v) r[e][c]  (G^T, entries +-1)
+template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_gradT(int32_t n_v, int32_t W, const int64_t *ptr,
-                                                 const int32_t *edge, const int8_t *sign,
-                                                 const double *r, double *g) {
+                                                 const int32_t *edge, const int8_t *sign, const R *r, R *g) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i >= (int64_t)n_v * W) return;
   const int32_t v = (int32_t)(i / W), c = (int32_t)(i % W);
-  double acc = 0.0;
+  R acc = 0;
   for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
-    const double t = r[(int64_t)edge[k] * W + c];
+    const R t = r[(int64_t)edge[k] * W + c];
     acc += sign[k] > 0 ? t : -t;
   }
   g[i] = acc;
 }
 
+template <typename R>
 void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edge, const int8_t *sign,
-                  const double *r, double *g, hipStream_t s) {
+                  const R *r, R *g, hipStream_t s) {
   const int64_t n = (int64_t)n_v * W;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gradT, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_v, W, ptr,
+  hipLaunchKernelGGL(k_gradT<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_v, W, ptr,
                      edge, sign, r, g);
 }
 
@@ -298,8 +316,8 @@ void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edg
 // -N_t below), per vertex row, in place:
 //   q = 1: y_n = sum_{m <= n} g_m (the running sum of eq. (8));
 //   q = 2: e_n = sum_{m <= n} g_{m,0}; y_{n,0} = e_{n-1} + (g0 - g1)/2, y_{n,1} = (g0 + g1)/2.
-template <int C, int Q>
-__global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, double *g) {
+template <typename R, int C, int Q>
+__global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, R *g) {
   constexpr int S = C / Q;
   const int W = N * Q;
   const int LPR = W / C;
@@ -308,8 +326,8 @@ __global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, dou
   const int li = lane % LPR, sub = lane / LPR;
   const int row = (blockIdx.x * (BLOCK / 64) + wave) * rpw + sub;
   const bool active = row < n_v;
-  double v[C];
-  double local = 0.0;
+  R v[C];
+  R local = 0;
   if (active) {
 #pragma unroll
     for (int j = 0; j < C; ++j) v[j] = g[(int64_t)row * W + li * C + j];
@@ -317,15 +335,15 @@ __global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, dou
     for (int s = 0; s < S; ++s) local += v[s * Q];
   } else {
 #pragma unroll
-    for (int j = 0; j < C; ++j) v[j] = 0.0;
+    for (int j = 0; j < C; ++j) v[j] = 0;
   }
   // exclusive scan of `local` over the lanes of this row (Hillis-Steele)
-  double incl = local;
+  R incl = local;
   for (int o = 1; o < LPR; o <<= 1) {
-    const double t = __shfl_up(incl, o, LPR);
+    const R t = __shfl_up(incl, o, LPR);
     if (li >= o) incl += t;
   }
-  double e = incl - local;  // sum over earlier lanes
+  R e = incl - local;  // sum over earlier lanes
   if (active) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -333,9 +351,9 @@ __global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, dou
         e += v[s];
         v[s] = e;
       } else {
-        const double g0 = v[2 * s], g1 = v[2 * s + 1];
-        v[2 * s] = e + 0.5 * (g0 - g1);
-        v[2 * s + 1] = 0.5 * (g0 + g1);
+        const R g0 = v[2 * s], g1 = v[2 * s + 1];
+        v[2 * s] = e + (R)0.5 * (g0 - g1);
+        v[2 * s + 1] = (R)0.5 * (g0 + g1);
         e += g0;
       }
     }
@@ -344,7 +362,8 @@ __global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, dou
   }
 }
 
-void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t s) {
+template <typename R>
+void launch_time_scan(int32_t n_v, int32_t N, int32_t q, R *g, hipStream_t s) {
   const int W = N * q;
   const int C = lane_chunk(W, q);
   const int LPR = W / C;
@@ -353,7 +372,7 @@ void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t 
   if (nb == 0) return;
 #define SCAN_CASE(CC, QQ)                                                                      \
   if (C == CC && q == QQ) {                                                                    \
-    hipLaunchKernelGGL((k_time_scan<CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, n_v, N, g);         \
+    hipLaunchKernelGGL((k_time_scan<R, CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, n_v, N, g);      \
     return;                                                                                    \
   }
   SCAN_CASE(1, 1)
@@ -370,23 +389,25 @@ void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t 
 }
 
 // x[e][c] += y[head(e)][c] - y[tail(e)][c]  (G, boundary vertices dropped)
+template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_grad_add(int32_t n_e, int32_t W, const int32_t *head,
-                                                    const int32_t *tail, const double *y, double *x) {
+                                                    const int32_t *tail, const R *y, R *x) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i >= (int64_t)n_e * W) return;
   const int32_t e = (int32_t)(i / W), c = (int32_t)(i % W);
-  double d = 0.0;
+  R d = 0;
   const int32_t h = head[e], t = tail[e];
   if (h >= 0) d += y[(int64_t)h * W + c];
   if (t >= 0) d -= y[(int64_t)t * W + c];
   x[i] += d;
 }
 
-void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const double *y,
-                     double *x, hipStream_t s) {
+template <typename R>
+void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const R *y, R *x,
+                     hipStream_t s) {
   const int64_t n = (int64_t)n_e * W;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_grad_add, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_e, W,
+  hipLaunchKernelGGL(k_grad_add<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_e, W,
                      head, tail, y, x);
 }
 
@@ -394,30 +415,32 @@ void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t 
 // Time prolongation of one coarse slab (coefficients c0, c1) to its halves:
 //   first half (c0 - c1/2, c1/2), second half (c0 + c1/2, c1/2); degree 0: (c, c).
 // Restriction is its transpose.
-__device__ inline void time_restrict(int q, const double *rf, double *out) {
+template <typename R>
+__device__ inline void time_restrict(int q, const R *rf, R *out) {
   // rf: [2][q] fine values of the two halves
   if (q == 1) {
     out[0] = rf[0] + rf[1];
   } else {
     out[0] = rf[0] + rf[2];
-    out[1] = 0.5 * (-rf[0] + rf[1] + rf[2] + rf[3]);
+    out[1] = (R)0.5 * (-rf[0] + rf[1] + rf[2] + rf[3]);
   }
 }
 
+template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr,
-                                                    const int32_t *col, const double *val,
-                                                    const double *rf, double *rc) {
+                                                    const int32_t *col, const double *val, const R *rf,
+                                                    R *rc) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (coarse row, coarse slab)
   if (i >= (int64_t)n_c * Nc) return;
   const int32_t row = (int32_t)(i / Nc), m = (int32_t)(i % Nc);
   const int Wf = 2 * Nc * q;
-  double acc[2] = {0.0, 0.0};
+  R acc[2] = {0, 0};
   if (ptr) {
     for (int64_t k = ptr[row]; k < ptr[row + 1]; ++k) {
-      double t[2];
+      R t[2];
       time_restrict(q, rf + (int64_t)col[k] * Wf + 2 * m * q, t);
-      acc[0] += val[k] * t[0];
-      if (q == 2) acc[1] += val[k] * t[1];
+      acc[0] += (R)val[k] * t[0];
+      if (q == 2) acc[1] += (R)val[k] * t[1];
     }
   } else {
     time_restrict(q, rf + (int64_t)row * Wf + 2 * m * q, acc);
@@ -426,51 +449,53 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(int32_t n_c, int32_t Nc, int
   if (q == 2) rc[i * q + 1] = acc[1];
 }
 
+template <typename R>
 void launch_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
-                     const double *val, const double *r_f, double *r_c, hipStream_t s) {
+                     const double *val, const R *r_f, R *r_c, hipStream_t s) {
   const int64_t n = (int64_t)n_c * Nc;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_c, Nc, q,
+  hipLaunchKernelGGL(k_restrict<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_c, Nc, q,
                      ptr, col, val, r_f, r_c);
 }
 
+template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_prolong_add(int32_t n_f, int32_t Nc, int32_t q,
                                                        const int64_t *ptr, const int32_t *col,
-                                                       const double *val, const double *ec,
-                                                       double *xf) {
+                                                       const double *val, const R *ec, R *xf) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // (fine row, coarse slab)
   if (i >= (int64_t)n_f * Nc) return;
   const int32_t row = (int32_t)(i / Nc), m = (int32_t)(i % Nc);
   const int Wc = Nc * q;
-  double c[2] = {0.0, 0.0};
+  R c[2] = {0, 0};
   if (ptr) {
     for (int64_t k = ptr[row]; k < ptr[row + 1]; ++k) {
-      const double *e = ec + (int64_t)col[k] * Wc + m * q;
-      c[0] += val[k] * e[0];
-      if (q == 2) c[1] += val[k] * e[1];
+      const R *e = ec + (int64_t)col[k] * Wc + m * q;
+      c[0] += (R)val[k] * e[0];
+      if (q == 2) c[1] += (R)val[k] * e[1];
     }
   } else {
-    const double *e = ec + (int64_t)row * Wc + m * q;
+    const R *e = ec + (int64_t)row * Wc + m * q;
     c[0] = e[0];
     if (q == 2) c[1] = e[1];
   }
-  double *x = xf + (int64_t)row * (2 * Wc) + 2 * m * q;
+  R *x = xf + (int64_t)row * (2 * Wc) + 2 * m * q;
   if (q == 1) {
     x[0] += c[0];
     x[1] += c[0];
   } else {
-    x[0] += c[0] - 0.5 * c[1];
-    x[1] += 0.5 * c[1];
-    x[2] += c[0] + 0.5 * c[1];
-    x[3] += 0.5 * c[1];
+    x[0] += c[0] - (R)0.5 * c[1];
+    x[1] += (R)0.5 * c[1];
+    x[2] += c[0] + (R)0.5 * c[1];
+    x[3] += (R)0.5 * c[1];
   }
 }
 
+template <typename R>
 void launch_prolong_add(int32_t n_f, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
-                        const double *val, const double *e_c, double *x_f, hipStream_t s) {
+                        const double *val, const R *e_c, R *x_f, hipStream_t s) {
   const int64_t n = (int64_t)n_f * Nc;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_prolong_add, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_f, Nc,
+  hipLaunchKernelGGL(k_prolong_add<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_f, Nc,
                      q, ptr, col, val, e_c, x_f);
 }
 
@@ -530,15 +555,17 @@ void launch_fold_initial(int32_t n_rows, int32_t N, int32_t q, const int64_t *pt
                      q, ptr, col, mval, map, u0_abi, b);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_fill(double *p, int64_t n, double v) {
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_fill(R *p, int64_t n, R v) {
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+template <typename R>
+void launch_fill(R *p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
-  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(BLOCK), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill<R>, dim3(nb), dim3(BLOCK), 0, s, p, n, (R)v);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_axpy(int64_t n, double a, const double *x, double *y) {
@@ -552,41 +579,133 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
   hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(BLOCK), 0, s, n, a, x, y);
 }
 
+// Precision conversions of the refinement loop: out = (float) in, and
+// y += (double) x.
+__global__ __launch_bounds__(BLOCK) void k_to_float(int64_t n, const double *in, float *out) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) out[i] = (float)in[i];
+}
+__global__ __launch_bounds__(BLOCK) void k_to_double(int64_t n, const float *in, double *out) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) out[i] = (double)in[i];
+}
+__global__ __launch_bounds__(BLOCK) void k_add_float(int64_t n, const float *x, double *y) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) y[i] += (double)x[i];
+}
+
+void launch_to_float(int64_t n, const double *in, float *out, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(BLOCK), 0, s, n, in, out);
+}
+void launch_to_double(int64_t n, const float *in, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_to_double, dim3(nb), dim3(BLOCK), 0, s, n, in, out);
+}
+void launch_add_float(int64_t n, const float *x, double *y, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_add_float, dim3(nb), dim3(BLOCK), 0, s, n, x, y);
+}
+
+#define VEC_INST(R)                                                                                         \
+  template void launch_slab_update<R>(int32_t, int32_t, int32_t, double, const R *, R *, int, hipStream_t); \
+  template void launch_slab_rhs<R>(int32_t, int32_t, int32_t, const R *, R *, hipStream_t);                \
+  template void launch_gradT<R>(int32_t, int32_t, const int64_t *, const int32_t *, const int8_t *,        \
+                                const R *, R *, hipStream_t);                                              \
+  template void launch_time_scan<R>(int32_t, int32_t, int32_t, R *, hipStream_t);                          \
+  template void launch_grad_add<R>(int32_t, int32_t, const int32_t *, const int32_t *, const R *, R *,     \
+                                   hipStream_t);                                                          \
+  template void launch_restrict<R>(int32_t, int32_t, int32_t, const int64_t *, const int32_t *,            \
+                                   const double *, const R *, R *, hipStream_t);                          \
+  template void launch_prolong_add<R>(int32_t, int32_t, int32_t, const int64_t *, const int32_t *,         \
+                                      const double *, const R *, R *, hipStream_t);                       \
+  template void launch_fill<R>(R *, int64_t, double, hipStream_t);
+VEC_INST(double)
+VEC_INST(float)
+#undef VEC_INST
+
 // ------------------------------------------------------ triangular solves
 // Each supernode s stores P_s = [inv(L_ss); -L_{R,s} inv(L_ss)] (m x w,
 // column-major). Per tree height, one batched launch does for every
 // supernode of that height
 //   forward:  [Z[C_s]; U_s] (+)= P_s X[C_s]          (U_s += : update rows)
 //   backward: X[C_s] = P_s^T [Z[C_s]; X[R_s]]
-// as a GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64; complex products as four
-// real MFMAs). Work items are (supernode, 64-row tile, column tile), the
+// as a GEMM on MFMA (v_mfma_f64_16x16x4f64 in FP64, v_mfma_f32_16x16x4f32
+// in FP32; complex products as three real MFMAs). Work items are (supernode, 64-row tile, column tile), the
 // column tile varying fastest so the tiles sharing a block of P_s run
 // together and read it through L2 once.
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Scalar traits: real type, MFMA accumulator, and the accumulator's lane
+// layout (16x16 block: lane l, register r holds column l % 16 of row
+// out_row(l, r); the FP64 and FP32 instructions differ here).
 template <typename T>
 struct Scalar;
 template <>
 struct Scalar<double> {
   static constexpr bool cpx = false;
+  using R = double;
+  using acc_t = v4d;
+  static constexpr const char *name = "double";
+  __device__ static int out_row(int lane, int r) { return 4 * r + lane / 16; }
 };
 template <>
 struct Scalar<cd> {
   static constexpr bool cpx = true;
+  using R = double;
+  using acc_t = v4d;
+  static constexpr const char *name = "cd";
+  __device__ static int out_row(int lane, int r) { return 4 * r + lane / 16; }
+};
+template <>
+struct Scalar<float> {
+  static constexpr bool cpx = false;
+  using R = float;
+  using acc_t = v4f;
+  static constexpr const char *name = "float";
+  __device__ static int out_row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+template <>
+struct Scalar<cf> {
+  static constexpr bool cpx = true;
+  using R = float;
+  using acc_t = v4f;
+  static constexpr const char *name = "cf";
+  __device__ static int out_row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-__device__ inline void split(double v, double &re, double &im) {
+__device__ inline v4d mfma_op(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma_op(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename R>
+__device__ inline void split(R v, R &re, R &im) {
   re = v;
-  im = 0.0;
+  im = 0;
 }
 __device__ inline void split(cd v, double &re, double &im) {
   re = v.re;
   im = v.im;
 }
-__device__ inline void make(double re, double, double &out) { out = re; }
+__device__ inline void split(cf v, float &re, float &im) {
+  re = v.re;
+  im = v.im;
+}
+template <typename R>
+__device__ inline void make(R re, R, R &out) {
+  out = re;
+}
 __device__ inline void make(double re, double im, cd &out) { out = {re, im}; }
+__device__ inline void make(float re, float im, cf &out) { out = {re, im}; }
 
 __device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
   int lo = 0, hi = n - 1;
@@ -607,21 +726,22 @@ __device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src,
                                                    int32_t nc, T *X, T *U) {
+  using R = typename Scalar<T>::R;
   const int64_t ti = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
   if (ti >= n_tgt) return;
   const int lane = threadIdx.x & 63;
   const AsmTarget t = tgt[ti];
   const int64_t s1 = tgt[ti + 1].src_begin;
   for (int c = lane; c < nc; c += 64) {
-    double ar = 0.0, ai = 0.0;
+    R ar = 0, ai = 0;
     for (int64_t k = t.src_begin; k < s1; ++k) {
-      double r, i;
+      R r, i;
       split(U[src[k] * nc + c], r, i);
       ar += r;
       ai += i;
     }
     if (t.dst >= 0) {
-      double r, i;
+      R r, i;
       split(X[t.dst * nc + c], r, i);
       make(r + ar, i + ai, X[t.dst * nc + c]);
     } else {
@@ -645,21 +765,23 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
                                                    int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
                                                    int32_t nsplit, int32_t kseg, T *ws) {
   constexpr bool CPX = Scalar<T>::cpx;
+  using R = typename Scalar<T>::R;
+  using ACC = typename Scalar<T>::acc_t;
   constexpr int NP = CPX ? 3 : 1;  // planes: re, im, re + im
   constexpr int KC = 16, LD = KC + 1;
   constexpr int WN = BN >= 32 ? 2 : 1, WM = 4 / WN;
   static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile shape");
   constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
   constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
-  __shared__ double As[NP][BM * LD];
-  __shared__ double Bs[NP][BN * LD];
+  __shared__ R As[NP][BM * LD];
+  __shared__ R Bs[NP][BN * LD];
   const int ct = blockIdx.x % ctiles, rs = blockIdx.x / ctiles;
   const int seg = rs % nsplit, rowtile = rs / nsplit;
   const int ti = find_task(tasks, n_tasks, rowtile);
   const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
   const T *P = reinterpret_cast<const T *>(DIR == 2 ? f.panel_t : f.panel) + f.panel_off[s];
-  const int32_t *R = f.rows + f.rptr[s];
+  const int32_t *Rrows = f.rows + f.rptr[s];
   const int i0 = rt * BM, j0 = ct * BN;
   const int rows = DIR == 0 ? m : w;
   const int kb0 = DIR == 0 ? 0 : i0;
@@ -669,7 +791,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave / WN) * (BM / WM), wc = (wave % WN) * (BN / WN);
 
-  double ra[AE][2], rb[BE][2];  // prefetch registers (re, im)
+  R ra[AE][2], rb[BE][2];  // prefetch registers (re, im)
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
@@ -683,7 +805,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
         i = e / KC;
       }
       const int gi = i0 + i, gk = k0 + k;
-      ra[q][0] = ra[q][1] = 0.0;
+      ra[q][0] = ra[q][1] = 0;
       if (gi < rows && gk < kend)
         split(DIR == 0 ? P[gi + (int64_t)gk * m] : (DIR == 1 ? P[gk + (int64_t)gi * m] : P[gi + (int64_t)gk * w]),
               ra[q][0], ra[q][1]);
@@ -693,13 +815,13 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       const int e = threadIdx.x + q * BLOCK;
       const int j = e % BN, k = e / BN;
       const int gk = k0 + k, gj = j0 + j;
-      rb[q][0] = rb[q][1] = 0.0;
+      rb[q][0] = rb[q][1] = 0;
       if (k < KC && gk < kend && gj < nc) {
         const T *row;
         if (DIR == 0)
           row = X + (int64_t)(c0 + gk) * nc;
         else
-          row = gk < w ? Z + (int64_t)(c0 + gk) * nc : X + (int64_t)R[gk - w] * nc;
+          row = gk < w ? Z + (int64_t)(c0 + gk) * nc : X + (int64_t)Rrows[gk - w] * nc;
         split(row[gj], rb[q][0], rb[q][1]);
       }
     }
@@ -729,13 +851,13 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
     }
   };
 
-  v4d acc[NP][MI][NI];
+  ACC acc[NP][MI][NI];
 #pragma unroll
   for (int c = 0; c < NP; ++c)
 #pragma unroll
     for (int a = 0; a < MI; ++a)
 #pragma unroll
-      for (int b = 0; b < NI; ++b) acc[c][a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < NI; ++b) acc[c][a][b] = ACC{0, 0, 0, 0};
 
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
@@ -747,7 +869,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       const int kr = kk + lane / 16;
 #pragma unroll
       for (int pl = 0; pl < NP; ++pl) {
-        double av[MI], bv[NI];
+        R av[MI], bv[NI];
 #pragma unroll
         for (int a = 0; a < MI; ++a) av[a] = As[pl][(wr + a * 16 + (lane & 15)) * LD + kr];
 #pragma unroll
@@ -756,25 +878,25 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
         for (int a = 0; a < MI; ++a)
 #pragma unroll
           for (int b = 0; b < NI; ++b)
-            acc[pl][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[pl][a][b], 0, 0, 0);
+            acc[pl][a][b] = mfma_op(av[a], bv[b], acc[pl][a][b]);
       }
     }
     __syncthreads();
   }
-  // epilogue: lane holds rows 4r + lane/16 of column lane%16 of each block
+  // epilogue: lane holds rows out_row(lane, r) of column lane % 16 of each block
 #pragma unroll
   for (int a = 0; a < MI; ++a)
 #pragma unroll
     for (int b = 0; b < NI; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wr + a * 16 + 4 * r + lane / 16;
+        const int row = i0 + wr + a * 16 + Scalar<T>::out_row(lane, r);
         const int col = j0 + wc + b * 16 + (lane & 15);
         if (nsplit > 1) {  // partial tile: (rowtile, seg) block of BM rows x nc
           if (col >= nc) continue;
-          double pr, pi = 0.0;
+          R pr, pi = 0;
           if constexpr (CPX) {
-            const double p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
+            const R p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
             pr = p1 - p2;
             pi = p3 - p1 - p2;
           } else {
@@ -784,9 +906,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
           continue;
         }
         if (row >= rows || col >= nc) continue;
-        double vr, vi = 0.0;
+        R vr, vi = 0;
         if constexpr (CPX) {
-          const double p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
+          const R p1 = acc[0][a][b][r], p2 = acc[CPX ? 1 : 0][a][b][r], p3 = acc[CPX ? 2 : 0][a][b][r];
           vr = p1 - p2;
           vi = p3 - p1 - p2;
         } else {
@@ -797,7 +919,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
             make(vr, vi, Z[(int64_t)(c0 + row) * nc + col]);
           } else {
             T *u = U + (f.uoff[s] + (row - w)) * nc + col;
-            double ur, ui;
+            R ur, ui;
             split(*u, ur, ui);
             make(ur + vr, ui + vi, *u);
           }
@@ -812,6 +934,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
 template <typename T, int BM>
 __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
                                                      int32_t nc, int32_t nsplit, const T *ws, T *X) {
+  using R = typename Scalar<T>::R;
   const int rowtile = blockIdx.x;
   const int ti = find_task(tasks, n_tasks, rowtile);
   const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
@@ -820,9 +943,9 @@ __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTas
     const int rr = e / nc, col = e % nc;
     const int row = rt * BM + rr;
     if (row >= w) continue;
-    double ar = 0.0, ai = 0.0;
+    R ar = 0, ai = 0;
     for (int g = 0; g < nsplit; ++g) {
-      double r, i;
+      R r, i;
       split(ws[(((int64_t)rowtile * nsplit + g) * BM + rr) * nc + col], r, i);
       ar += r;
       ai += i;
@@ -872,10 +995,10 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   // algorithmic work: one multiply-add per factor entry and right-hand side
   // (8 flops complex, 2 real); traffic: the factor panels once, the
   // right-hand-side rows in and out once
-  const double scal = Scalar<T>::cpx ? 16.0 : 8.0;
+  const double scal = (double)sizeof(T);
   char name[96];
   if (prof) {
-    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>%s", Scalar<T>::cpx ? "cd" : "double", bmv, bn,
+    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>%s", Scalar<T>::name, bmv, bn,
              DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd"), nsplit > 1 ? "+splitk" : "");
     prof->begin(s);
   }
@@ -914,15 +1037,18 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
 
 template <typename T>
 void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s) {
-  for (int h = p.n_heights - 1; h >= 0; --h) launch_sn_gemm<T, 1>(f, p.bwd[h], p.tile_rows, p.splitk, p.prof, p.splitk_ws, p.splitk_bytes, nc, X, Z,
+  for (int h = p.n_heights - 1; h >= 0; --h)
+    launch_sn_gemm<T, 1>(f, p.bwd[h], p.tile_rows, p.splitk, p.prof, p.splitk_ws, p.splitk_bytes, nc, X, Z,
                          nullptr, s);
 }
 
-template void solve_forward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,
-                                    double *, hipStream_t);
-template void solve_forward<cd>(const FactorDev &, const SolvePlan &, int32_t, cd *, cd *, cd *, hipStream_t);
-template void solve_backward<double>(const FactorDev &, const SolvePlan &, int32_t, double *, double *,
-                                     hipStream_t);
-template void solve_backward<cd>(const FactorDev &, const SolvePlan &, int32_t, cd *, cd *, hipStream_t);
+#define SOLVE_INST(T)                                                                                   \
+  template void solve_forward<T>(const FactorDev &, const SolvePlan &, int32_t, T *, T *, T *, hipStream_t); \
+  template void solve_backward<T>(const FactorDev &, const SolvePlan &, int32_t, T *, T *, hipStream_t);
+SOLVE_INST(double)
+SOLVE_INST(cd)
+SOLVE_INST(float)
+SOLVE_INST(cf)
+#undef SOLVE_INST
 
 }  // namespace stmg

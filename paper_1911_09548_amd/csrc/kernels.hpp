@@ -21,30 +21,36 @@ struct Profiler {
   void *impl = nullptr;
 };
 
-struct cd {  // complex double, 16-byte aligned
+struct cd {  // complex double
   double re, im;
+};
+struct cf {  // complex float
+  float re, im;
 };
 
 // Space-time residual of one level (fused SpMM with M and K on their shared
 // pattern + DG coupling to the previous slab in the same row).
-struct ResidualArgs {
+template <typename R>
+struct ResidualArgsT {
   int32_t n_rows;
   int32_t N, q;                 // slabs, components
   const int64_t *ptr;
   const int32_t *col;
-  const double *mval, *kval;
+  const R *mval, *kval;
   double tau;
-  const double *x;              // may be null: x = 0
-  const double *b;
-  double *out;
-  double *partial;              // may be null: per-block sum of squares of r
+  const R *x;                   // may be null: x = 0
+  const R *b;
+  R *out;
+  double *partial;              // may be null: per-block sum of squares of r (FP64)
   int32_t mode;                 // 0: out = r; 1: out = slab-solve right-hand side
   int64_t nnz = 0;              // pattern nonzeros (work accounting only)
   Profiler *prof = nullptr;
 };
+using ResidualArgs = ResidualArgsT<double>;
 enum { RES_OUT_R = 0, RES_OUT_SLABRHS = 1 };
 int residual_blocks(int32_t n_rows, int32_t W, int32_t q);
-void launch_residual(const ResidualArgs &a, hipStream_t s);
+template <typename R>
+void launch_residual(const ResidualArgsT<R> &a, hipStream_t s);
 
 // Sum of `n` doubles in fixed order (deterministic), result at out[0].
 void launch_sum(const double *partial, int32_t n, double *out, hipStream_t s);
@@ -54,25 +60,31 @@ int launch_sumsq(const double *v, int64_t n, double *partial, hipStream_t s);
 // Jacobi update x += omega * (time back-transform of z) (eq. (2)).
 // q = 2: x0 += omega 2 Re z, x1 += omega 2 (Re z - sqrt2 Im z); q = 1: x += omega z.
 // assign != 0: x = (...) instead of +=.
-void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const double *z,
-                        double *x, int assign, hipStream_t s);
+template <typename R>
+void launch_slab_update(int32_t n_rows, int32_t N, int32_t q, double omega, const R *z, R *x, int assign,
+                        hipStream_t s);
 // Slab-solve right-hand side from a residual-layout vector r (no SpMV).
-void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const double *r, double *w, hipStream_t s);
+template <typename R>
+void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const R *r, R *w, hipStream_t s);
 
 // Nodal correction pieces (eq. (8)).
+template <typename R>
 void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edge, const int8_t *sign,
-                  const double *r, double *g, hipStream_t s);
-void launch_time_scan(int32_t n_v, int32_t N, int32_t q, double *g, hipStream_t s);
-void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const double *y,
-                     double *x, hipStream_t s);
+                  const R *r, R *g, hipStream_t s);
+template <typename R>
+void launch_time_scan(int32_t n_v, int32_t N, int32_t q, R *g, hipStream_t s);
+template <typename R>
+void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const R *y, R *x,
+                     hipStream_t s);
 
 // Space-time transfers. P_s given as CSR (rows: coarse for restrict = P^T,
-// fine for prolong = P); identity when ptr == nullptr (then map gives the row
-// correspondence... rows coincide).
+// fine for prolong = P); the identity when ptr == nullptr (same mesh).
+template <typename R>
 void launch_restrict(int32_t n_c, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
-                     const double *val, const double *r_f, double *r_c, hipStream_t s);
+                     const double *val, const R *r_f, R *r_c, hipStream_t s);
+template <typename R>
 void launch_prolong_add(int32_t n_f, int32_t Nc, int32_t q, const int64_t *ptr, const int32_t *col,
-                        const double *val, const double *e_c, double *x_f, hipStream_t s);
+                        const double *val, const R *e_c, R *x_f, hipStream_t s);
 
 // Layout changes between ABI vectors [N][q][ncols] and internal [row][N][q];
 // map[row] = ABI column of the internal row.
@@ -86,8 +98,13 @@ void launch_fold_initial(int32_t n_rows, int32_t N, int32_t q, const int64_t *pt
                          const double *mval, const int32_t *map, const double *u0_abi, double *b,
                          hipStream_t s);
 
-void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+template <typename R>
+void launch_fill(R *p, int64_t n, double v, hipStream_t s);
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+// refinement-loop conversions: out = (float) in; out = (double) in; y += (double) x
+void launch_to_float(int64_t n, const double *in, float *out, hipStream_t s);
+void launch_to_double(int64_t n, const float *in, double *out, hipStream_t s);
+void launch_add_float(int64_t n, const float *x, double *y, hipStream_t s);
 
 // ------------------------------------------------------------------ solves
 // Multifrontal forward/backward solves with a supernodal L (L L^T = A) for

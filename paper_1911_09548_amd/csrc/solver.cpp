@@ -176,25 +176,46 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.plan.bwd = D.bwd.data();
 }
 
-// Upload P_s of every supernode; with `transpose`, also P_s^T (w x m,
-// column-major), which the backward solve then streams with unit stride.
+// Upload P_s of every supernode (and P_s^T when `transpose`: w x m,
+// column-major, which the backward solve then streams with unit stride)
+// into `F` with scalar type T; TH is the host FP64 scalar, T may be the FP64
+// type or its FP32 counterpart (values rounded to nearest).
+inline void narrow(const double &a, double &b) { b = a; }
+inline void narrow(const double &a, float &b) { b = (float)a; }
+inline void narrow(const cplx &a, cd &b) { b = {a.re, a.im}; }
+inline void narrow(const cplx &a, cf &b) { b = {(float)a.re, (float)a.im}; }
+
 template <typename T, typename TH>
-void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, DevFactor &D, bool transpose) {
-  static_assert(sizeof(T) == sizeof(TH), "scalar size mismatch");
-  D.f.panel = dev_upload(h, reinterpret_cast<const T *>(F.panel.data()), F.panel.size());
-  D.f.panel_off = dev_upload(h, F.panel_off);
-  D.factor_bytes = (int64_t)(F.panel.size() * sizeof(T));
-  D.f.panel_t = nullptr;
+void upload_panels(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, FactorDev &fd, bool transpose,
+                   int64_t &bytes) {
+  std::vector<T> P(F.panel.size());
+  for (size_t i = 0; i < P.size(); ++i) narrow(F.panel[i], P[i]);
+  fd.panel = dev_upload(h, P);
+  bytes += (int64_t)(P.size() * sizeof(T));
+  fd.panel_t = nullptr;
   if (transpose) {
-    std::vector<TH> Pt(F.panel.size());
+    std::vector<T> Pt(P.size());
     for (int32_t s = 0; s < S.ns; ++s) {
       const int64_t w = S.width(s), m = w + S.nrows(s), o = F.panel_off[s];
       for (int64_t k = 0; k < w; ++k)
-        for (int64_t i = 0; i < m; ++i) Pt[o + k + i * w] = F.panel[o + i + k * m];
+        for (int64_t i = 0; i < m; ++i) Pt[o + k + i * w] = P[o + i + k * m];
     }
-    D.f.panel_t = dev_upload(h, reinterpret_cast<const T *>(Pt.data()), Pt.size());
-    D.factor_bytes *= 2;
+    fd.panel_t = dev_upload(h, Pt);
+    bytes += (int64_t)(Pt.size() * sizeof(T));
   }
+}
+
+// Offsets (shared by both precisions) and the panels each form needs.
+template <typename T64, typename T32, typename TH>
+void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, DevFactor &D, bool transpose,
+                   bool need64, bool need32) {
+  D.f.panel_off = dev_upload(h, F.panel_off);
+  D.f.panel = D.f.panel_t = nullptr;
+  D.factor_bytes = 0;
+  if (need64) upload_panels<T64>(h, S, F, D.f, transpose, D.factor_bytes);
+  D.f32 = D.f;
+  D.f32.panel = D.f32.panel_t = nullptr;
+  if (need32) upload_panels<T32>(h, S, F, D.f32, transpose, D.factor_bytes);
   h->factor_bytes += D.factor_bytes;
 }
 
@@ -217,6 +238,11 @@ void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
   md.d_col = dev_upload(h, md.Mp.col);
   md.d_mval = dev_upload(h, md.Mp.val);
   md.d_kval = dev_upload(h, md.Kp.val);
+  if (h->opt.precision == STMG_FP32_REFINED) {
+    std::vector<float> mv(md.Mp.val.begin(), md.Mp.val.end()), kv(md.Kp.val.begin(), md.Kp.val.end());
+    md.d_mval32 = dev_upload(h, mv);
+    md.d_kval32 = dev_upload(h, kv);
+  }
   const int32_t ne = T.n_int_edges(), nv = T.n_int_verts();
   // G in internal numberings
   std::vector<int32_t> head(ne, -1), tail(ne, -1);
@@ -266,7 +292,8 @@ void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
   }
   if (has_nodal) {
     build_plan(h, md.sym_v, md.nodal);
-    upload_factor<double>(h, md.sym_v, *md.nodal_host, md.nodal, true);
+    upload_factor<double, float>(h, md.sym_v, *md.nodal_host, md.nodal, true, true,
+                                 h->opt.precision == STMG_FP32_REFINED);
     if (!h->opt.host_only) md.nodal_host.reset();
   }
 }
@@ -316,6 +343,16 @@ bool slab_transpose(const stmg_handle *h, const LevelData &L) {
   return total <= (int64_t)40 << 30 || L.N <= 16;
 }
 
+// Which slab factors each form keeps on the device: the plain form all FP64;
+// the precision form FP32 on every level plus FP64 on the coarsest.
+bool is_coarsest(const stmg_handle *h, const LevelData &L) { return &L == &h->levels.back(); }
+bool need64(const stmg_handle *h, const LevelData &L) {
+  return h->opt.precision != STMG_FP32_REFINED || is_coarsest(h, L);
+}
+bool need32(const stmg_handle *h, const LevelData &L) {
+  return h->opt.precision == STMG_FP32_REFINED && !is_coarsest(h, L);
+}
+
 void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   const SpaceLevel &S = *md.S;
@@ -329,7 +366,8 @@ void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
     if (device) {
       L.slab.is_complex = true;
       build_plan(h, md.sym_e, L.slab);
-      upload_factor<cd>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L));
+      upload_factor<cd, cf>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L), need64(h, L),
+                            need32(h, L));
       if (!h->opt.host_only) L.slab_host_c.reset();
     }
   } else {
@@ -339,48 +377,109 @@ void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
     factor_host<double>(md.sym_e, S.M, v, *L.slab_host_r);
     if (device) {
       build_plan(h, md.sym_e, L.slab);
-      upload_factor<double>(h, md.sym_e, *L.slab_host_r, L.slab, slab_transpose(h, L));
+      upload_factor<double, float>(h, md.sym_e, *L.slab_host_r, L.slab, slab_transpose(h, L), need64(h, L),
+                                   need32(h, L));
       if (!h->opt.host_only) L.slab_host_r.reset();
     }
   }
 }
 
-void alloc_level_vectors(stmg_handle *h, LevelData &L) {
+void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   const int64_t ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
   const int64_t W = (int64_t)L.N * h->q;
-  L.x = dev_alloc<double>(h, ne * W);
-  L.b = dev_alloc<double>(h, ne * W);
-  L.w = dev_alloc<double>(h, ne * W);
-  L.z = dev_alloc<double>(h, ne * W);
-  L.u = dev_alloc<double>(h, std::max<int64_t>(1, L.slab.u_rows * W));
-  if (nv > 0) {
+  const bool prec = h->opt.precision == STMG_FP32_REFINED;
+  const bool last = is_coarsest(h, L);
+  // FP64: every level in the plain form; in the precision form the outer
+  // iterate, right-hand side and residual on level 0 and the coarsest solve
+  if (!prec || first || last) {
+    L.x = dev_alloc<double>(h, ne * W);
+    L.b = dev_alloc<double>(h, ne * W);
+    L.w = dev_alloc<double>(h, ne * W);
+  }
+  if (!prec || last) {
+    L.z = dev_alloc<double>(h, ne * W);
+    L.u = dev_alloc<double>(h, std::max<int64_t>(1, L.slab.u_rows * W));
+  }
+  if (!prec && nv > 0) {
     L.g = dev_alloc<double>(h, nv * W);
     L.zn = dev_alloc<double>(h, nv * W);
     L.un = dev_alloc<double>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
   }
+  if (prec) {
+    L.x32 = dev_alloc<float>(h, ne * W);
+    L.b32 = dev_alloc<float>(h, ne * W);
+    L.w32 = dev_alloc<float>(h, ne * W);
+    L.z32 = dev_alloc<float>(h, ne * W);
+    L.u32 = dev_alloc<float>(h, std::max<int64_t>(1, L.slab.u_rows * W));
+    if (nv > 0) {
+      L.g32 = dev_alloc<float>(h, nv * W);
+      L.zn32 = dev_alloc<float>(h, nv * W);
+      L.un32 = dev_alloc<float>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
+    }
+  }
 }
 
 // --------------------------------------------------------------- operators
-struct Ops {
+// Buffer and factor selection by precision: R = double is the plain FP64
+// form; R = float the smoother of the precision form (FP32 vectors, matrix
+// values and factors), whose coarsest solve runs in FP64.
+template <typename R>
+struct Bufs;
+template <>
+struct Bufs<double> {
+  static double *x(LevelData &L) { return L.x; }
+  static double *b(LevelData &L) { return L.b; }
+  static double *w(LevelData &L) { return L.w; }
+  static double *z(LevelData &L) { return L.z; }
+  static double *u(LevelData &L) { return L.u; }
+  static double *g(LevelData &L) { return L.g; }
+  static double *zn(LevelData &L) { return L.zn; }
+  static double *un(LevelData &L) { return L.un; }
+  static const double *mval(MeshData &m) { return m.d_mval; }
+  static const double *kval(MeshData &m) { return m.d_kval; }
+  static const FactorDev &fac(DevFactor &d) { return d.f; }
+  using C = cd;
+};
+template <>
+struct Bufs<float> {
+  static float *x(LevelData &L) { return L.x32; }
+  static float *b(LevelData &L) { return L.b32; }
+  static float *w(LevelData &L) { return L.w32; }
+  static float *z(LevelData &L) { return L.z32; }
+  static float *u(LevelData &L) { return L.u32; }
+  static float *g(LevelData &L) { return L.g32; }
+  static float *zn(LevelData &L) { return L.zn32; }
+  static float *un(LevelData &L) { return L.un32; }
+  static const float *mval(MeshData &m) { return m.d_mval32; }
+  static const float *kval(MeshData &m) { return m.d_kval32; }
+  static const FactorDev &fac(DevFactor &d) { return d.f32; }
+  using C = cf;
+};
+
+template <typename R>
+struct OpsT {
   stmg_handle *h;
   hipStream_t s;
+  using B = Bufs<R>;
+  using CX = typename B::C;
 
   MeshData &mesh(int l) { return h->meshes[h->mesh_slot[h->levels[l].mesh]]; }
   int32_t ne(int l) { return mesh(l).S->topo.n_int_edges(); }
   int32_t nv(int l) { return mesh(l).S->topo.n_int_verts(); }
   int32_t W(int l) { return h->levels[l].N * h->q; }
+  bool coarsest(int l) { return l + 1 == (int)h->levels.size(); }
 
-  void residual(int l, const double *x, const double *b, double *out, int mode, double *partial) {
+  void residual(int l, const R *x, const R *b, R *out, int mode, double *partial) {
     MeshData &md = mesh(l);
-    ResidualArgs a;
+    ResidualArgsT<R> a;
     a.n_rows = ne(l);
     a.N = h->levels[l].N;
     a.q = h->q;
     a.ptr = md.d_ptr;
     a.col = md.d_col;
-    a.mval = md.d_mval;
-    a.kval = md.d_kval;
+    a.mval = B::mval(md);
+    a.kval = B::kval(md);
     a.tau = h->levels[l].tau;
     a.x = x;
     a.b = b;
@@ -393,94 +492,139 @@ struct Ops {
   }
 
   // w <- A_l^{-1} w in place (slab right-hand-side layout)
-  void slab_solve(int l, double *w) {
+  void slab_solve(int l, R *w) {
     LevelData &L = h->levels[l];
     const int32_t nc = L.N;
+    const FactorDev &F = B::fac(L.slab);
     if (L.slab.is_complex) {
-      solve_forward<cd>(L.slab.f, L.slab.plan, nc, (cd *)w, (cd *)L.z, (cd *)L.u, s);
-      solve_backward<cd>(L.slab.f, L.slab.plan, nc, (cd *)w, (cd *)L.z, s);
+      solve_forward<CX>(F, L.slab.plan, nc, (CX *)w, (CX *)B::z(L), (CX *)B::u(L), s);
+      solve_backward<CX>(F, L.slab.plan, nc, (CX *)w, (CX *)B::z(L), s);
     } else {
-      solve_forward<double>(L.slab.f, L.slab.plan, nc, w, L.z, L.u, s);
-      solve_backward<double>(L.slab.f, L.slab.plan, nc, w, L.z, s);
+      solve_forward<R>(F, L.slab.plan, nc, w, B::z(L), B::u(L), s);
+      solve_backward<R>(F, L.slab.plan, nc, w, B::z(L), s);
     }
   }
 
-  void smooth_S(int l, double *x, const double *b) {
+  void smooth_S(int l, R *x, const R *b) {
     LevelData &L = h->levels[l];
-    residual(l, x, b, L.w, RES_OUT_SLABRHS, nullptr);
-    slab_solve(l, L.w);
-    launch_slab_update(ne(l), L.N, h->q, h->opt.omega, L.w, x, 0, s);
+    residual(l, x, b, B::w(L), RES_OUT_SLABRHS, nullptr);
+    slab_solve(l, B::w(L));
+    launch_slab_update<R>(ne(l), L.N, h->q, h->opt.omega, B::w(L), x, 0, s);
   }
 
-  void nodal_A(int l, double *x, const double *b) {
+  void nodal_A(int l, R *x, const R *b) {
     LevelData &L = h->levels[l];
     MeshData &md = mesh(l);
     if (nv(l) == 0) return;
     const int32_t w = W(l);
-    residual(l, x, b, L.w, RES_OUT_R, nullptr);
-    launch_gradT(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, L.w, L.g, s);
-    solve_forward<double>(md.nodal.f, md.nodal.plan, w, L.g, L.zn, L.un, s);
-    solve_backward<double>(md.nodal.f, md.nodal.plan, w, L.g, L.zn, s);
-    launch_time_scan(nv(l), L.N, h->q, L.g, s);
-    launch_grad_add(ne(l), w, md.d_head, md.d_tail, L.g, x, s);
+    residual(l, x, b, B::w(L), RES_OUT_R, nullptr);
+    launch_gradT<R>(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, B::w(L), B::g(L), s);
+    const FactorDev &F = B::fac(md.nodal);
+    solve_forward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), B::un(L), s);
+    solve_backward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), s);
+    launch_time_scan<R>(nv(l), L.N, h->q, B::g(L), s);
+    launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s);
   }
 
-  void hybrid(int l, double *x, const double *b) {
+  void hybrid(int l, R *x, const R *b) {
     smooth_S(l, x, b);
     if (h->opt.smoother == STMG_SMOOTH_SAS) nodal_A(l, x, b);
     smooth_S(l, x, b);
   }
 
-  void exact(int l, double *x, const double *b) {
-    LevelData &L = h->levels[l];
-    launch_slab_rhs(ne(l), L.N, h->q, b, L.w, s);
-    slab_solve(l, L.w);
-    launch_slab_update(ne(l), L.N, h->q, 1.0, L.w, x, 1, s);
-  }
+  void exact(int l, R *x, const R *b);
 
-  void restrict_to(int l, const double *rf, double *rc) {
+  void restrict_to(int l, const R *rf, R *rc) {
     LevelData &C = h->levels[l + 1];
     if (C.mesh != h->levels[l].mesh) {
       MeshData &mc = mesh(l + 1);
-      launch_restrict(ne(l + 1), C.N, h->q, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, rf, rc, s);
+      launch_restrict<R>(ne(l + 1), C.N, h->q, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, rf, rc, s);
     } else {
-      launch_restrict(ne(l + 1), C.N, h->q, nullptr, nullptr, nullptr, rf, rc, s);
+      launch_restrict<R>(ne(l + 1), C.N, h->q, nullptr, nullptr, nullptr, rf, rc, s);
     }
   }
 
-  void prolong_add(int l, const double *ec, double *xf) {
+  void prolong_add(int l, const R *ec, R *xf) {
     // from level l+1 to level l
     LevelData &C = h->levels[l + 1];
     if (C.mesh != h->levels[l].mesh) {
       MeshData &mc = mesh(l + 1);
-      launch_prolong_add(ne(l), C.N, h->q, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, ec, xf, s);
+      launch_prolong_add<R>(ne(l), C.N, h->q, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, ec, xf, s);
     } else {
-      launch_prolong_add(ne(l), C.N, h->q, nullptr, nullptr, nullptr, ec, xf, s);
+      launch_prolong_add<R>(ne(l), C.N, h->q, nullptr, nullptr, nullptr, ec, xf, s);
     }
   }
 
-  void vcycle(int l, double *x, const double *b) {
+  void vcycle(int l, R *x, const R *b) {
     LevelData &L = h->levels[l];
     if (L.N == 1) {
       exact(l, x, b);
       return;
     }
     hybrid(l, x, b);
-    residual(l, x, b, L.w, RES_OUT_R, nullptr);
+    residual(l, x, b, B::w(L), RES_OUT_R, nullptr);
     LevelData &C = h->levels[l + 1];
-    restrict_to(l, L.w, C.b);
-    launch_fill(C.x, (int64_t)ne(l + 1) * W(l + 1), 0.0, s);
-    vcycle(l + 1, C.x, C.b);
-    prolong_add(l, C.x, x);
+    restrict_to(l, B::w(L), B::b(C));
+    launch_fill<R>(B::x(C), (int64_t)ne(l + 1) * W(l + 1), 0.0, s);
+    vcycle(l + 1, B::x(C), B::b(C));
+    prolong_add(l, B::x(C), x);
     hybrid(l, x, b);
   }
 
-  // ||b - L x||^2 into d_scalar[slot] (device)
-  void residual_norm2(int l, const double *x, const double *b, double *dst) {
-    residual(l, x, b, h->levels[l].w, RES_OUT_R, h->d_partial);
+  // ||b - L x||^2 into dst (device), FP64 accumulation
+  void residual_norm2(int l, const R *x, const R *b, R *out, double *dst) {
+    residual(l, x, b, out, RES_OUT_R, h->d_partial);
     launch_sum(h->d_partial, residual_blocks(ne(l), W(l), h->q), dst, s);
   }
 };
+
+// Exact solve with the slab factor on a one-slab level (FP64 factor).
+template <>
+void OpsT<double>::exact(int l, double *x, const double *b) {
+  LevelData &L = h->levels[l];
+  launch_slab_rhs<double>(ne(l), L.N, h->q, b, L.w, s);
+  slab_solve(l, L.w);
+  launch_slab_update<double>(ne(l), L.N, h->q, 1.0, L.w, x, 1, s);
+}
+
+// The precision form keeps the coarsest solve in FP64: widen b, solve with
+// the FP64 factor, narrow x.
+template <>
+void OpsT<float>::exact(int l, float *x, const float *b) {
+  LevelData &L = h->levels[l];
+  const int64_t n = (int64_t)ne(l) * W(l);
+  launch_to_double(n, b, L.b, s);
+  OpsT<double>{h, s}.exact(l, L.x, L.b);
+  launch_to_float(n, L.x, x, s);
+}
+
+using Ops = OpsT<double>;
+
+// One iteration of the precision form on level 0: e = V32(r) from e = 0,
+// x += e in FP64, then the FP64 residual r = b - L x and its squared norm.
+void refine_iteration(stmg_handle *h, double *dst_norm2) {
+  OpsT<float> o32{h, h->stream};
+  Ops o64{h, h->stream};
+  LevelData &L = h->levels[0];
+  const int64_t n = (int64_t)o64.ne(0) * o64.W(0);
+  launch_to_float(n, L.w, L.b32, h->stream);
+  launch_fill<float>(L.x32, n, 0.0, h->stream);
+  o32.vcycle(0, L.x32, L.b32);
+  launch_add_float(n, L.x32, L.x, h->stream);
+  o64.residual_norm2(0, L.x, L.b, L.w, dst_norm2);
+}
+
+// One solver iteration on level 0 (either form); ||b - L x||^2 into dst.
+void solver_iteration(stmg_handle *h, double *dst_norm2) {
+  if (h->opt.precision == STMG_FP32_REFINED) {
+    refine_iteration(h, dst_norm2);
+  } else {
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    op.vcycle(0, L.x, L.b);
+    op.residual_norm2(0, L.x, L.b, L.w, dst_norm2);
+  }
+}
 
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
@@ -508,6 +652,55 @@ double *tmp_buf(stmg_handle *h, int i) {
     h->d_tmp[i] = dev_alloc<double>(h, (size_t)md.S->topo.n_int_edges() * L.N * h->q);
   }
   return h->d_tmp[i];
+}
+
+float *tmp_buf32(stmg_handle *h, int i) {
+  if (!h->f_tmp[i]) {
+    const LevelData &L = h->levels[0];
+    const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    h->f_tmp[i] = dev_alloc<float>(h, (size_t)md.S->topo.n_int_edges() * L.N * h->q);
+  }
+  return h->f_tmp[i];
+}
+
+// One level operation on internal-layout buffers t0 (x or input), t1 (b),
+// result in t2.
+template <typename R>
+void apply_op(stmg_handle *h, int level, int op_code, R *t0, R *t1, R *t2) {
+  OpsT<R> op{h, h->stream};
+  hipStream_t s = h->stream;
+  LevelData &L = h->levels[level];
+  const int32_t ne = op.ne(level);
+  const size_t bytes = (size_t)ne * op.W(level) * sizeof(R);
+  switch (op_code) {
+    case STMG_OP_RESIDUAL:
+      op.residual(level, t0, t1, t2, RES_OUT_R, nullptr);
+      break;
+    case STMG_OP_SMOOTH_S:
+    case STMG_OP_NODAL_A:
+    case STMG_OP_SAS:
+    case STMG_OP_VCYCLE:
+      hip_check(hipMemcpyAsync(t2, t0, bytes, hipMemcpyDeviceToDevice, s), "copy");
+      if (op_code == STMG_OP_SMOOTH_S) op.smooth_S(level, t2, t1);
+      if (op_code == STMG_OP_NODAL_A) op.nodal_A(level, t2, t1);
+      if (op_code == STMG_OP_SAS) op.hybrid(level, t2, t1);
+      if (op_code == STMG_OP_VCYCLE) op.vcycle(level, t2, t1);
+      break;
+    case STMG_OP_SLAB_SOLVE:
+      launch_slab_rhs<R>(ne, L.N, h->q, t0, Bufs<R>::w(L), s);
+      op.slab_solve(level, Bufs<R>::w(L));
+      launch_slab_update<R>(ne, L.N, h->q, 1.0, Bufs<R>::w(L), t2, 1, s);
+      break;
+    case STMG_OP_RESTRICT:
+      op.restrict_to(level, t0, t2);
+      break;
+    case STMG_OP_PROLONG:
+      launch_fill<R>(t2, (int64_t)op.ne(level - 1) * op.W(level - 1), 0.0, s);
+      op.prolong_add(level - 1, t0, t2);
+      break;
+    default:
+      fail(STMG_EINVAL, "unknown op");
+  }
 }
 
 void destroy_handle(stmg_handle *h) {
@@ -631,7 +824,8 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
     else
       stmg_default_options(&h->opt);
     STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
-    STMG_REQUIRE(h->opt.precision == STMG_FP64, STMG_ENOSYS, "precision form not available yet");
+    STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
+                 "unknown precision form");
     if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
     STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                  "gemm_rows must be 0, 32 or 64");
@@ -684,7 +878,7 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
     for (size_t l = 0; l < h->levels.size(); ++l) {
       LevelData &L = h->levels[l];
       setup_level_factor(h, L, device);
-      if (device) alloc_level_vectors(h, L);
+      if (device) alloc_level_vectors(h, L, l == 0);
       if (verbose())
         fprintf(stderr, "[stmg] level %zu (mesh %d, N %d, tau %.4g, lambda %.3g) factored (%.2fs)\n", l, L.mesh,
                 L.N, L.tau, L.lambda, wall_time() - t0);
@@ -775,6 +969,8 @@ int stmg_load(stmg_handle *h, const double *rhs_dev, const double *u0_dev, const
       launch_fill(L.x, (int64_t)ne * op.W(0), 0.0, h->stream);
     const int nb = launch_sumsq(L.b, (int64_t)ne * op.W(0), h->d_partial, h->stream);
     launch_sum(h->d_partial, nb, h->d_scalar, h->stream);
+    // the precision form refines from the FP64 residual of the current iterate
+    if (h->opt.precision == STMG_FP32_REFINED) op.residual(0, L.x, L.b, L.w, RES_OUT_R, nullptr);
     check_launch();
     double b2 = 0.0;
     hip_check(hipMemcpyAsync(&b2, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
@@ -791,12 +987,7 @@ int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host) {
   return guard([&] {
     require_device(h);
     STMG_REQUIRE(n_cycles >= 0 && n_cycles <= 8192, STMG_EINVAL, "n_cycles out of range");
-    Ops op{h, h->stream};
-    LevelData &L = h->levels[0];
-    for (int32_t i = 0; i < n_cycles; ++i) {
-      op.vcycle(0, L.x, L.b);
-      op.residual_norm2(0, L.x, L.b, h->d_scalar + i);
-    }
+    for (int32_t i = 0; i < n_cycles; ++i) solver_iteration(h, h->d_scalar + i);
     check_launch();
     if (res_host && n_cycles > 0) {
       std::vector<double> r2(n_cycles);
@@ -839,12 +1030,9 @@ int stmg_solve(stmg_handle *h, const double *rhs_dev, const double *u0_dev, cons
     h->rel_res = 0.0;
     h->cycles = 0;
     if (bn > 0.0) {
-      Ops op{h, h->stream};
-      LevelData &L = h->levels[0];
       status = STMG_ENOTCONV;
       for (int32_t c = 0; c < h->opt.max_cycles; ++c) {
-        op.vcycle(0, L.x, L.b);
-        op.residual_norm2(0, L.x, L.b, h->d_scalar);
+        solver_iteration(h, h->d_scalar);
         check_launch();
         double r2 = 0.0;
         hip_check(hipMemcpyAsync(&r2, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
@@ -909,54 +1097,34 @@ int stmg_level_apply(stmg_handle *h, int32_t level, int32_t op_code, const doubl
     const int32_t nl = (int32_t)h->levels.size();
     STMG_REQUIRE(level >= 0 && level < nl, STMG_EINVAL, "level out of range");
     STMG_REQUIRE(in_dev && out_dev, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(op_code >= STMG_OP_RESIDUAL && op_code <= STMG_OP_VCYCLE, STMG_EINVAL, "unknown op");
+    const bool needs_in2 = op_code == STMG_OP_RESIDUAL || op_code == STMG_OP_SMOOTH_S ||
+                           op_code == STMG_OP_NODAL_A || op_code == STMG_OP_SAS || op_code == STMG_OP_VCYCLE;
+    STMG_REQUIRE(!needs_in2 || in2_dev, STMG_EINVAL, "in2 is null");
+    STMG_REQUIRE(op_code != STMG_OP_RESTRICT || level + 1 < nl, STMG_EINVAL, "no coarser level");
+    STMG_REQUIRE(op_code != STMG_OP_PROLONG || level >= 1, STMG_EINVAL, "no finer level");
+    const bool prec = h->opt.precision == STMG_FP32_REFINED;
+    const bool last = level + 1 == nl;
+    STMG_REQUIRE(!(prec && last && (op_code == STMG_OP_SMOOTH_S || op_code == STMG_OP_NODAL_A || op_code == STMG_OP_SAS)),
+                 STMG_ENOSYS, "the precision form only solves exactly on the coarsest level");
     Ops op{h, h->stream};
     hipStream_t s = h->stream;
-    LevelData &L = h->levels[level];
     MeshData &md = op.mesh(level);
-    const int32_t ne = op.ne(level), n = ne;
+    const int32_t n = op.ne(level);
+    const int out_level = op_code == STMG_OP_RESTRICT ? level + 1 : (op_code == STMG_OP_PROLONG ? level - 1 : level);
+    const int64_t n_in = (int64_t)n * op.W(level), n_out = (int64_t)op.ne(out_level) * op.W(out_level);
     double *t0 = tmp_buf(h, 0), *t1 = tmp_buf(h, 1), *t2 = tmp_buf(h, 2);
-    launch_abi_to_internal(n, L.N, h->q, n, md.d_map_level, in_dev, t0, s);
-    auto need_in2 = [&] {
-      STMG_REQUIRE(in2_dev, STMG_EINVAL, "in2 is null");
-      launch_abi_to_internal(n, L.N, h->q, n, md.d_map_level, in2_dev, t1, s);
-    };
-    const size_t bytes = (size_t)ne * op.W(level) * sizeof(double);
-    int out_level = level;
-    switch (op_code) {
-      case STMG_OP_RESIDUAL:
-        need_in2();
-        op.residual(level, t0, t1, t2, RES_OUT_R, nullptr);
-        break;
-      case STMG_OP_SMOOTH_S:
-      case STMG_OP_NODAL_A:
-      case STMG_OP_SAS:
-      case STMG_OP_VCYCLE:
-        need_in2();
-        hip_check(hipMemcpyAsync(t2, t0, bytes, hipMemcpyDeviceToDevice, s), "copy");
-        if (op_code == STMG_OP_SMOOTH_S) op.smooth_S(level, t2, t1);
-        if (op_code == STMG_OP_NODAL_A) op.nodal_A(level, t2, t1);
-        if (op_code == STMG_OP_SAS) op.hybrid(level, t2, t1);
-        if (op_code == STMG_OP_VCYCLE) op.vcycle(level, t2, t1);
-        break;
-      case STMG_OP_SLAB_SOLVE:
-        launch_slab_rhs(ne, L.N, h->q, t0, L.w, s);
-        op.slab_solve(level, L.w);
-        launch_slab_update(ne, L.N, h->q, 1.0, L.w, t2, 1, s);
-        break;
-      case STMG_OP_RESTRICT:
-        STMG_REQUIRE(level + 1 < nl, STMG_EINVAL, "no coarser level");
-        op.restrict_to(level, t0, t2);
-        out_level = level + 1;
-        break;
-      case STMG_OP_PROLONG: {
-        STMG_REQUIRE(level >= 1, STMG_EINVAL, "no finer level");
-        launch_fill(t2, (int64_t)op.ne(level - 1) * op.W(level - 1), 0.0, s);
-        op.prolong_add(level - 1, t0, t2);
-        out_level = level - 1;
-        break;
-      }
-      default:
-        fail(STMG_EINVAL, "unknown op");
+    launch_abi_to_internal(n, h->levels[level].N, h->q, n, md.d_map_level, in_dev, t0, s);
+    if (needs_in2) launch_abi_to_internal(n, h->levels[level].N, h->q, n, md.d_map_level, in2_dev, t1, s);
+    // the slab solve of the precision form's coarsest level is its FP64 solve
+    if (!prec || (last && op_code == STMG_OP_SLAB_SOLVE)) {
+      apply_op<double>(h, level, op_code, t0, t1, t2);
+    } else {
+      float *f0 = tmp_buf32(h, 0), *f1 = tmp_buf32(h, 1), *f2 = tmp_buf32(h, 2);
+      launch_to_float(n_in, t0, f0, s);
+      if (needs_in2) launch_to_float(n_in, t1, f1, s);
+      apply_op<float>(h, level, op_code, f0, f1, f2);
+      launch_to_double(n_out, f2, t2, s);
     }
     MeshData &mo = op.mesh(out_level);
     const int32_t no = op.ne(out_level);

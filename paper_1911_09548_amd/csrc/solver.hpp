@@ -24,7 +24,8 @@ struct DevBuf {
 // Device copy of one factor plus its solve plan.
 struct DevFactor {
   bool is_complex = false;
-  FactorDev f{};
+  FactorDev f{};                 // FP64 panels (null when only FP32 is kept)
+  FactorDev f32{};               // FP32 panels of the precision form (same plan)
   SolvePlan plan{};
   int64_t u_rows = 0;            // sum of r_s
   int64_t factor_bytes = 0;
@@ -43,6 +44,7 @@ struct MeshData {
   int64_t *d_ptr = nullptr;
   int32_t *d_col = nullptr;
   double *d_mval = nullptr, *d_kval = nullptr;
+  float *d_mval32 = nullptr, *d_kval32 = nullptr;
   int32_t *d_head = nullptr, *d_tail = nullptr;  // G: edge -> vertex (internal), -1 boundary
   int64_t *d_gt_ptr = nullptr;                   // G^T CSR over internal vertices
   int32_t *d_gt_edge = nullptr;
@@ -67,9 +69,11 @@ struct LevelData {
   std::unique_ptr<HostFactor<double>> slab_host_r;
   std::unique_ptr<HostFactor<cplx>> slab_host_c;
   DevFactor slab;
-  // device vectors (internal layout)
+  // device vectors (internal layout): FP64, and FP32 for the precision form
   double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *u = nullptr;
   double *g = nullptr, *zn = nullptr, *un = nullptr;
+  float *x32 = nullptr, *b32 = nullptr, *w32 = nullptr, *z32 = nullptr, *u32 = nullptr;
+  float *g32 = nullptr, *zn32 = nullptr, *un32 = nullptr;
 };
 
 // Event-pair timing of individual launches (see Profiler).
@@ -108,6 +112,7 @@ struct stmg_handle {
   double *d_partial = nullptr, *d_scalar = nullptr;
   int32_t n_partial = 0;
   double *d_tmp[3] = {nullptr, nullptr, nullptr};
+  float *f_tmp[3] = {nullptr, nullptr, nullptr};
   double bnorm = 0.0;
   std::vector<double> history;
   double setup_s = 0.0, solve_s = 0.0;
