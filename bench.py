@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--sample-Nt", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form measurement")
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
@@ -159,6 +160,36 @@ def main():
                  "final_rel_res": rep["rel_res"]}
         log(f"[bench] solve to 1e-8: {extra['time_to_1e-8_s']:.2f}s in {rep['cycles']} cycles")
 
+    prec = None
+    if not args.no_fp32:
+        # precision form on the same workload: FP32 V-cycle inside FP64
+        # refinement; same metric (one refinement iteration = one V-cycle)
+        solver.close()
+        del solver
+        torch.cuda.empty_cache()
+        log("[bench] setup of the precision form (FP32 smoother, FP64 refinement)")
+        t0 = time.perf_counter()
+        s32 = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=stmg.FP32_REFINED)
+        setup32 = time.perf_counter() - t0
+        s32.load(rhs)
+        s32.cycles(args.warmup)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s32.cycles(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1) / args.steps
+        t = time.perf_counter()
+        x32, rep32 = s32.solve(rhs)
+        torch.cuda.synchronize()
+        tts32 = time.perf_counter() - t
+        prec = {"form": "fp32 smoother + fp64 refinement", "value": dofs / (ms32 * 1e-3),
+                "ms_per_step": ms32, "time_to_1e-8_s": tts32, "cycles_to_1e-8": rep32["cycles"],
+                "final_rel_res": rep32["rel_res"], "setup_s": setup32}
+        log(f"[bench] precision form: {ms32:.2f} ms per iteration, 1e-8 in {rep32['cycles']} cycles "
+            f"({tts32:.2f}s)")
+        s32.close()
+
     out = {
         "metric": "space-time DOF-updates/s per V-cycle",
         "value": dofs / (ms * 1e-3),
@@ -173,6 +204,8 @@ def main():
         "roofline": roof,
         "kernels": breakdown,
     }
+    if prec:
+        out["precision_form"] = prec
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         cb = cpu_baseline(args)

@@ -225,6 +225,49 @@ int stmg_profile_count(stmg_handle *h, int32_t *n_kernels);
 int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
                      double *total_ms, double *flops, double *bytes);
 
+/* ------------------------------------------------------------- serving
+ * A continuous-batching request server. Requests (problem + rhs on the host)
+ * are set up on host worker threads, admitted to the GPU when their
+ * estimated device bytes fit the HBM budget and a slot is free, and iterated
+ * concurrently (one non-blocking HIP stream per active request, one
+ * iteration in flight each, convergence polled without blocking); results
+ * return to host memory and the request's device memory is released on its
+ * stream. Each request runs exactly the kernels it would run alone, in the
+ * same order with deterministic reductions, so its result does not depend
+ * on the mix. Thread-safe; the calling thread never blocks on the GPU except
+ * in stmg_server_wait. */
+typedef struct stmg_server stmg_server;
+typedef struct {
+  int64_t hbm_budget;            /* device bytes the server may hold; <= 0: 90% of free memory */
+  int32_t max_active;            /* requests on the GPU at once (default 16) */
+  int32_t setup_threads;         /* host setup workers (default 4) */
+} stmg_server_options;
+typedef struct {
+  int64_t submitted, completed, failed, active, pending;
+  double p50_s, p99_s, mean_s;   /* latency from submit to result ready (completed requests) */
+  double throughput_req_s;       /* completed / (last completion - first submission) */
+  double throughput_dofs;        /* sum over completed of n_e N_t (p_t+1) x cycles, same span */
+  int64_t hbm_reserved, hbm_peak, hbm_budget;
+} stmg_server_stats_t;
+
+void stmg_server_default_options(stmg_server_options *opt);
+int stmg_server_create(const stmg_server_options *opt, stmg_server **out);
+/* Copies the problem (all arrays), options and rhs [Nt][pt+1][n_edges] (and u0
+ * [n_edges], may be NULL) from host memory; returns a ticket at once. */
+int stmg_submit(stmg_server *s, const stmg_problem *prob, const stmg_options *opt, const double *rhs_host,
+                const double *u0_host, uint64_t *ticket);
+/* STMG_EAGAIN while the request is queued or running. Otherwise copies the
+ * solution (full layout, may be NULL to drop it), fills rep (res_history is
+ * NULL), forgets the ticket and returns the request's status: STMG_OK,
+ * STMG_ENOTCONV (x is the last iterate), STMG_ENOMEM (larger than the
+ * budget), STMG_EINVAL, STMG_ENUMERIC or STMG_EHIP. */
+int stmg_poll(stmg_server *s, uint64_t ticket, double *x_host, stmg_report *rep);
+/* Blocks until the request has finished or timeout_s passed (STMG_EAGAIN). */
+int stmg_server_wait(stmg_server *s, uint64_t ticket, double timeout_s);
+int stmg_server_stats(stmg_server *s, stmg_server_stats_t *stats);
+/* Stops the threads, waits for in-flight device work and frees everything. */
+void stmg_server_destroy(stmg_server *s);
+
 /* Host copy of a level's factor (host_only handles): which = 0 slab block
  * (complex for pt = 1: values interleaved re, im), 1 nodal matrix K_n.
  * Layout as used by the solves: DOF new = perm^{-1}(old) in nested-dissection

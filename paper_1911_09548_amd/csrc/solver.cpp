@@ -38,20 +38,30 @@ void hip_check(hipError_t e, const char *what) {
   fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Handles owned by the server allocate stream-ordered (hipMallocAsync on
+// their own stream) so that allocation and release never wait for other
+// requests' work; other handles use hipMalloc.
 template <typename T>
 T *dev_alloc(stmg_handle *h, size_t count) {
   if (count == 0) count = 1;
   void *p = nullptr;
-  hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  if (h->stream_ordered)
+    hip_check(hipMallocAsync(&p, count * sizeof(T), h->stream), "hipMallocAsync");
+  else
+    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
   h->bufs.push_back({p, count * sizeof(T)});
   h->device_bytes += (int64_t)(count * sizeof(T));
   return static_cast<T *>(p);
 }
 
+// Copies on the handle's stream and waits for that stream only.
 template <typename T>
 T *dev_upload(stmg_handle *h, const T *src, size_t count) {
   T *p = dev_alloc<T>(h, count);
-  if (count) hip_check(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice), "upload");
+  if (count) {
+    hip_check(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, h->stream), "upload");
+    hip_check(hipStreamSynchronize(h->stream), "upload");
+  }
   return p;
 }
 
@@ -220,7 +230,7 @@ void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, D
 }
 
 // ------------------------------------------------------------ level setup
-void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
+void setup_mesh_host(stmg_handle *h, MeshData &md) {
   SpaceLevel &S = *md.S;
   const Topo &T = S.topo;
   md.nd = nested_dissection(T, h->opt.leaf_size);
@@ -233,7 +243,12 @@ void setup_mesh(stmg_handle *h, MeshData &md, bool device) {
   }
   md.Mp = csr_permute_sym(S.M, md.sym_e.perm);
   md.Kp = csr_permute_sym(S.K, md.sym_e.perm);
-  if (!device) return;
+}
+
+void setup_mesh_device(stmg_handle *h, MeshData &md) {
+  SpaceLevel &S = *md.S;
+  const Topo &T = S.topo;
+  const bool has_nodal = T.n_int_verts() > 0;
   md.d_ptr = dev_upload(h, md.Mp.ptr);
   md.d_col = dev_upload(h, md.Mp.col);
   md.d_mval = dev_upload(h, md.Mp.val);
@@ -353,7 +368,7 @@ bool need32(const stmg_handle *h, const LevelData &L) {
   return h->opt.precision == STMG_FP32_REFINED && !is_coarsest(h, L);
 }
 
-void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
+void setup_level_factor_host(stmg_handle *h, LevelData &L) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   const SpaceLevel &S = *md.S;
   const int64_t nnz = S.M.nnz();
@@ -363,24 +378,25 @@ void setup_level_factor(stmg_handle *h, LevelData &L, bool device) {
     for (int64_t k = 0; k < nnz; ++k) v[k] = {2.0 * S.M.val[k] + L.tau * S.K.val[k], s2 * S.M.val[k]};
     L.slab_host_c = std::make_unique<HostFactor<cplx>>();
     factor_host<cplx>(md.sym_e, S.M, v, *L.slab_host_c);
-    if (device) {
-      L.slab.is_complex = true;
-      build_plan(h, md.sym_e, L.slab);
-      upload_factor<cd, cf>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L), need64(h, L),
-                            need32(h, L));
-      if (!h->opt.host_only) L.slab_host_c.reset();
-    }
   } else {
     std::vector<double> v(nnz);
     for (int64_t k = 0; k < nnz; ++k) v[k] = S.M.val[k] + L.tau * S.K.val[k];
     L.slab_host_r = std::make_unique<HostFactor<double>>();
     factor_host<double>(md.sym_e, S.M, v, *L.slab_host_r);
-    if (device) {
-      build_plan(h, md.sym_e, L.slab);
-      upload_factor<double, float>(h, md.sym_e, *L.slab_host_r, L.slab, slab_transpose(h, L), need64(h, L),
-                                   need32(h, L));
-      if (!h->opt.host_only) L.slab_host_r.reset();
-    }
+  }
+}
+
+void setup_level_factor_device(stmg_handle *h, LevelData &L) {
+  MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+  build_plan(h, md.sym_e, L.slab);
+  if (h->pt == 1) {
+    L.slab.is_complex = true;
+    upload_factor<cd, cf>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L), need64(h, L), need32(h, L));
+    L.slab_host_c.reset();
+  } else {
+    upload_factor<double, float>(h, md.sym_e, *L.slab_host_r, L.slab, slab_transpose(h, L), need64(h, L),
+                                 need32(h, L));
+    L.slab_host_r.reset();
   }
 }
 
@@ -711,7 +727,11 @@ void destroy_handle(stmg_handle *h) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : h->prof_state.pool) (void)hipEventDestroy(e);
-  for (auto &b : h->bufs) (void)hipFree(b.p);
+  if (h->stream_ordered) {
+    for (auto &b : h->bufs) (void)hipFreeAsync(b.p, h->stream);
+  } else {
+    for (auto &b : h->bufs) (void)hipFree(b.p);
+  }
   delete h;
 }
 
@@ -773,6 +793,159 @@ void prof_collect(stmg_handle *h) {
 }
 }  // namespace
 
+// ============================================================ setup phases
+// Host phase: validation, topology, FP64 assembly, hierarchy (eq. (3)),
+// orderings, symbolic and numeric factorisations. No HIP calls; safe to run
+// on worker threads.
+stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt) {
+  STMG_REQUIRE(prob, STMG_EINVAL, "null argument");
+  STMG_REQUIRE(prob->Nt >= 1 && (prob->Nt & (prob->Nt - 1)) == 0, STMG_EINVAL, "Nt must be a power of two");
+  STMG_REQUIRE(prob->pt == 0 || prob->pt == 1, STMG_EINVAL, "pt must be 0 or 1");
+  STMG_REQUIRE(prob->T > 0 && std::isfinite(prob->T), STMG_EINVAL, "T must be > 0");
+  const double t0 = wall_time();
+  std::unique_ptr<stmg_handle> h(new stmg_handle());
+  if (opt)
+    h->opt = *opt;
+  else
+    stmg_default_options(&h->opt);
+  STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
+  STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
+               "unknown precision form");
+  if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
+  STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
+               "gemm_rows must be 0, 32 or 64");
+  if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
+  h->pt = prob->pt;
+  h->q = prob->pt + 1;
+  h->Nt = prob->Nt;
+  h->T = prob->T;
+  h->space = build_space_levels(*prob);
+  // space-time levels: halve N; coarsen space where eq. (3) holds
+  LevelData L0;
+  L0.mesh = 0;
+  L0.N = prob->Nt;
+  L0.tau = prob->T / prob->Nt;
+  h->levels.push_back(std::move(L0));
+  while (h->levels.back().N > 1) {
+    LevelData &c = h->levels.back();
+    c.lambda = h->space[c.mesh].anisotropy(c.tau);
+    const bool sp = h->opt.allow_space_coarsening && c.mesh + 1 < (int32_t)h->space.size() &&
+                    c.lambda >= h->opt.lambda_crit;
+    LevelData n;
+    n.mesh = sp ? c.mesh + 1 : c.mesh;
+    n.N = c.N / 2;
+    n.tau = 2.0 * c.tau;
+    h->levels.push_back(std::move(n));
+  }
+  h->levels.back().lambda = h->space[h->levels.back().mesh].anisotropy(h->levels.back().tau);
+  const int32_t used = h->levels.back().mesh + 1;
+  h->mesh_slot.assign(h->space.size(), -1);
+  h->meshes.resize(used);
+  if (verbose()) fprintf(stderr, "[stmg] assembly and hierarchy %.2fs\n", wall_time() - t0);
+  for (int32_t j = 0; j < used; ++j) {
+    h->mesh_slot[j] = j;
+    h->meshes[j].index = j;
+    h->meshes[j].S = &h->space[j];
+    setup_mesh_host(h.get(), h->meshes[j]);
+    if (verbose())
+      fprintf(stderr, "[stmg] mesh %d: %d edges, slab nnz(L) %.3e, %d supernodes (%.2fs)\n", j,
+              h->meshes[j].S->topo.n_int_edges(), (double)h->meshes[j].sym_e.nnz_L, h->meshes[j].sym_e.ns,
+              wall_time() - t0);
+  }
+  for (size_t l = 0; l < h->levels.size(); ++l) {
+    LevelData &L = h->levels[l];
+    setup_level_factor_host(h.get(), L);
+    if (verbose())
+      fprintf(stderr, "[stmg] level %zu (mesh %d, N %d, tau %.4g, lambda %.3g) factored (%.2fs)\n", l, L.mesh, L.N,
+              L.tau, L.lambda, wall_time() - t0);
+  }
+  h->setup_s = wall_time() - t0;
+  return h.release();
+}
+
+// Device bytes the device phase will allocate (vectors, factors, patterns),
+// from host data; used by the server's admission control. Plans and small
+// index arrays are covered by a 5% margin.
+int64_t estimate_device_bytes(const stmg_handle *h) {
+  const bool prec = h->opt.precision == STMG_FP32_REFINED;
+  int64_t bytes = 0;
+  for (const auto &md : h->meshes) {
+    const int64_t nnz = md.Mp.nnz(), ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
+    bytes += nnz * (4 + 8 + 8 + (prec ? 8 : 0)) + 8 * (ne + 1) + 24 * ne + 40 * nv;
+    const int64_t pn = md.sym_v.panel_entries;
+    bytes += pn * 8 * 2 + (prec ? pn * 4 * 2 : 0);
+  }
+  for (size_t l = 0; l < h->levels.size(); ++l) {
+    const LevelData &L = h->levels[l];
+    const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    const int64_t W = (int64_t)L.N * h->q, ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
+    const int64_t scal = h->pt == 1 ? 16 : 8;
+    const int64_t pe = md.sym_e.panel_entries * (slab_transpose(h, L) ? 2 : 1);
+    if (need64(h, L)) bytes += pe * scal;
+    if (need32(h, L)) bytes += pe * scal / 2;
+    const int64_t urow = md.sym_e.rptr[md.sym_e.ns];
+    const bool last = l + 1 == h->levels.size();
+    if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + md.sym_v.rptr[md.sym_v.ns]);
+    if (prec) {
+      bytes += 4 * W * (4 * ne + urow + 2 * nv + md.sym_v.rptr[md.sym_v.ns]);
+      if (l == 0 || last) bytes += 8 * W * 3 * ne;
+      if (last) bytes += 8 * W * (ne + urow);
+    }
+  }
+  const LevelData &L0 = h->levels[0];
+  const int64_t v0 = (int64_t)h->meshes[0].S->topo.n_int_edges() * L0.N * h->q * 8;
+  bytes += std::min<int64_t>((int64_t)256 << 20, 4 * v0);  // split-K workspace
+  return bytes + bytes / 20 + (1 << 20);
+}
+
+// Device phase: uploads, plans and workspaces on `stream` (no device-wide
+// synchronisation, so other handles' work keeps running).
+void setup_device_phase(stmg_handle *h, hipStream_t stream) {
+  const double t0 = wall_time();
+  h->stream = stream;
+  const int32_t used = (int32_t)h->meshes.size();
+  for (int32_t j = 0; j < used; ++j) {
+    setup_mesh_device(h, h->meshes[j]);
+    if (j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
+  }
+  for (size_t l = 0; l < h->levels.size(); ++l) {
+    setup_level_factor_device(h, h->levels[l]);
+    alloc_level_vectors(h, h->levels[l], l == 0);
+  }
+  // split-K partial sums of the backward solves, shared by all factors
+  const LevelData &L0 = h->levels[0];
+  const int64_t v0 = (int64_t)h->space[0].topo.n_int_edges() * L0.N * h->q * 8;
+  const int64_t ws_bytes = std::min<int64_t>((int64_t)256 << 20, 4 * v0);
+  void *ws = dev_alloc<char>(h, (size_t)ws_bytes);
+  for (auto &L : h->levels) {
+    L.slab.plan.splitk_ws = ws;
+    L.slab.plan.splitk_bytes = ws_bytes;
+  }
+  for (auto &m : h->meshes) {
+    m.nodal.plan.splitk_ws = ws;
+    m.nodal.plan.splitk_bytes = ws_bytes;
+  }
+  h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L0.N * h->q, h->q) + 4096;
+  h->d_partial = dev_alloc<double>(h, h->n_partial);
+  h->d_scalar = dev_alloc<double>(h, 8192);
+  hip_check(hipStreamSynchronize(stream), "setup");
+  h->setup_s += wall_time() - t0;
+}
+
+namespace stmg {
+namespace internal {
+stmg_handle *setup_host(const stmg_problem *prob, const stmg_options *opt) { return setup_host_phase(prob, opt); }
+int64_t estimate_bytes(const stmg_handle *h) { return estimate_device_bytes(h); }
+void setup_device(stmg_handle *h, hipStream_t stream) { setup_device_phase(h, stream); }
+void iteration(stmg_handle *h, double *dst_norm2) {
+  solver_iteration(h, dst_norm2);
+  check_launch();
+}
+void destroy(stmg_handle *h) { destroy_handle(h); }
+const char *last_error() { return g_err.c_str(); }
+}  // namespace internal
+}  // namespace stmg
+
 // =================================================================== ABI
 extern "C" {
 
@@ -813,95 +986,14 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
   if (out) *out = nullptr;
   stmg_handle *h = nullptr;
   int rc = guard([&] {
-    STMG_REQUIRE(prob && out, STMG_EINVAL, "null argument");
-    STMG_REQUIRE(prob->Nt >= 1 && (prob->Nt & (prob->Nt - 1)) == 0, STMG_EINVAL, "Nt must be a power of two");
-    STMG_REQUIRE(prob->pt == 0 || prob->pt == 1, STMG_EINVAL, "pt must be 0 or 1");
-    STMG_REQUIRE(prob->T > 0 && std::isfinite(prob->T), STMG_EINVAL, "T must be > 0");
-    const double t0 = wall_time();
-    h = new stmg_handle();
-    if (opt)
-      h->opt = *opt;
-    else
-      stmg_default_options(&h->opt);
-    STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
-    STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
-                 "unknown precision form");
-    if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
-    STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
-                 "gemm_rows must be 0, 32 or 64");
-    if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
-    h->stream = static_cast<hipStream_t>(stream);
-    h->pt = prob->pt;
-    h->q = prob->pt + 1;
-    h->Nt = prob->Nt;
-    h->T = prob->T;
-    const bool device = !h->opt.host_only;
-    if (device) {
+    STMG_REQUIRE(out, STMG_EINVAL, "null argument");
+    h = setup_host_phase(prob, opt);
+    if (!h->opt.host_only) {
       int ndev = 0;
       hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
       STMG_REQUIRE(ndev > 0, STMG_EHIP, "no HIP device");
+      setup_device_phase(h, static_cast<hipStream_t>(stream));
     }
-    h->space = build_space_levels(*prob);
-    // space-time levels: halve N; coarsen space where eq. (3) holds
-    LevelData L0;
-    L0.mesh = 0;
-    L0.N = prob->Nt;
-    L0.tau = prob->T / prob->Nt;
-    h->levels.push_back(std::move(L0));
-    while (h->levels.back().N > 1) {
-      LevelData &c = h->levels.back();
-      c.lambda = h->space[c.mesh].anisotropy(c.tau);
-      const bool sp = h->opt.allow_space_coarsening && c.mesh + 1 < (int32_t)h->space.size() &&
-                      c.lambda >= h->opt.lambda_crit;
-      LevelData n;
-      n.mesh = sp ? c.mesh + 1 : c.mesh;
-      n.N = c.N / 2;
-      n.tau = 2.0 * c.tau;
-      h->levels.push_back(std::move(n));
-    }
-    h->levels.back().lambda = h->space[h->levels.back().mesh].anisotropy(h->levels.back().tau);
-    const int32_t used = h->levels.back().mesh + 1;
-    h->mesh_slot.assign(h->space.size(), -1);
-    h->meshes.resize(used);
-    if (verbose()) fprintf(stderr, "[stmg] assembly and hierarchy %.2fs\n", wall_time() - t0);
-    for (int32_t j = 0; j < used; ++j) {
-      h->mesh_slot[j] = j;
-      h->meshes[j].index = j;
-      h->meshes[j].S = &h->space[j];
-      setup_mesh(h, h->meshes[j], device);
-      if (device && j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
-      if (verbose())
-        fprintf(stderr, "[stmg] mesh %d: %d edges, slab nnz(L) %.3e, %d supernodes (%.2fs)\n", j,
-                h->meshes[j].S->topo.n_int_edges(), (double)h->meshes[j].sym_e.nnz_L, h->meshes[j].sym_e.ns,
-                wall_time() - t0);
-    }
-    for (size_t l = 0; l < h->levels.size(); ++l) {
-      LevelData &L = h->levels[l];
-      setup_level_factor(h, L, device);
-      if (device) alloc_level_vectors(h, L, l == 0);
-      if (verbose())
-        fprintf(stderr, "[stmg] level %zu (mesh %d, N %d, tau %.4g, lambda %.3g) factored (%.2fs)\n", l, L.mesh,
-                L.N, L.tau, L.lambda, wall_time() - t0);
-    }
-    if (device) {
-      // split-K partial sums of the backward solves, shared by all factors
-      const int64_t ws_bytes = (int64_t)256 << 20;
-      void *ws = dev_alloc<char>(h, (size_t)ws_bytes);
-      for (auto &L : h->levels) {
-        L.slab.plan.splitk_ws = ws;
-        L.slab.plan.splitk_bytes = ws_bytes;
-      }
-      for (auto &m : h->meshes) {
-        m.nodal.plan.splitk_ws = ws;
-        m.nodal.plan.splitk_bytes = ws_bytes;
-      }
-      const LevelData &L = h->levels[0];
-      h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L.N * h->q, h->q) + 4096;
-      h->d_partial = dev_alloc<double>(h, h->n_partial);
-      h->d_scalar = dev_alloc<double>(h, 8192);
-      hip_check(hipDeviceSynchronize(), "setup");
-    }
-    h->setup_s = wall_time() - t0;
   });
   if (rc != STMG_OK) {
     destroy_handle(h);

@@ -101,6 +101,7 @@ struct ProfState {
 struct stmg_handle {
   stmg_options opt{};
   hipStream_t stream = nullptr;
+  bool stream_ordered = false;   // allocations via hipMallocAsync on `stream`
   int32_t pt = 1, q = 2, Nt = 1;
   double T = 1.0;
   std::vector<stmg::SpaceLevel> space;
@@ -121,3 +122,17 @@ struct stmg_handle {
   int32_t cycles = 0;
   double rel_res = 0.0;
 };
+
+namespace stmg {
+namespace internal {
+// Phases of stmg_setup and one solver iteration, for the request server.
+// All throw StmgError on failure.
+stmg_handle *setup_host(const stmg_problem *prob, const stmg_options *opt);  // no HIP calls
+int64_t estimate_bytes(const stmg_handle *h);                                // device bytes the next phase needs
+void setup_device(stmg_handle *h, hipStream_t stream);                       // uploads on `stream`
+void iteration(stmg_handle *h, double *dst_norm2);                          // enqueue one iteration on h->stream
+void destroy(stmg_handle *h);
+const char *last_error();
+}  // namespace internal
+}  // namespace stmg
+

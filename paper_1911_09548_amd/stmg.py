@@ -66,6 +66,17 @@ class LevelInfo(C.Structure):
                 ("lambda_", C.c_double)]
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("setup_threads", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("active", C.c_int64), ("pending", C.c_int64), ("p50_s", C.c_double), ("p99_s", C.c_double),
+                ("mean_s", C.c_double), ("throughput_req_s", C.c_double), ("throughput_dofs", C.c_double),
+                ("hbm_reserved", C.c_int64), ("hbm_peak", C.c_int64), ("hbm_budget", C.c_int64)]
+
+
 _lib = None
 
 
@@ -101,13 +112,21 @@ def lib():
         L.stmg_export_matrix.argtypes = [vp, ip, ip, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), vp, vp, vp]
         L.stmg_export_factor.argtypes = [vp, ip, ip] + [vp] * 11
+        L.stmg_server_default_options.argtypes = [C.POINTER(ServerOptions)]
+        L.stmg_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(vp)]
+        L.stmg_submit.argtypes = [vp, C.POINTER(_Problem), C.POINTER(Options), vp, vp, C.POINTER(C.c_uint64)]
+        L.stmg_poll.argtypes = [vp, C.c_uint64, vp, C.POINTER(Report)]
+        L.stmg_server_wait.argtypes = [vp, C.c_uint64, C.c_double]
+        L.stmg_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.stmg_server_destroy.argtypes = [vp]
         L.stmg_profile.argtypes = [vp, ip]
         L.stmg_profile_count.argtypes = [vp, C.POINTER(C.c_int32)]
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_residual", "stmg_level_apply",
                      "stmg_export_matrix", "stmg_export_factor", "stmg_profile", "stmg_profile_count",
-                     "stmg_profile_get"):
+                     "stmg_profile_get", "stmg_server_create", "stmg_submit", "stmg_poll", "stmg_server_wait",
+                     "stmg_server_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -140,32 +159,87 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _marshal_problem(problem, keep):
+    """Build the C problem struct; arrays are appended to `keep`."""
+    meshes = (_Mesh * len(problem.levels))()
+    for j, lev in enumerate(problem.levels):
+        c = np.ascontiguousarray(lev.coords, dtype=np.float64)
+        t = np.ascontiguousarray(lev.tets, dtype=np.int32)
+        keep += [c, t]
+        meshes[j].n_vertices = c.shape[0]
+        meshes[j].coords = c.ctypes.data_as(C.POINTER(C.c_double))
+        meshes[j].n_tets = t.shape[0]
+        meshes[j].tets = t.ctypes.data_as(C.POINTER(C.c_int32))
+        if j > 0:
+            vp = np.ascontiguousarray(lev.vertex_parent, dtype=np.int32)
+            tp = np.ascontiguousarray(lev.tet_parent, dtype=np.int32)
+            keep += [vp, tp]
+            meshes[j].vertex_parent = vp.ctypes.data_as(C.POINTER(C.c_int32))
+            meshes[j].tet_parent = tp.ctypes.data_as(C.POINTER(C.c_int32))
+    sig = np.ascontiguousarray(problem.sigma, dtype=np.float64)
+    nu = np.ascontiguousarray(problem.nu, dtype=np.float64)
+    keep += [sig, nu, meshes]
+    return _Problem(len(problem.levels), meshes, sig.ctypes.data_as(C.POINTER(C.c_double)),
+                    nu.ctypes.data_as(C.POINTER(C.c_double)), float(problem.T), int(problem.Nt),
+                    int(problem.pt))
+
+
+class Server:
+    """Continuous-batching request server (see stmg_server_* in include/stmg.h)."""
+
+    def __init__(self, hbm_budget=0, max_active=16, setup_threads=4):
+        o = ServerOptions(int(hbm_budget), int(max_active), int(setup_threads))
+        h = C.c_void_p()
+        _check(lib().stmg_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+
+    def submit(self, problem, rhs, u0=None, **opts):
+        """rhs: host array [Nt][pt+1][n_edges] (float64); returns a ticket."""
+        keep = []
+        p = _marshal_problem(problem, keep)
+        o = default_options(**opts)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+        t = C.c_uint64()
+        _check(lib().stmg_submit(self._h, C.byref(p), C.byref(o), C.c_void_p(rhs.ctypes.data),
+                                 None if u0 is None else C.c_void_p(u0.ctypes.data), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout=600.0):
+        return lib().stmg_server_wait(self._h, ticket, float(timeout)) == STMG_OK
+
+    def poll(self, ticket, shape=None):
+        """(status, x or None, report); status STMG_EAGAIN while running."""
+        x = np.zeros(shape, dtype=np.float64) if shape is not None else None
+        rep = Report()
+        rc = lib().stmg_poll(self._h, ticket, None if x is None else C.c_void_p(x.ctypes.data), C.byref(rep))
+        if rc == STMG_EAGAIN:
+            return rc, None, None
+        return rc, x, dict(cycles=rep.cycles, rel_res=rep.rel_res, setup_s=rep.setup_s, solve_s=rep.solve_s)
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().stmg_server_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stmg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One space-time problem set up on the GPU (or host-only for inspection)."""
 
     def __init__(self, problem, stream=None, **opts):
         self._keep = []
-        meshes = (_Mesh * len(problem.levels))()
-        for j, lev in enumerate(problem.levels):
-            c = np.ascontiguousarray(lev.coords, dtype=np.float64)
-            t = np.ascontiguousarray(lev.tets, dtype=np.int32)
-            self._keep += [c, t]
-            meshes[j].n_vertices = c.shape[0]
-            meshes[j].coords = c.ctypes.data_as(C.POINTER(C.c_double))
-            meshes[j].n_tets = t.shape[0]
-            meshes[j].tets = t.ctypes.data_as(C.POINTER(C.c_int32))
-            if j > 0:
-                vp = np.ascontiguousarray(lev.vertex_parent, dtype=np.int32)
-                tp = np.ascontiguousarray(lev.tet_parent, dtype=np.int32)
-                self._keep += [vp, tp]
-                meshes[j].vertex_parent = vp.ctypes.data_as(C.POINTER(C.c_int32))
-                meshes[j].tet_parent = tp.ctypes.data_as(C.POINTER(C.c_int32))
-        sig = np.ascontiguousarray(problem.sigma, dtype=np.float64)
-        nu = np.ascontiguousarray(problem.nu, dtype=np.float64)
-        self._keep += [sig, nu, meshes]
-        p = _Problem(len(problem.levels), meshes, sig.ctypes.data_as(C.POINTER(C.c_double)),
-                     nu.ctypes.data_as(C.POINTER(C.c_double)), float(problem.T), int(problem.Nt),
-                     int(problem.pt))
+        p = _marshal_problem(problem, self._keep)
         self.options = default_options(**opts)
         self.host_only = bool(self.options.host_only)
         if stream is None and not self.host_only:

@@ -1,0 +1,139 @@
+"""Serving form on the GPU: continuous batching of space-time solves.
+
+* A mix of requests with different meshes, horizons, DG degrees and
+  materials runs concurrently; each result is bitwise the result of the same
+  request run alone (tolerance 0: the same kernels run in the same order with
+  deterministic reductions) and equals the plain single-problem solver's.
+* Every result meets the 1e-8 relative residual by the oracle's residual.
+* Admission respects the HBM budget; requests larger than the budget are
+  rejected with STMG_ENOMEM; failures (max_cycles, NaN data) come back as
+  status codes.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_09548_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MIX = [  # (n, Nt, pt, seed)
+    (4, 16, 1, 101), (6, 8, 0, 102), (8, 32, 1, 103), (4, 64, 0, 104),
+    (8, 16, 0, 105), (6, 32, 1, 106), (8, 8, 1, 107), (4, 8, 1, 108),
+]
+
+
+def _request(n, Nt, pt, seed):
+    if n % 4 == 0:
+        prob = inputs.config_request(n, Nt, pt, seed)
+    else:
+        prob = inputs.config_block_random(n=n, Nt=Nt, pt=pt, seed=seed, block_hexes=max(1, n // 2),
+                                          sigma_range=(1e-2, 1e4), nu_range=(1e-3, 100.0))
+    E = inputs.count_edges(prob.levels[0].tets, prob.levels[0].coords.shape[0])
+    rhs = np.random.default_rng(seed).standard_normal((Nt, pt + 1, E))
+    return prob, rhs
+
+
+@pytest.fixture(scope="module")
+def results():
+    from paper_1911_09548_amd import stmg
+    reqs = [_request(*m) for m in MIX]
+    opts = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
+    # in the mix: all submitted at once, four on the GPU together
+    srv = stmg.Server(max_active=4, setup_threads=4)
+    tickets = [srv.submit(p, r, **opts) for p, r in reqs]
+    mix = []
+    for (p, r), t in zip(reqs, tickets):
+        assert srv.wait(t, 300)
+        rc, x, rep = srv.poll(t, r.shape)
+        mix.append((rc, x, rep))
+    stats = srv.stats()
+    srv.close()
+    # alone: one request on the server at a time
+    srv1 = stmg.Server(max_active=1, setup_threads=1)
+    alone = []
+    for p, r in reqs:
+        t = srv1.submit(p, r, **opts)
+        assert srv1.wait(t, 300)
+        alone.append(srv1.poll(t, r.shape))
+    srv1.close()
+    print(f"\n[serving] stats {stats}", flush=True)
+    return reqs, mix, alone, stats
+
+
+def test_every_request_converges(results):
+    from paper_1911_09548_amd import stmg
+    from oracle.vcycle import SpaceTimeMultigrid
+    reqs, mix, alone, stats = results
+    assert stats["completed"] == len(MIX) and stats["failed"] == 0
+    for (p, r), (rc, x, rep) in zip(reqs, mix):
+        assert rc == stmg.STMG_OK, rc
+        ora = SpaceTimeMultigrid(p)
+        b = ora.to_interior(r)
+        rr = np.linalg.norm(ora.levels[0].residual(ora.to_interior(x), b)) / np.linalg.norm(b)
+        print(f"[serving] n={p.levels[0].n} Nt={p.Nt} pt={p.pt}: cycles {rep['cycles']} oracle residual {rr:.2e}")
+        assert rr <= 1e-8
+
+
+def test_alone_equals_mix_bitwise(results):
+    reqs, mix, alone, stats = results
+    for (rc_m, x_m, _), (rc_a, x_a, _) in zip(mix, alone):
+        assert rc_m == rc_a
+        assert np.array_equal(x_m, x_a)
+
+
+def test_server_equals_plain_solver(results):
+    import torch
+    from paper_1911_09548_amd import stmg
+    reqs, mix, alone, stats = results
+    for (p, r), (rc, x, rep) in list(zip(reqs, mix))[:3]:
+        s = stmg.Solver(p, precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
+        xs, rep_s = s.solve(torch.from_numpy(r).cuda())
+        assert rep_s["cycles"] == rep["cycles"]
+        assert np.array_equal(xs.cpu().numpy(), x)
+        s.close()
+
+
+def test_latency_stats_reported(results):
+    reqs, mix, alone, stats = results
+    assert 0 < stats["p50_s"] <= stats["p99_s"]
+    assert stats["throughput_req_s"] > 0 and stats["throughput_dofs"] > 0
+    assert stats["hbm_peak"] <= stats["hbm_budget"]
+
+
+def test_budget_admission_and_rejection():
+    from paper_1911_09548_amd import stmg
+    p, r = _request(8, 16, 1, 201)
+    # a budget below one request's needs: rejected, not crashed
+    srv = stmg.Server(hbm_budget=1 << 20, max_active=4)
+    t = srv.submit(p, r, precision=stmg.FP32_REFINED)
+    assert srv.wait(t, 120)
+    rc, x, rep = srv.poll(t, r.shape)
+    assert rc == stmg.STMG_ENOMEM
+    srv.close()
+    # a small budget: requests are admitted as memory frees, peak stays below
+    srv = stmg.Server(hbm_budget=64 << 20, max_active=8)
+    ts = [srv.submit(*_request(8, 16, 1, 300 + k), precision=stmg.FP32_REFINED) for k in range(4)]
+    for t in ts:
+        assert srv.wait(t, 300)
+        rc, x, rep = srv.poll(t, r.shape)
+        assert rc in (stmg.STMG_OK, stmg.STMG_ENOMEM)
+    st = srv.stats()
+    assert st["hbm_peak"] <= st["hbm_budget"]
+    srv.close()
+
+
+def test_failures_are_status_codes():
+    from paper_1911_09548_amd import stmg
+    p, r = _request(4, 16, 1, 401)
+    srv = stmg.Server(max_active=2)
+    t1 = srv.submit(p, r, precision=stmg.FP32_REFINED, max_cycles=1)
+    bad = r.copy()
+    bad[0, 0, :] = np.nan      # whole first slab: interior edges included
+    t2 = srv.submit(p, bad, precision=stmg.FP32_REFINED)
+    for t in (t1, t2):
+        assert srv.wait(t, 120)
+    rc1, x1, rep1 = srv.poll(t1, r.shape)
+    rc2, x2, rep2 = srv.poll(t2, r.shape)
+    assert rc1 == stmg.STMG_ENOTCONV and rep1["cycles"] == 1
+    assert rc2 == stmg.STMG_ENUMERIC
+    srv.close()
