@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form measurement")
+    ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
+                    help="first run one plain device copy of this many MiB (read + write), so that "
+                         "hardware byte counters can be scaled by a kernel of known traffic")
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
@@ -101,6 +104,15 @@ def main():
     from paper_1911_09548_amd import inputs, stmg
 
     torch.cuda.set_device(0)
+    if args.hbm_calibrate > 0:
+        n = args.hbm_calibrate << 17  # doubles
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+        del src, dst
     prob = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
     log(f"[bench] setup n={args.n} Nt={args.Nt} pt={args.pt}")
     t0 = time.perf_counter()
@@ -132,7 +144,7 @@ def main():
     kernels = solver.profile_report()
     solver.profile(False)
     log(f"[bench] {ms:.2f} ms per V-cycle, residuals {res[-1]:.2e}")
-    for k in kernels[:8]:
+    for k in kernels:
         log(f"[bench]   {k['kernel']:28s} {k['ms'] / args.steps:8.2f} ms/step {k['launches'] // args.steps:5d} launches/step "
             f"{k['flops'] / (k['ms'] * 1e-3) / 1e12:7.2f} TFLOP/s {k['bytes'] / (k['ms'] * 1e-3) / 1e9:8.1f} GB/s")
     top = kernels[0]

@@ -99,11 +99,13 @@ typedef struct {
   double rtol;                   /* relative residual target of stmg_solve, default 1e-8 */
   int32_t max_cycles;            /* cap of stmg_solve, default 100 */
   int32_t host_only;             /* 1: build host data only (no device), for tests */
-  int32_t factor_on_device;      /* 1 (default): numeric factorisation on the GPU */
+  int32_t stream_chunk;          /* residual row segment: max values per lane, 0 = default, 1..16 */
+  int32_t row_schedule;          /* residual row visiting order: 0 = Morton order of edge midpoints, 1 = storage order */
   int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
   int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */
   int32_t factor_transpose;      /* also keep P^T for the backward solves: -1 auto, 0 never, 1 always */
-  int32_t gemm_splitk;           /* backward K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
+  int32_t gemm_splitk;           /* solve K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
+  int32_t device_factor;         /* 1 (default): numeric factorisation on the GPU; 0: on the host */
 } stmg_options;
 
 typedef struct {
@@ -221,6 +223,12 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
  * the residual) and bytes (each operand read once, each result written
  * once). Timing adds no synchronisation inside a cycle. */
 int stmg_profile(stmg_handle *h, int32_t enable);
+
+/* Changes the residual's launch shape after setup (same meaning and values
+ * as the stream_chunk and row_schedule options); results do not depend on
+ * it except for the summation order of the residual norm. STMG_EINVAL on an
+ * unknown value. For tuning on a live handle without a second setup. */
+int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_schedule);
 int stmg_profile_count(stmg_handle *h, int32_t *n_kernels);
 int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
                      double *total_ms, double *flops, double *bytes);
@@ -268,14 +276,15 @@ int stmg_server_stats(stmg_server *s, stmg_server_stats_t *stats);
 /* Stops the threads, waits for in-flight device work and frees everything. */
 void stmg_server_destroy(stmg_server *s);
 
-/* Host copy of a level's factor (host_only handles): which = 0 slab block
- * (complex for pt = 1: values interleaved re, im), 1 nodal matrix K_n.
+/* Host copy of a level's factor: which = 0 slab block (complex for pt = 1:
+ * values interleaved re, im), 1 nodal matrix K_n. host_only handles return
+ * the host factorisation; device handles copy their FP64 panels back from
+ * HBM (STMG_ENOSYS for levels that keep only FP32 panels).
  * Layout as used by the solves: DOF new = perm^{-1}(old) in nested-dissection
  * order; supernode s owns columns [col0[s], col0[s+1]), below-diagonal rows
  * rows[rptr[s] .. rptr[s+1]) (new numbering) and the column-major panel
  * P_s = [inv(L_ss); -L_{R,s} inv(L_ss)] at panel + panel_off[s] (scalars).
- * Pass NULL arrays to query sizes. Returns STMG_ENOSYS on device handles
- * (their factors live only in HBM). */
+ * Pass NULL arrays to query sizes. */
 int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32_t *n, int32_t *ns,
                        int64_t *n_rows_total, int64_t *n_panel, int32_t *is_complex, int32_t *perm,
                        int32_t *col0, int64_t *rptr, int32_t *rows, int64_t *panel_off, double *panel);

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libstmg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["space.cpp", "ordering.cpp", "factor.cpp"]
-HIP_SOURCES = ["kernels.hip", "solver.cpp", "server.cpp"]  # .cpp here: host code using the HIP runtime
+HIP_SOURCES = ["kernels.hip", "factor_dev.hip", "solver.cpp", "server.cpp"]  # .cpp here: host code using the HIP runtime
 
 
 def _hipcc() -> str:
@@ -53,7 +53,11 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         list(ex.map(lambda j: _compile(*j), jobs))
     tmp = OUT + ".tmp"
+    # rocBLAS (dense triangular solves and symmetric updates of the device
+    # factorisation) resolves to the copy the host process has loaded, else
+    # to the ROCm installation
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fopenmp", "-o", tmp] + [j[1] for j in jobs]
+    cmd += ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

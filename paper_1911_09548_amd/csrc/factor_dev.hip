@@ -1,0 +1,351 @@
+// Numeric multifrontal factorisation on the GPU (see factor_dev.hpp).
+#include "factor_dev.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+namespace stmg {
+
+// ------------------------------------------------------------- host plan
+void build_front_plan(const Symbolic &S, const Csr &A, FrontPlan &fp) {
+  const int32_t ns = S.ns;
+  fp.a_ptr.assign(ns + 1, 0);
+  fp.a_pos.clear();
+  fp.a_k.clear();
+  fp.uoff.assign(ns + 1, 0);
+  fp.kid_ptr.assign(ns + 1, 0);
+  fp.max_m2 = 1;
+  std::vector<int32_t> pos(S.n, -1);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t w = S.width(s), r = S.nrows(s), m = w + r;
+    const int32_t c0 = S.col0[s];
+    for (int64_t j = 0; j < w; ++j) pos[c0 + j] = (int32_t)j;
+    for (int64_t k = 0; k < r; ++k) pos[S.rows[S.rptr[s] + k]] = (int32_t)(w + k);
+    for (int64_t j = 0; j < w; ++j) {
+      const int32_t o = S.perm[c0 + j];
+      for (int64_t k = A.ptr[o]; k < A.ptr[o + 1]; ++k) {
+        const int32_t i = S.iperm[A.col[k]];
+        if (i < c0 + j) continue;  // lower triangle only
+        fp.a_pos.push_back(pos[i] + j * m);
+        fp.a_k.push_back(k);
+      }
+    }
+    fp.a_ptr[s + 1] = (int64_t)fp.a_pos.size();
+    fp.max_m2 = std::max(fp.max_m2, m * m);
+    const bool keeps_update = S.parent[s] >= 0 && r > 0;
+    fp.uoff[s + 1] = fp.uoff[s] + (keeps_update ? r * r : 0);
+  }
+  // children lists (post-order keeps children before parents)
+  for (int32_t s = 0; s < ns; ++s)
+    if (S.parent[s] >= 0) fp.kid_ptr[S.parent[s] + 1]++;
+  for (int32_t s = 0; s < ns; ++s) fp.kid_ptr[s + 1] += fp.kid_ptr[s];
+  fp.kids.assign(fp.kid_ptr[ns], 0);
+  {
+    std::vector<int32_t> nx(fp.kid_ptr.begin(), fp.kid_ptr.end() - 1);
+    for (int32_t s = 0; s < ns; ++s)
+      if (S.parent[s] >= 0) fp.kids[nx[S.parent[s]]++] = s;
+  }
+  // update row of s -> row of the parent's front
+  fp.relpos.assign(S.rows.size(), 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t p = S.parent[s];
+    if (p < 0) continue;
+    const int32_t pc0 = S.col0[p], pw = S.width(p);
+    const int32_t *pr = S.rows.data() + S.rptr[p], *pe = S.rows.data() + S.rptr[p + 1];
+    for (int64_t k = S.rptr[s]; k < S.rptr[s + 1]; ++k) {
+      const int32_t g = S.rows[k];
+      int32_t at;
+      if (g >= pc0 && g < pc0 + pw) {
+        at = g - pc0;
+      } else {
+        const int32_t *it = std::lower_bound(pr, pe, g);
+        STMG_REQUIRE(it != pe && *it == g, STMG_EINVAL, "front plan: update row not in the parent's structure");
+        at = pw + (int32_t)(it - pr);
+      }
+      fp.relpos[k] = at;
+    }
+  }
+}
+
+// --------------------------------------------------------------- kernels
+namespace {
+
+constexpr int FB = 256;  // threads per block
+
+__device__ inline double f_zero(double) { return 0.0; }
+__device__ inline cd f_zero(cd) { return {0.0, 0.0}; }
+__device__ inline double f_one(double) { return 1.0; }
+__device__ inline cd f_one(cd) { return {1.0, 0.0}; }
+__device__ inline double f_add(double a, double b) { return a + b; }
+__device__ inline cd f_add(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline double f_mul(double a, double b) { return a * b; }
+__device__ inline cd f_mul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline double f_fms(double c, double a, double b) { return c - a * b; }  // c - a b
+__device__ inline cd f_fms(cd c, cd a, cd b) {
+  return {c.re - (a.re * b.re - a.im * b.im), c.im - (a.re * b.im + a.im * b.re)};
+}
+__device__ inline double f_recip(double a) { return 1.0 / a; }
+__device__ inline cd f_recip(cd a) {
+  const double d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+__device__ inline bool f_bad_pivot(double a) { return !(a > 0.0) || !isfinite(a); }
+__device__ inline bool f_bad_pivot(cd a) {
+  return !isfinite(a.re) || !isfinite(a.im) || (a.re == 0.0 && a.im == 0.0);
+}
+__device__ inline double f_sqrt(double a) { return sqrt(a); }
+// principal square root: Re >= 0, and the sign of Im follows Im(a)
+__device__ inline cd f_sqrt(cd a) {
+  const double r = hypot(a.re, a.im);
+  if (r == 0.0) return {0.0, 0.0};
+  if (a.re >= 0.0) {
+    const double t = sqrt(0.5 * (r + a.re));
+    return {t, a.im / (2.0 * t)};
+  }
+  const double t = sqrt(0.5 * (r - a.re));
+  return {fabs(a.im) / (2.0 * t), copysign(t, a.im)};
+}
+
+template <typename T>
+__global__ __launch_bounds__(FB) void k_front_zero(T *F, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * FB;
+  for (int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x; i < n; i += stride) F[i] = f_zero(T{});
+}
+
+// F[pos[e]] += vals[k[e]]; the positions of one front are distinct
+template <typename T>
+__global__ __launch_bounds__(FB) void k_front_assemble(T *F, const int64_t *pos, const int64_t *kidx, int64_t n,
+                                                       const T *vals) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e < n) F[pos[e]] = f_add(F[pos[e]], vals[kidx[e]]);
+}
+
+// F[rel[a], rel[b]] += U[a, b] for a >= b (one child's update matrix)
+template <typename T>
+__global__ __launch_bounds__(FB) void k_extend_add(T *F, int64_t m, const T *U, int32_t r, const int32_t *rel) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int32_t a = (int32_t)(e % r), b = (int32_t)(e / r);
+  if (a < b) return;
+  T *f = F + rel[a] + (int64_t)rel[b] * m;
+  *f = f_add(*f, U[e]);
+}
+
+// In-place L L^T of the kb x kb diagonal block at A (ld), kb <= NB, in LDS.
+template <typename T>
+__global__ __launch_bounds__(FB) void k_diag_chol(T *A, int64_t ld, int kb, int32_t *flag) {
+  __shared__ T Ls[NB * NB];
+  __shared__ T dinv;
+  for (int e = threadIdx.x; e < kb * kb; e += FB) {
+    const int i = e % kb, c = e / kb;
+    Ls[e] = i >= c ? A[i + c * ld] : f_zero(T{});
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (threadIdx.x == 0) {
+      T p = Ls[j + j * kb];
+      if (f_bad_pivot(p)) {
+        flag[0] = 1;
+        p = f_one(T{});
+      }
+      const T d = f_sqrt(p);
+      Ls[j + j * kb] = d;
+      dinv = f_recip(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < kb; i += FB) Ls[i + j * kb] = f_mul(Ls[i + j * kb], dinv);
+    __syncthreads();
+    const int n = kb - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += FB) {
+      const int i = j + 1 + e % n, c = j + 1 + e / n;
+      if (i >= c) Ls[i + c * kb] = f_fms(Ls[i + c * kb], Ls[i + j * kb], Ls[c + j * kb]);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kb * kb; e += FB) {
+    const int i = e % kb, c = e / kb;
+    if (i >= c) A[i + c * ld] = Ls[e];
+  }
+}
+
+// P (w x w, ld) = identity
+template <typename T>
+__global__ __launch_bounds__(FB) void k_set_identity(T *P, int64_t ld, int32_t w) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= (int64_t)w * w) return;
+  const int32_t i = (int32_t)(e % w), c = (int32_t)(e / w);
+  P[i + c * ld] = i == c ? f_one(T{}) : f_zero(T{});
+}
+
+// strict upper triangle of the w x w block at P (ld) = 0
+template <typename T>
+__global__ __launch_bounds__(FB) void k_zero_upper(T *P, int64_t ld, int32_t w) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= (int64_t)w * w) return;
+  const int32_t i = (int32_t)(e % w), c = (int32_t)(e / w);
+  if (i < c) P[i + c * ld] = f_zero(T{});
+}
+
+// U (r x r, lower, ld r) = F[w:, w:] (the update matrix)
+template <typename T>
+__global__ __launch_bounds__(FB) void k_take_update(const T *F, int64_t m, int32_t w, int32_t r, T *U) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int32_t a = (int32_t)(e % r), b = (int32_t)(e / r);
+  U[e] = a >= b ? F[(w + a) + (int64_t)(w + b) * m] : f_zero(T{});
+}
+
+__device__ inline void cvt(double a, double &b) { b = a; }
+__device__ inline void cvt(double a, float &b) { b = (float)a; }
+__device__ inline void cvt(cd a, cd &b) { b = a; }
+__device__ inline void cvt(cd a, cf &b) { b = {(float)a.re, (float)a.im}; }
+
+// Conversion / transposition of all panels: entry e lies in supernode s
+// (binary search over panel_off); P_s is m x w column-major, P_s^T w x m.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(FB) void k_convert_panels(const TS *in, TD *out, TD *out_t, const int64_t *off,
+                                                       const int32_t *width, int32_t ns, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= n) return;
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  TD v;
+  cvt(in[e], v);
+  if (out) out[e] = v;
+  if (out_t) {
+    const int64_t w = width[lo], m = (off[lo + 1] - off[lo]) / w, o = e - off[lo];
+    const int64_t i = o % m, k = o / m;
+    out_t[off[lo] + k + i * w] = v;
+  }
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + FB - 1) / FB); }
+
+void rb_check(rocblas_status st, const char *what) {
+  if (st != rocblas_status_success)
+    fail(STMG_EHIP, std::string("rocBLAS ") + what + " failed: " + rocblas_status_to_string(st));
+}
+
+// Typed rocBLAS calls (column-major, host-side scalars).
+void rb_trsm(rocblas_handle h, rocblas_side sd, rocblas_operation op, int m, int n, const double *A, int lda,
+             double *B, int ldb) {
+  const double one = 1.0;
+  rb_check(rocblas_dtrsm(h, sd, rocblas_fill_lower, op, rocblas_diagonal_non_unit, m, n, &one, A, lda, B, ldb),
+           "dtrsm");
+}
+void rb_trsm(rocblas_handle h, rocblas_side sd, rocblas_operation op, int m, int n, const cd *A, int lda, cd *B,
+             int ldb) {
+  const rocblas_double_complex one(1.0, 0.0);
+  rb_check(rocblas_ztrsm(h, sd, rocblas_fill_lower, op, rocblas_diagonal_non_unit, m, n, &one,
+                         reinterpret_cast<const rocblas_double_complex *>(A), lda,
+                         reinterpret_cast<rocblas_double_complex *>(B), ldb),
+           "ztrsm");
+}
+void rb_syrk_sub(rocblas_handle h, int n, int k, const double *A, int lda, double *C, int ldc) {
+  const double alpha = -1.0, beta = 1.0;
+  rb_check(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, n, k, &alpha, A, lda, &beta, C, ldc),
+           "dsyrk");
+}
+void rb_syrk_sub(rocblas_handle h, int n, int k, const cd *A, int lda, cd *C, int ldc) {
+  const rocblas_double_complex alpha(-1.0, 0.0), beta(1.0, 0.0);
+  rb_check(rocblas_zsyrk(h, rocblas_fill_lower, rocblas_operation_none, n, k, &alpha,
+                         reinterpret_cast<const rocblas_double_complex *>(A), lda, &beta,
+                         reinterpret_cast<rocblas_double_complex *>(C), ldc),
+           "zsyrk");
+}
+// C = -B A with A lower triangular (right side)
+void rb_trmm_neg(rocblas_handle h, int m, int n, const double *A, int lda, const double *B, int ldb, double *C,
+                 int ldc) {
+  const double alpha = -1.0;
+  rb_check(rocblas_dtrmm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, m, n, &alpha, A, lda, B, ldb, C, ldc),
+           "dtrmm");
+}
+void rb_trmm_neg(rocblas_handle h, int m, int n, const cd *A, int lda, const cd *B, int ldb, cd *C, int ldc) {
+  const rocblas_double_complex alpha(-1.0, 0.0);
+  rb_check(rocblas_ztrmm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, m, n, &alpha, reinterpret_cast<const rocblas_double_complex *>(A),
+                         lda, reinterpret_cast<const rocblas_double_complex *>(B), ldb,
+                         reinterpret_cast<rocblas_double_complex *>(C), ldc),
+           "ztrmm");
+}
+
+}  // namespace
+
+template <typename T>
+void factor_device(const Symbolic &S, const FrontPlan &fp, const FrontPlanDev &fd,
+                   const std::vector<int64_t> &panel_off, const T *vals, T *panel, T *front, T *arena,
+                   int32_t *flag, rocblas_handle rb, hipStream_t st) {
+  rb_check(rocblas_set_stream(rb, st), "set_stream");
+  for (int32_t s = 0; s < S.ns; ++s) {
+    const int32_t w = S.width(s), r = S.nrows(s), m = w + r;
+    T *F = front;
+    // 1. assembly
+    hipLaunchKernelGGL(k_front_zero<T>, dim3(std::min<unsigned>(4096, blocks_for((int64_t)m * m))), dim3(FB), 0,
+                       st, F, (int64_t)m * m);
+    const int64_t na = fp.a_ptr[s + 1] - fp.a_ptr[s];
+    if (na > 0)
+      hipLaunchKernelGGL(k_front_assemble<T>, dim3(blocks_for(na)), dim3(FB), 0, st, F, fd.a_pos + fp.a_ptr[s],
+                         fd.a_k + fp.a_ptr[s], na, vals);
+    for (int32_t q = fp.kid_ptr[s]; q < fp.kid_ptr[s + 1]; ++q) {
+      const int32_t ch = fp.kids[q], rc = S.nrows(ch);
+      if (rc == 0) continue;
+      hipLaunchKernelGGL(k_extend_add<T>, dim3(blocks_for((int64_t)rc * rc)), dim3(FB), 0, st, F, (int64_t)m,
+                         (const T *)(arena + fp.uoff[ch]), rc, fd.relpos + S.rptr[ch]);
+    }
+    // 2. partial factorisation of the first w columns
+    for (int32_t k0 = 0; k0 < w; k0 += NB) {
+      const int32_t kb = std::min(NB, w - k0), rest = m - k0 - kb;
+      T *D = F + k0 + (int64_t)k0 * m;
+      hipLaunchKernelGGL(k_diag_chol<T>, dim3(1), dim3(FB), 0, st, D, (int64_t)m, kb, flag);
+      if (rest > 0) {
+        T *B = F + (k0 + kb) + (int64_t)k0 * m;
+        rb_trsm(rb, rocblas_side_right, rocblas_operation_transpose, rest, kb, D, m, B, m);
+        rb_syrk_sub(rb, rest, kb, B, m, F + (k0 + kb) + (int64_t)(k0 + kb) * m, m);
+      }
+    }
+    if (S.parent[s] >= 0 && r > 0)
+      hipLaunchKernelGGL(k_take_update<T>, dim3(blocks_for((int64_t)r * r)), dim3(FB), 0, st, (const T *)F,
+                         (int64_t)m, w, r, arena + fp.uoff[s]);
+    // 3. selective inversion into the panel (ld = m)
+    T *P = panel + panel_off[s];
+    hipLaunchKernelGGL(k_set_identity<T>, dim3(blocks_for((int64_t)w * w)), dim3(FB), 0, st, P, (int64_t)m, w);
+    rb_trsm(rb, rocblas_side_left, rocblas_operation_none, w, w, F, m, P, m);
+    hipLaunchKernelGGL(k_zero_upper<T>, dim3(blocks_for((int64_t)w * w)), dim3(FB), 0, st, P, (int64_t)m, w);
+    if (r > 0) rb_trmm_neg(rb, r, w, P, m, F + w, m, P + w, m);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(STMG_EHIP, std::string("factorisation kernels: ") + hipGetErrorString(e));
+}
+
+template <typename TS, typename TD>
+void convert_panels(const TS *in, TD *out, TD *out_t, const int64_t *panel_off_dev, const int32_t *width_dev,
+                    int32_t ns, int64_t n_entries, hipStream_t st) {
+  if (n_entries == 0 || (!out && !out_t)) return;
+  hipLaunchKernelGGL((k_convert_panels<TS, TD>), dim3(blocks_for(n_entries)), dim3(FB), 0, st, in, out, out_t,
+                     panel_off_dev, width_dev, ns, n_entries);
+}
+
+template void factor_device<double>(const Symbolic &, const FrontPlan &, const FrontPlanDev &,
+                                    const std::vector<int64_t> &, const double *, double *, double *, double *,
+                                    int32_t *, rocblas_handle, hipStream_t);
+template void factor_device<cd>(const Symbolic &, const FrontPlan &, const FrontPlanDev &,
+                                const std::vector<int64_t> &, const cd *, cd *, cd *, cd *, int32_t *,
+                                rocblas_handle, hipStream_t);
+template void convert_panels<double, double>(const double *, double *, double *, const int64_t *, const int32_t *,
+                                             int32_t, int64_t, hipStream_t);
+template void convert_panels<double, float>(const double *, float *, float *, const int64_t *, const int32_t *,
+                                            int32_t, int64_t, hipStream_t);
+template void convert_panels<cd, cd>(const cd *, cd *, cd *, const int64_t *, const int32_t *, int32_t, int64_t,
+                                     hipStream_t);
+template void convert_panels<cd, cf>(const cd *, cf *, cf *, const int64_t *, const int32_t *, int32_t, int64_t,
+                                     hipStream_t);
+
+}  // namespace stmg

@@ -46,25 +46,7 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
-// Values per lane for a row of W doubles: at least q, and W/64 when the row
-// is wider than a wavefront.
-inline int lane_chunk(int W, int q) {
-  int c = W / 64;
-  return c < q ? q : c;
-}
-
 }  // namespace
-
-template <typename R>
-struct Vec2;
-template <>
-struct Vec2<double> {
-  using type = double2;
-};
-template <>
-struct Vec2<float> {
-  using type = float2;
-};
 
 // ---------------------------------------------------------------- residual
 // r_n = b_n - (K_t (x) M + M_t (x) K) x_n + (N_t (x) M) x_{n-1}
@@ -75,113 +57,201 @@ struct Vec2<float> {
 // Slab-solve right-hand side (mode 1), q = 2: w = (1/2 + i sqrt2/4) r0 - (3 i sqrt2/4) r1
 // stored as (re, im) in the two slots of slab n; q = 1: w = r.
 // The optional norm (sum of squares of r) is accumulated in FP64.
-template <typename R, int C, int Q>
-__global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a) {
-  constexpr int S = C / Q;
-  using V2 = typename Vec2<R>::type;
+//
+// Lane mapping. A row segment of LPR * C values is read as packets of P = 2
+// values (one slab for q = 2): packet p of lane li holds values
+// [(p * LPR + li) * P, +P), so every load instruction of a wave covers one
+// contiguous run of LPR * P values. The end value of the slab before a
+// packet comes from lane li - 1 (same packet) or lane LPR - 1 (packet p - 1).
+// Wide rows (N q >= 64 q): one wave per row with the row index wave-uniform,
+// so the matrix pattern and values are scalar loads. Rows longer than 64 C
+// values (C at most the handle's chunk option) are split into segments, one
+// launch per segment in slab order: the set of gathered x rows in flight on
+// an XCD is then one segment wide and stays in its L2. Launch s hands the end
+// value E of its last slab to launch s + 1 through halo[row] (two alternating
+// n_rows arrays). Narrow rows: 64 / LPR rows per wave, one segment.
+// Rows are visited in the order sched[] (a Morton order of the edge
+// midpoints): the rows in flight on an XCD then form a compact patch of the
+// mesh whose neighbour rows are gathered while still in its L2.
+namespace {
+template <typename R, int P>
+struct Pack;
+template <typename R>
+struct Pack<R, 1> {
+  using type = R;
+  __device__ static R get(const type &v, int) { return v; }
+  __device__ static void set(type &v, int, R x) { v = x; }
+};
+template <typename R>
+struct Pack<R, 2> {
+  using type = R __attribute__((ext_vector_type(2)));
+  __device__ static R get(const type &v, int t) { return v[t]; }
+  __device__ static void set(type &v, int t, R x) { v[t] = x; }
+};
+}  // namespace
+
+template <typename R, int C, int Q, bool WIDE>
+__global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a, int seg, int nseg) {
+  constexpr int P = (C % 2 == 0) ? 2 : 1;
+  constexpr int NP = C / P;
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
   const int W = a.N * Q;
-  const int LPR = W / C;
-  const int rpw = 64 / LPR;
+  const int LPR = WIDE ? 64 : W / C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane % LPR, sub = lane / LPR;
+  const int li = WIDE ? lane : lane % LPR;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int row = (blk * (BLOCK / 64) + wave) * rpw + sub;
-  const bool active = row < a.n_rows;
+  const int gw = blk * (BLOCK / 64) + wave;
+  const int slot = WIDE ? gw : gw * (64 / LPR) + lane / LPR;  // position in the visiting order
+  const bool active = slot < a.n_rows;
+  int row = active && a.sched ? a.sched[slot] : slot;
+  if constexpr (WIDE) row = __builtin_amdgcn_readfirstlane(row);
+  const int64_t c0 = (int64_t)seg * 64 * C;  // first value of the segment
+  R *halo = static_cast<R *>(a.halo);
+  const R *hin = seg > 0 ? halo + (int64_t)((seg - 1) & 1) * a.n_rows : nullptr;
+  R *hout = seg + 1 < nseg ? halo + (int64_t)(seg & 1) * a.n_rows : nullptr;
   R am[C], ak[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) am[j] = ak[j] = 0;
   if (active && a.x) {
-    const int64_t k1 = a.ptr[row + 1];
-    for (int64_t k = a.ptr[row]; k < k1; ++k) {
-      const int c = a.col[k];
-      const R mv = a.mval[k], kv = a.kval[k];
-      const R *xr = a.x + (int64_t)c * W + li * C;
-      if constexpr (C % 2 == 0) {
+    // U nonzeros per step with all their loads issued before the first FMA;
+    // the last group repeats the row's last nonzero with weight 0
+    constexpr int U = !WIDE ? 4 : (NP >= 8 ? 1 : 8 / NP);
+    const int64_t k0 = a.ptr[row], k1 = a.ptr[row + 1];
+    for (int64_t k = k0; k < k1; k += U) {
+      R mv[U], kv[U];
+      V v[U][NP];
 #pragma unroll
-        for (int j = 0; j < C; j += 2) {
-          const V2 v = *reinterpret_cast<const V2 *>(xr + j);
-          am[j] += mv * v.x;
-          am[j + 1] += mv * v.y;
-          ak[j] += kv * v.x;
-          ak[j + 1] += kv * v.y;
-        }
-      } else {
+      for (int u = 0; u < U; ++u) {
+        const bool in = k + u < k1;
+        const int64_t kk = in ? k + u : k1 - 1;
+        const int c = a.col[kk];
+        mv[u] = in ? a.mval[kk] : (R)0;
+        kv[u] = in ? a.kval[kk] : (R)0;
+        const R *xr = a.x + (int64_t)c * W + c0;
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-          am[j] += mv * xr[j];
-          ak[j] += kv * xr[j];
-        }
+        for (int p = 0; p < NP; ++p) v[u][p] = *reinterpret_cast<const V *>(xr + (int64_t)(p * LPR + li) * P);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int t = 0; t < P; ++t) {
+            am[p * P + t] += mv[u] * PK::get(v[u][p], t);
+            ak[p * P + t] += kv[u] * PK::get(v[u][p], t);
+          }
     }
   }
-  // end value of the lane's last slab, passed to the next lane
-  R elast = 0;
+  // end value of the slab before each packet
+  const R e_in = (hin && active) ? hin[row] : (R)0;
+  R prev[NP];
+  R e_last = 0;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) elast += am[(S - 1) * Q + k];
-  R eprev = __shfl_up(elast, 1, LPR);
-  if (li == 0) eprev = 0;
+  for (int p = 0; p < NP; ++p) {
+    R e = am[p * P + P - 1];
+    if constexpr (Q == 2) e += am[p * P];
+    const R up = __shfl_up(e, 1, LPR);
+    R wrap = e_in;
+    if (p > 0) {
+      R e1 = am[(p - 1) * P + P - 1];
+      if constexpr (Q == 2) e1 += am[(p - 1) * P];
+      wrap = __shfl(e1, LPR - 1, LPR);
+    }
+    prev[p] = li == 0 ? wrap : up;
+    e_last = e;
+  }
+  if (hout && active && lane == 63) hout[row] = e_last;
   double ss = 0.0;
   const R tau = (R)a.tau;
   if (active) {
-    const int64_t base = (int64_t)row * W + li * C;
-    R bv[C], out[C];
+    const int64_t base = (int64_t)row * W + c0;
 #pragma unroll
-    for (int j = 0; j < C; ++j) bv[j] = a.b[base + j];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int p = 0; p < NP; ++p) {
+      const int64_t off = base + (int64_t)(p * LPR + li) * P;
+      const V bv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.b + off));
+      V ov;
       if constexpr (Q == 1) {
-        const R r = bv[s] - am[s] + eprev - tau * ak[s];
-        eprev = am[s];
-        out[s] = r;
-        ss += (double)r * r;
+        R eprev = prev[p];
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          const R r = PK::get(bv, t) - am[p * P + t] + eprev - tau * ak[p * P + t];
+          eprev = am[p * P + t];
+          PK::set(ov, t, r);
+          ss += (double)r * r;
+        }
       } else {
-        const R m0 = am[2 * s], m1 = am[2 * s + 1];
-        const R r0 = bv[2 * s] - (m0 + m1) + eprev - tau * ak[2 * s];
-        const R r1 = bv[2 * s + 1] + m0 - m1 - eprev - (tau / (R)3) * ak[2 * s + 1];
-        eprev = m0 + m1;
+        const R m0 = am[2 * p], m1 = am[2 * p + 1];
+        const R r0 = PK::get(bv, 0) - (m0 + m1) + prev[p] - tau * ak[2 * p];
+        const R r1 = PK::get(bv, 1) + m0 - m1 - prev[p] - (tau / (R)3) * ak[2 * p + 1];
         ss += (double)r0 * r0 + (double)r1 * r1;
         if (a.mode == RES_OUT_SLABRHS) {
           const R s2 = (R)1.4142135623730951;
-          out[2 * s] = (R)0.5 * r0;
-          out[2 * s + 1] = (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1;
+          PK::set(ov, 0, (R)0.5 * r0);
+          PK::set(ov, 1, (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1);
         } else {
-          out[2 * s] = r0;
-          out[2 * s + 1] = r1;
+          PK::set(ov, 0, r0);
+          PK::set(ov, 1, r1);
         }
       }
+      __builtin_nontemporal_store(ov, reinterpret_cast<V *>(a.out + off));
     }
-#pragma unroll
-    for (int j = 0; j < C; ++j) a.out[base + j] = out[j];
   }
   if (a.partial) {
     const double t = block_sum(ss);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = t;
+    if (threadIdx.x == 0) a.partial[(int64_t)seg * gridDim.x + blockIdx.x] = t;
   }
 }
 
-int residual_blocks(int32_t n_rows, int32_t W, int32_t q) {
-  const int C = lane_chunk(W, q);
-  const int LPR = W / C;
-  const int rows_per_block = (64 / LPR) * (BLOCK / 64);
+namespace {
+// Values per lane C and rows-per-wave layout of a row of W = N q values.
+struct ResShape {
+  int C;
+  bool wide;
+  int nseg;
+};
+ResShape residual_shape(int W, int q, int chunk) {
+  if (W >= 64 * q) {
+    const int cmax = std::max(q, chunk > 0 ? std::min(chunk, 16) : RES_CHUNK_DEFAULT);
+    const int C = std::min(W / 64, cmax);
+    return {C, true, W / (64 * C)};
+  }
+  return {q, false, 1};
+}
+}  // namespace
+
+// Blocks of one segment's launch.
+int residual_blocks_per_launch(int32_t n_rows, int32_t W, const ResShape &sh) {
+  if (sh.wide) return (n_rows + BLOCK / 64 - 1) / (BLOCK / 64);
+  const int rows_per_block = (64 / (W / sh.C)) * (BLOCK / 64);
   return (n_rows + rows_per_block - 1) / rows_per_block;
 }
 
+int residual_blocks(int32_t n_rows, int32_t W, int32_t q, int32_t chunk) {
+  const ResShape sh = residual_shape(W, q, chunk);
+  return residual_blocks_per_launch(n_rows, W, sh) * sh.nseg;
+}
+
 template <typename R>
-static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, int C, hipStream_t s) {
-#define RES_CASE(CC, QQ)                                                                    \
-  if (C == CC && a.q == QQ) {                                                               \
-    hipLaunchKernelGGL((k_residual<R, CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, a);            \
+static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, const ResShape &sh, hipStream_t s) {
+#define RES_CASE(CC, QQ, WW)                                                                \
+  if (sh.C == CC && a.q == QQ && sh.wide == WW) {                                           \
+    for (int seg = 0; seg < sh.nseg; ++seg)                                                 \
+      hipLaunchKernelGGL((k_residual<R, CC, QQ, WW>), dim3(nb), dim3(BLOCK), 0, s, a, seg,  \
+                         sh.nseg);                                                          \
     return;                                                                                 \
   }
-  RES_CASE(1, 1)
-  RES_CASE(2, 1)
-  RES_CASE(4, 1)
-  RES_CASE(8, 1)
-  RES_CASE(16, 1)
-  RES_CASE(2, 2)
-  RES_CASE(4, 2)
-  RES_CASE(8, 2)
-  RES_CASE(16, 2)
+  RES_CASE(1, 1, false)
+  RES_CASE(1, 1, true)
+  RES_CASE(2, 1, true)
+  RES_CASE(4, 1, true)
+  RES_CASE(8, 1, true)
+  RES_CASE(16, 1, true)
+  RES_CASE(2, 2, false)
+  RES_CASE(2, 2, true)
+  RES_CASE(4, 2, true)
+  RES_CASE(8, 2, true)
+  RES_CASE(16, 2, true)
 #undef RES_CASE
   fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", a.N * a.q, a.q);
 }
@@ -189,21 +259,21 @@ static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, int C, hipS
 template <typename R>
 void launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
   const int W = a.N * a.q;
-  const int C = lane_chunk(W, a.q);
-  const int nb = residual_blocks(a.n_rows, W, a.q);
+  const ResShape sh = residual_shape(W, a.q, a.chunk);
+  const int nb = residual_blocks_per_launch(a.n_rows, W, sh);
   if (nb == 0) return;
   if (a.prof) {
     // algorithmic traffic: x, b read once, out written once, the pattern and
     // both value arrays read once; 4 flops per nonzero and column (two FMAs)
     char name[64];
-    snprintf(name, sizeof name, "k_residual<%s,%d,%d>", sizeof(R) == 8 ? "double" : "float", C, a.q);
+    snprintf(name, sizeof name, "k_residual<%s,%d,%d>", sizeof(R) == 8 ? "double" : "float", sh.C, a.q);
     a.prof->begin(s);
-    launch_residual_inner(a, nb, C, s);
+    launch_residual_inner(a, nb, sh, s);
     const double rows = a.n_rows, cols = W, nnz = (double)a.nnz, sz = sizeof(R);
     a.prof->end(s, name, 4.0 * nnz * cols, sz * rows * cols * (a.x ? 3.0 : 2.0) + (4.0 + 2.0 * sz) * nnz + 8.0 * (rows + 1));
     return;
   }
-  launch_residual_inner(a, nb, C, s);
+  launch_residual_inner(a, nb, sh, s);
 }
 template void launch_residual<double>(const ResidualArgsT<double> &, hipStream_t);
 template void launch_residual<float>(const ResidualArgsT<float> &, hipStream_t);
@@ -316,74 +386,89 @@ void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edg
 // -N_t below), per vertex row, in place:
 //   q = 1: y_n = sum_{m <= n} g_m (the running sum of eq. (8));
 //   q = 2: e_n = sum_{m <= n} g_{m,0}; y_{n,0} = e_{n-1} + (g0 - g1)/2, y_{n,1} = (g0 + g1)/2.
-template <typename R, int C, int Q>
+// Same packet mapping as the residual; a wave walks the packets (and, for
+// wide rows, the segments) of its row in slab order, scanning across lanes
+// and carrying the running sum.
+template <typename R, int C, int Q, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_time_scan(int32_t n_v, int32_t N, R *g) {
-  constexpr int S = C / Q;
+  constexpr int P = (C % 2 == 0) ? 2 : 1;
+  constexpr int NP = C / P;
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
   const int W = N * Q;
-  const int LPR = W / C;
-  const int rpw = 64 / LPR;
+  const int LPR = WIDE ? 64 : W / C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane % LPR, sub = lane / LPR;
-  const int row = (blockIdx.x * (BLOCK / 64) + wave) * rpw + sub;
+  const int li = WIDE ? lane : lane % LPR;
+  const int gw = blockIdx.x * (BLOCK / 64) + wave;
+  const int row = WIDE ? __builtin_amdgcn_readfirstlane(gw) : gw * (64 / LPR) + lane / LPR;
   const bool active = row < n_v;
-  R v[C];
-  R local = 0;
-  if (active) {
+  const int nseg = WIDE ? W / (64 * C) : 1;
+  R carry = 0;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int64_t base = (int64_t)row * W + (int64_t)seg * 64 * C;
 #pragma unroll
-    for (int j = 0; j < C; ++j) v[j] = g[(int64_t)row * W + li * C + j];
-#pragma unroll
-    for (int s = 0; s < S; ++s) local += v[s * Q];
-  } else {
-#pragma unroll
-    for (int j = 0; j < C; ++j) v[j] = 0;
-  }
-  // exclusive scan of `local` over the lanes of this row (Hillis-Steele)
-  R incl = local;
-  for (int o = 1; o < LPR; o <<= 1) {
-    const R t = __shfl_up(incl, o, LPR);
-    if (li >= o) incl += t;
-  }
-  R e = incl - local;  // sum over earlier lanes
-  if (active) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if constexpr (Q == 1) {
-        e += v[s];
-        v[s] = e;
+    for (int p = 0; p < NP; ++p) {
+      const int64_t off = base + (int64_t)(p * LPR + li) * P;
+      V v;
+      if (active) {
+        v = *reinterpret_cast<const V *>(g + off);
       } else {
-        const R g0 = v[2 * s], g1 = v[2 * s + 1];
-        v[2 * s] = e + (R)0.5 * (g0 - g1);
-        v[2 * s + 1] = (R)0.5 * (g0 + g1);
-        e += g0;
-      }
-    }
 #pragma unroll
-    for (int j = 0; j < C; ++j) g[(int64_t)row * W + li * C + j] = v[j];
+        for (int t = 0; t < P; ++t) PK::set(v, t, (R)0);
+      }
+      R local = 0;
+      if constexpr (Q == 2) {
+        local = PK::get(v, 0);
+      } else {
+#pragma unroll
+        for (int t = 0; t < P; ++t) local += PK::get(v, t);
+      }
+      R incl = local;
+      for (int o = 1; o < LPR; o <<= 1) {
+        const R t = __shfl_up(incl, o, LPR);
+        if (li >= o) incl += t;
+      }
+      R e = carry + (incl - local);
+      carry += __shfl(incl, LPR - 1, LPR);
+      if constexpr (Q == 2) {
+        const R g0 = PK::get(v, 0), g1 = PK::get(v, 1);
+        PK::set(v, 0, e + (R)0.5 * (g0 - g1));
+        PK::set(v, 1, (R)0.5 * (g0 + g1));
+      } else {
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          e += PK::get(v, t);
+          PK::set(v, t, e);
+        }
+      }
+      if (active) *reinterpret_cast<V *>(g + off) = v;
+    }
   }
 }
 
 template <typename R>
 void launch_time_scan(int32_t n_v, int32_t N, int32_t q, R *g, hipStream_t s) {
   const int W = N * q;
-  const int C = lane_chunk(W, q);
-  const int LPR = W / C;
-  const int rows_per_block = (64 / LPR) * (BLOCK / 64);
+  const ResShape sh = residual_shape(W, q, 16);
+  const int rows_per_block = sh.wide ? BLOCK / 64 : (64 / (W / sh.C)) * (BLOCK / 64);
   const int nb = (n_v + rows_per_block - 1) / rows_per_block;
   if (nb == 0) return;
-#define SCAN_CASE(CC, QQ)                                                                      \
-  if (C == CC && q == QQ) {                                                                    \
-    hipLaunchKernelGGL((k_time_scan<R, CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, n_v, N, g);      \
-    return;                                                                                    \
+#define SCAN_CASE(CC, QQ, WW)                                                                      \
+  if (sh.C == CC && q == QQ && sh.wide == WW) {                                                    \
+    hipLaunchKernelGGL((k_time_scan<R, CC, QQ, WW>), dim3(nb), dim3(BLOCK), 0, s, n_v, N, g);      \
+    return;                                                                                        \
   }
-  SCAN_CASE(1, 1)
-  SCAN_CASE(2, 1)
-  SCAN_CASE(4, 1)
-  SCAN_CASE(8, 1)
-  SCAN_CASE(16, 1)
-  SCAN_CASE(2, 2)
-  SCAN_CASE(4, 2)
-  SCAN_CASE(8, 2)
-  SCAN_CASE(16, 2)
+  SCAN_CASE(1, 1, false)
+  SCAN_CASE(1, 1, true)
+  SCAN_CASE(2, 1, true)
+  SCAN_CASE(4, 1, true)
+  SCAN_CASE(8, 1, true)
+  SCAN_CASE(16, 1, true)
+  SCAN_CASE(2, 2, false)
+  SCAN_CASE(2, 2, true)
+  SCAN_CASE(4, 2, true)
+  SCAN_CASE(8, 2, true)
+  SCAN_CASE(16, 2, true)
 #undef SCAN_CASE
   fprintf(stderr, "stmg: unsupported scan shape W=%d q=%d\n", W, q);
 }
@@ -759,7 +844,8 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t
 // DIR 0: forward (A = P). DIR 1: backward (A = P^T, read from P), DIR 2:
 // backward reading the stored transpose (same access pattern as forward).
 // With nsplit > 1 the K range is cut into nsplit segments of kseg and each
-// work item writes its partial tile to ws; k_sn_reduce adds them in order.
+// work item writes its partial tile to ws; k_sn_reduce adds them in order
+// and applies the epilogue.
 template <typename T, int BM, int BN, int DIR>
 __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
                                                    int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
@@ -930,19 +1016,23 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
 }
 
 // Sum of the split-K partial tiles in segment order, then the same epilogue
-// as the unsplit kernel (backward: X[C_s] rows).
-template <typename T, int BM>
+// as the unsplit kernel (forward: Z rows and U update rows; backward: X[C_s]
+// rows). One block per (row tile, chunk of RC columns).
+template <typename T, int BM, int DIR>
 __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
-                                                     int32_t nc, int32_t nsplit, const T *ws, T *X) {
+                                                     int32_t nc, int32_t nsplit, const T *ws, T *X, T *Z, T *U) {
   using R = typename Scalar<T>::R;
-  const int rowtile = blockIdx.x;
+  const int RC = nc < 64 ? nc : 64;  // columns per block
+  const int cchunks = (nc + RC - 1) / RC;
+  const int rowtile = blockIdx.x / cchunks, cc = blockIdx.x % cchunks;
   const int ti = find_task(tasks, n_tasks, rowtile);
   const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0;
-  for (int e = threadIdx.x; e < BM * nc; e += BLOCK) {
-    const int rr = e / nc, col = e % nc;
+  const int rows = DIR == 0 ? f.m[s] : w;
+  for (int e = threadIdx.x; e < BM * RC; e += BLOCK) {
+    const int rr = e / RC, col = cc * RC + e % RC;
     const int row = rt * BM + rr;
-    if (row >= w) continue;
+    if (row >= rows || col >= nc) continue;
     R ar = 0, ai = 0;
     for (int g = 0; g < nsplit; ++g) {
       R r, i;
@@ -950,7 +1040,16 @@ __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTas
       ar += r;
       ai += i;
     }
-    make(ar, ai, X[(int64_t)(c0 + row) * nc + col]);
+    if (DIR != 0) {
+      make(ar, ai, X[(int64_t)(c0 + row) * nc + col]);
+    } else if (row < w) {
+      make(ar, ai, Z[(int64_t)(c0 + row) * nc + col]);
+    } else {
+      T *u = U + (f.uoff[s] + (row - w)) * nc + col;
+      R ur, ui;
+      split(*u, ur, ui);
+      make(ur + ar, ui + ai, *u);
+    }
   }
 }
 
@@ -974,16 +1073,19 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   const int ct = (nc + bn - 1) / bn;
   const SolveTask *tasks = bm32 ? L.tasks32 : L.tasks;
   const int64_t tiles = bm32 ? L.n_tiles32 : L.n_tiles;
-  // backward launches with too few work items for the GPU and long K ranges
-  // are split along K (deterministic two-pass sum)
+  // launches with too few work items for the GPU and long K ranges are split
+  // along K (deterministic two-pass sum)
   int nsplit = 1, kseg = 0;
   const int bmv = bm32 ? 32 : 64;
-  if (DIR != 0 && ws && splitk >= 0) {
+  if (ws && splitk >= 0) {
     int want = 1;
+    // forward partial tiles cover all m rows of a front (the update rows
+    // too), so the forward splits only launches that leave most of the GPU idle
+    const int64_t fill = DIR == 0 ? 512 : 2048;
     if (splitk >= 2)
       want = splitk;
-    else if (tiles * ct < 2048 && L.kmax >= 512)
-      want = (int)std::min<int64_t>(8, (2048 + tiles * ct - 1) / (tiles * ct));
+    else if (tiles * ct < fill && L.kmax >= 512)
+      want = (int)std::min<int64_t>(8, (fill + tiles * ct - 1) / (tiles * ct));
     if (want > 1 && L.kmax > 16) {
       kseg = ((L.kmax + want - 1) / want + 15) / 16 * 16;
       nsplit = (L.kmax + kseg - 1) / kseg;
@@ -1011,8 +1113,8 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
       hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
                          nc, ct, X, Z, U, nsplit, kseg, (T *)ws);                                          \
     if (nsplit > 1)                                                                                        \
-      hipLaunchKernelGGL((k_sn_reduce<T, BMV>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
-                         nc, nsplit, (const T *)ws, X);                                                    \
+      hipLaunchKernelGGL((k_sn_reduce<T, BMV, DIR>), dim3((unsigned)(tiles * ((nc + 63) / 64))), dim3(BLOCK), \
+                         0, s, f, tasks, L.n_tasks, nc, nsplit, (const T *)ws, X, Z, U);                   \
     if (prof) prof->end(s, name, (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz * nc, scal * (L.nnz + 2.0 * L.rows * nc)); \
     return;                                                                                                \
   }
@@ -1031,7 +1133,8 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
     if (t1 > t0)
       hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(BLOCK), 0, s, p.tgt + t0,
                          t1 - t0, p.src, nc, X, U);
-    launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, p.splitk, p.prof, nullptr, 0, nc, X, Z, U, s);
+    launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, p.splitk, p.prof, p.splitk_ws, p.splitk_bytes, nc, X, Z, U,
+                         s);
   }
 }
 

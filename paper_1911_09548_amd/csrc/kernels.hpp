@@ -45,10 +45,14 @@ struct ResidualArgsT {
   int32_t mode;                 // 0: out = r; 1: out = slab-solve right-hand side
   int64_t nnz = 0;              // pattern nonzeros (work accounting only)
   Profiler *prof = nullptr;
+  int32_t chunk = 0;            // max values per lane of a row segment (0: default)
+  void *halo = nullptr;         // 2 * n_rows values of R: segment-to-segment end values
+  const int32_t *sched = nullptr;  // visiting order of the rows (null: storage order)
 };
 using ResidualArgs = ResidualArgsT<double>;
+constexpr int RES_CHUNK_DEFAULT = 16;
 enum { RES_OUT_R = 0, RES_OUT_SLABRHS = 1 };
-int residual_blocks(int32_t n_rows, int32_t W, int32_t q);
+int residual_blocks(int32_t n_rows, int32_t W, int32_t q, int32_t chunk);
 template <typename R>
 void launch_residual(const ResidualArgsT<R> &a, hipStream_t s);
 

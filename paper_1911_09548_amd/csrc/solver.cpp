@@ -70,6 +70,45 @@ T *dev_upload(stmg_handle *h, const std::vector<T> &v) {
   return dev_upload(h, v.data(), v.size());
 }
 
+// A device buffer that lives only during setup (released on the handle's
+// stream for stream-ordered handles, after a stream synchronisation
+// otherwise).
+struct DevTemp {
+  stmg_handle *h;
+  void *p = nullptr;
+  DevTemp(stmg_handle *h_, size_t bytes) : h(h_) {
+    if (bytes == 0) bytes = 16;
+    if (h->stream_ordered)
+      hip_check(hipMallocAsync(&p, bytes, h->stream), "hipMallocAsync");
+    else
+      hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  }
+  template <typename T>
+  DevTemp(stmg_handle *h_, const std::vector<T> &v) : DevTemp(h_, v.size() * sizeof(T)) {
+    if (!v.empty()) {
+      hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream), "upload");
+      hip_check(hipStreamSynchronize(h->stream), "upload");
+    }
+  }
+  ~DevTemp() {
+    if (!p) return;
+    if (h->stream_ordered) {
+      (void)hipFreeAsync(p, h->stream);
+    } else {
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipFree(p);
+    }
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+  DevTemp(const DevTemp &) = delete;
+  DevTemp &operator=(const DevTemp &) = delete;
+};
+
+bool dev_factor(const stmg_handle *h) { return h->opt.device_factor && !h->opt.host_only; }
+
 // ------------------------------------------------------------- solve plans
 void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   const int32_t ns = S.ns, H = S.n_heights;
@@ -229,7 +268,101 @@ void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, D
   h->factor_bytes += D.factor_bytes;
 }
 
+// Numeric factorisation on the device (values `vals` on the pattern the
+// front plan was built from), then the panels each form keeps: FP64 (and its
+// transpose) and/or FP32 (and its transpose), converted on the device.
+template <typename T64, typename T32>
+void factor_into(stmg_handle *h, const Symbolic &S, const FrontPlan &fp, const std::vector<T64> &vals,
+                 DevFactor &D, bool transpose, bool need64, bool need32) {
+  std::vector<int64_t> off;
+  factor_layout(S, off);
+  const int64_t n = off[S.ns];
+  D.h_panel_off = off;
+  D.f.panel_off = dev_upload(h, off);
+  std::vector<int32_t> width(S.ns);
+  for (int32_t s = 0; s < S.ns; ++s) width[s] = S.width(s);
+  DevTemp t_width(h, width), t_pos(h, fp.a_pos), t_k(h, fp.a_k), t_rel(h, fp.relpos), t_vals(h, vals);
+  DevTemp t_front(h, (size_t)fp.max_m2 * sizeof(T64));
+  DevTemp t_arena(h, (size_t)fp.uoff[S.ns] * sizeof(T64));
+  DevTemp t_flag(h, sizeof(int32_t));
+  DevTemp t_p64(h, need64 ? 0 : (size_t)n * sizeof(T64));
+  T64 *p64 = need64 ? dev_alloc<T64>(h, (size_t)n) : t_p64.as<T64>();
+  hip_check(hipMemsetAsync(t_flag.p, 0, sizeof(int32_t), h->stream), "memset");
+  FrontPlanDev fd;
+  fd.a_pos = t_pos.as<int64_t>();
+  fd.a_k = t_k.as<int64_t>();
+  fd.relpos = t_rel.as<int32_t>();
+  factor_device<T64>(S, fp, fd, off, t_vals.as<T64>(), p64, t_front.as<T64>(), t_arena.as<T64>(),
+                     t_flag.as<int32_t>(), h->rb, h->stream);
+  int32_t bad = 0;
+  hip_check(hipMemcpyAsync(&bad, t_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "copy");
+  hip_check(hipStreamSynchronize(h->stream), "factorisation");
+  STMG_REQUIRE(bad == 0, STMG_ENUMERIC, "zero or non-finite pivot in factorisation");
+  D.factor_bytes = 0;
+  D.f.panel = need64 ? p64 : nullptr;
+  D.f.panel_t = nullptr;
+  if (need64) {
+    D.factor_bytes += n * (int64_t)sizeof(T64);
+    if (transpose) {
+      T64 *pt = dev_alloc<T64>(h, (size_t)n);
+      convert_panels<T64, T64>(p64, nullptr, pt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, h->stream);
+      D.f.panel_t = pt;
+      D.factor_bytes += n * (int64_t)sizeof(T64);
+    }
+  }
+  D.f32 = D.f;
+  D.f32.panel = D.f32.panel_t = nullptr;
+  if (need32) {
+    T32 *q = dev_alloc<T32>(h, (size_t)n), *qt = transpose ? dev_alloc<T32>(h, (size_t)n) : nullptr;
+    convert_panels<T64, T32>(p64, q, qt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, h->stream);
+    D.f32.panel = q;
+    D.f32.panel_t = qt;
+    D.factor_bytes += n * (int64_t)sizeof(T32) * (transpose ? 2 : 1);
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+  hip_check(hipStreamSynchronize(h->stream), "factor conversion");
+  h->factor_bytes += D.factor_bytes;
+}
+
 // ------------------------------------------------------------ level setup
+// Internal edge rows sorted by the Morton code of their midpoints (21 bits
+// per axis over the mesh's bounding box); ties keep the storage order.
+std::vector<int32_t> morton_schedule(const Topo &T, const std::vector<int32_t> &perm) {
+  const int32_t ne = (int32_t)perm.size();
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int32_t v = 0; v < T.nv; ++v)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], T.coords[3 * v + d]);
+      hi[d] = std::max(hi[d], T.coords[3 * v + d]);
+    }
+  auto spread = [](uint64_t x) {  // 21 bits -> every third bit
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+  };
+  std::vector<std::pair<uint64_t, int32_t>> key(ne);
+  for (int32_t r = 0; r < ne; ++r) {
+    const int32_t e = T.int_edges[perm[r]];
+    const int32_t a = T.edges[2 * e], b = T.edges[2 * e + 1];
+    uint64_t code = 0;
+    for (int d = 0; d < 3; ++d) {
+      const double m = 0.5 * (T.coords[3 * a + d] + T.coords[3 * b + d]);
+      const double ext = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+      const uint64_t qd = (uint64_t)std::min(2097151.0, std::max(0.0, (m - lo[d]) / ext * 2097151.0));
+      code |= spread(qd) << d;
+    }
+    key[r] = {code, r};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> sched(ne);
+  for (int32_t i = 0; i < ne; ++i) sched[i] = key[i].second;
+  return sched;
+}
+
 void setup_mesh_host(stmg_handle *h, MeshData &md) {
   SpaceLevel &S = *md.S;
   const Topo &T = S.topo;
@@ -238,11 +371,17 @@ void setup_mesh_host(stmg_handle *h, MeshData &md) {
   const bool has_nodal = T.n_int_verts() > 0;
   if (has_nodal) {
     md.sym_v = symbolic_from_tree(md.nd, vertex_nodes(T, md.nd), S.Kn);
-    md.nodal_host = std::make_unique<HostFactor<double>>();
-    factor_host<double>(md.sym_v, S.Kn, S.Kn.val, *md.nodal_host);
+    if (dev_factor(h)) {
+      build_front_plan(md.sym_v, S.Kn, md.fp_v);
+    } else {
+      md.nodal_host = std::make_unique<HostFactor<double>>();
+      factor_host<double>(md.sym_v, S.Kn, S.Kn.val, *md.nodal_host);
+    }
   }
   md.Mp = csr_permute_sym(S.M, md.sym_e.perm);
   md.Kp = csr_permute_sym(S.K, md.sym_e.perm);
+  md.sched = morton_schedule(T, md.sym_e.perm);
+  if (dev_factor(h)) build_front_plan(md.sym_e, S.M, md.fp_e);
 }
 
 void setup_mesh_device(stmg_handle *h, MeshData &md) {
@@ -250,6 +389,7 @@ void setup_mesh_device(stmg_handle *h, MeshData &md) {
   const Topo &T = S.topo;
   const bool has_nodal = T.n_int_verts() > 0;
   md.d_ptr = dev_upload(h, md.Mp.ptr);
+  md.d_sched = dev_upload(h, md.sched);
   md.d_col = dev_upload(h, md.Mp.col);
   md.d_mval = dev_upload(h, md.Mp.val);
   md.d_kval = dev_upload(h, md.Kp.val);
@@ -307,9 +447,14 @@ void setup_mesh_device(stmg_handle *h, MeshData &md) {
   }
   if (has_nodal) {
     build_plan(h, md.sym_v, md.nodal);
-    upload_factor<double, float>(h, md.sym_v, *md.nodal_host, md.nodal, true, true,
+    if (dev_factor(h)) {
+      factor_into<double, float>(h, md.sym_v, md.fp_v, S.Kn.val, md.nodal, true, true,
                                  h->opt.precision == STMG_FP32_REFINED);
-    if (!h->opt.host_only) md.nodal_host.reset();
+    } else {
+      upload_factor<double, float>(h, md.sym_v, *md.nodal_host, md.nodal, true, true,
+                                   h->opt.precision == STMG_FP32_REFINED);
+      if (!h->opt.host_only) md.nodal_host.reset();
+    }
   }
 }
 
@@ -389,6 +534,23 @@ void setup_level_factor_host(stmg_handle *h, LevelData &L) {
 void setup_level_factor_device(stmg_handle *h, LevelData &L) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   build_plan(h, md.sym_e, L.slab);
+  if (dev_factor(h)) {
+    const SpaceLevel &S = *md.S;
+    const int64_t nnz = S.M.nnz();
+    if (h->pt == 1) {
+      std::vector<cd> v(nnz);
+      const double s2 = std::sqrt(2.0);
+      for (int64_t k = 0; k < nnz; ++k) v[k] = {2.0 * S.M.val[k] + L.tau * S.K.val[k], s2 * S.M.val[k]};
+      L.slab.is_complex = true;
+      factor_into<cd, cf>(h, md.sym_e, md.fp_e, v, L.slab, slab_transpose(h, L), need64(h, L), need32(h, L));
+    } else {
+      std::vector<double> v(nnz);
+      for (int64_t k = 0; k < nnz; ++k) v[k] = S.M.val[k] + L.tau * S.K.val[k];
+      factor_into<double, float>(h, md.sym_e, md.fp_e, v, L.slab, slab_transpose(h, L), need64(h, L),
+                                 need32(h, L));
+    }
+    return;
+  }
   if (h->pt == 1) {
     L.slab.is_complex = true;
     upload_factor<cd, cf>(h, md.sym_e, *L.slab_host_c, L.slab, slab_transpose(h, L), need64(h, L), need32(h, L));
@@ -504,6 +666,9 @@ struct OpsT {
     a.mode = mode;
     a.nnz = md.Mp.nnz();
     a.prof = h->prof_state.on ? &h->prof : nullptr;
+    a.chunk = h->opt.stream_chunk;
+    a.halo = h->d_halo;
+    a.sched = h->opt.row_schedule == 0 ? md.d_sched : nullptr;
     launch_residual(a, s);
   }
 
@@ -590,7 +755,7 @@ struct OpsT {
   // ||b - L x||^2 into dst (device), FP64 accumulation
   void residual_norm2(int l, const R *x, const R *b, R *out, double *dst) {
     residual(l, x, b, out, RES_OUT_R, h->d_partial);
-    launch_sum(h->d_partial, residual_blocks(ne(l), W(l), h->q), dst, s);
+    launch_sum(h->d_partial, residual_blocks(ne(l), W(l), h->q, h->opt.stream_chunk), dst, s);
   }
 };
 
@@ -814,6 +979,13 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
   STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                "gemm_rows must be 0, 32 or 64");
+  {
+    const int c = h->opt.stream_chunk;
+    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16, STMG_EINVAL,
+                 "stream_chunk must be 0, 1, 2, 4, 8 or 16");
+    STMG_REQUIRE(h->opt.row_schedule == 0 || h->opt.row_schedule == 1, STMG_EINVAL,
+                 "row_schedule must be 0 or 1");
+  }
   if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
   h->pt = prob->pt;
   h->q = prob->pt + 1;
@@ -852,7 +1024,7 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
               h->meshes[j].S->topo.n_int_edges(), (double)h->meshes[j].sym_e.nnz_L, h->meshes[j].sym_e.ns,
               wall_time() - t0);
   }
-  for (size_t l = 0; l < h->levels.size(); ++l) {
+  for (size_t l = 0; l < h->levels.size() && !dev_factor(h.get()); ++l) {
     LevelData &L = h->levels[l];
     setup_level_factor_host(h.get(), L);
     if (verbose())
@@ -903,6 +1075,17 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
 void setup_device_phase(stmg_handle *h, hipStream_t stream) {
   const double t0 = wall_time();
   h->stream = stream;
+  struct RbGuard {
+    stmg_handle *h;
+    ~RbGuard() {
+      if (h->rb) (void)rocblas_destroy_handle(h->rb);
+      h->rb = nullptr;
+    }
+  } rb_guard{h};
+  if (dev_factor(h)) {
+    STMG_REQUIRE(rocblas_create_handle(&h->rb) == rocblas_status_success, STMG_EHIP, "rocblas_create_handle failed");
+    STMG_REQUIRE(rocblas_set_stream(h->rb, stream) == rocblas_status_success, STMG_EHIP, "rocblas_set_stream failed");
+  }
   const int32_t used = (int32_t)h->meshes.size();
   for (int32_t j = 0; j < used; ++j) {
     setup_mesh_device(h, h->meshes[j]);
@@ -911,6 +1094,9 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
   for (size_t l = 0; l < h->levels.size(); ++l) {
     setup_level_factor_device(h, h->levels[l]);
     alloc_level_vectors(h, h->levels[l], l == 0);
+    if (verbose())
+      fprintf(stderr, "[stmg] level %zu device setup (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
+              wall_time() - t0);
   }
   // split-K partial sums of the backward solves, shared by all factors
   const LevelData &L0 = h->levels[0];
@@ -925,8 +1111,9 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
     m.nodal.plan.splitk_ws = ws;
     m.nodal.plan.splitk_bytes = ws_bytes;
   }
-  h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L0.N * h->q, h->q) + 4096;
+  h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L0.N * h->q, h->q, 1) + 4096;  // any chunk
   h->d_partial = dev_alloc<double>(h, h->n_partial);
+  h->d_halo = dev_alloc<double>(h, 2 * (size_t)h->space[0].topo.n_int_edges() + 64);
   h->d_scalar = dev_alloc<double>(h, 8192);
   hip_check(hipStreamSynchronize(stream), "setup");
   h->setup_s += wall_time() - t0;
@@ -975,11 +1162,13 @@ void stmg_default_options(stmg_options *o) {
   o->rtol = 1e-8;
   o->max_cycles = 100;
   o->host_only = 0;
-  o->factor_on_device = 0;
+  o->stream_chunk = 0;
+  o->row_schedule = 0;
   o->leaf_size = 8;
   o->gemm_rows = 0;
   o->factor_transpose = -1;
   o->gemm_splitk = 0;
+  o->device_factor = 1;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -1253,6 +1442,18 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
   });
 }
 
+int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_schedule) {
+  return guard([&] {
+    STMG_REQUIRE(h, STMG_EINVAL, "null handle");
+    const int c = stream_chunk;
+    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16, STMG_EINVAL,
+                 "stream_chunk must be 0, 1, 2, 4, 8 or 16");
+    STMG_REQUIRE(row_schedule == 0 || row_schedule == 1, STMG_EINVAL, "row_schedule must be 0 or 1");
+    h->opt.stream_chunk = stream_chunk;
+    h->opt.row_schedule = row_schedule;
+  });
+}
+
 int stmg_profile(stmg_handle *h, int32_t enable) {
   return guard([&] {
     require_device(h);
@@ -1296,7 +1497,6 @@ int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32
   return guard([&] {
     STMG_REQUIRE(h && n && ns && n_rows_total && n_panel && is_complex, STMG_EINVAL, "null argument");
     STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
-    STMG_REQUIRE(h->opt.host_only, STMG_ENOSYS, "factors of device handles live only in HBM");
     const LevelData &L = h->levels[level];
     const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
     const Symbolic *S = nullptr;
@@ -1304,7 +1504,25 @@ int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32
     const double *vals = nullptr;
     size_t nvals = 0;
     int cpx = 0;
-    if (which == 0) {
+    std::vector<double> copy;  // device panels copied back
+    if (!h->opt.host_only) {
+      STMG_REQUIRE(which == 0 || which == 1, STMG_EINVAL, "which must be 0 or 1");
+      const DevFactor &D = which == 0 ? L.slab : md.nodal;
+      S = which == 0 ? &md.sym_e : &md.sym_v;
+      STMG_REQUIRE(D.f.panel != nullptr && !D.h_panel_off.empty(), STMG_ENOSYS,
+                   "no FP64 factor of this level on the device");
+      cpx = which == 0 && D.is_complex ? 1 : 0;
+      off = &D.h_panel_off;
+      nvals = (size_t)D.h_panel_off[S->ns] * (cpx ? 2 : 1);
+      if (panel) {
+        copy.resize(nvals);
+        hip_check(hipMemcpyAsync(copy.data(), D.f.panel, nvals * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream),
+                  "copy");
+        hip_check(hipStreamSynchronize(h->stream), "copy");
+        vals = copy.data();
+      }
+    } else if (which == 0) {
       S = &md.sym_e;
       if (L.slab_host_c) {
         off = &L.slab_host_c->panel_off;

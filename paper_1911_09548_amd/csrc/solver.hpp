@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "factor.hpp"
+#include "factor_dev.hpp"
 #include "kernels.hpp"
 #include "ordering.hpp"
 #include "space.hpp"
@@ -29,6 +30,7 @@ struct DevFactor {
   SolvePlan plan{};
   int64_t u_rows = 0;            // sum of r_s
   int64_t factor_bytes = 0;
+  std::vector<int64_t> h_panel_off;  // panel offsets (host copy)
   // host-side plan storage (descriptors point into device arrays)
   std::vector<int64_t> h_tgt_off;
   std::vector<SolvePlan::Launch> fwd, bwd;
@@ -39,9 +41,12 @@ struct MeshData {
   SpaceLevel *S = nullptr;
   NdTree nd;
   Symbolic sym_e, sym_v;
+  FrontPlan fp_e, fp_v;          // assembly plans of the device factorisation
   Csr Mp, Kp;                    // M, K in factor (internal) numbering
+  std::vector<int32_t> sched;    // residual visiting order of the internal rows
   // device
   int64_t *d_ptr = nullptr;
+  int32_t *d_sched = nullptr;
   int32_t *d_col = nullptr;
   double *d_mval = nullptr, *d_kval = nullptr;
   float *d_mval32 = nullptr, *d_kval32 = nullptr;
@@ -111,12 +116,14 @@ struct stmg_handle {
   std::vector<stmg::DevBuf> bufs;
   int64_t device_bytes = 0, factor_bytes = 0;
   double *d_partial = nullptr, *d_scalar = nullptr;
+  double *d_halo = nullptr;  // residual segment hand-over, 2 * n_e (finest) values
   int32_t n_partial = 0;
   double *d_tmp[3] = {nullptr, nullptr, nullptr};
   float *f_tmp[3] = {nullptr, nullptr, nullptr};
   double bnorm = 0.0;
   std::vector<double> history;
   double setup_s = 0.0, solve_s = 0.0;
+  rocblas_handle rb = nullptr;          // during the device setup phase only
   stmg::ProfState prof_state;
   stmg::Profiler prof;
   int32_t cycles = 0;

@@ -44,9 +44,9 @@ class Options(C.Structure):
     _fields_ = [("omega", C.c_double), ("lambda_crit", C.c_double),
                 ("allow_space_coarsening", C.c_int32), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
-                ("host_only", C.c_int32), ("factor_on_device", C.c_int32),
+                ("host_only", C.c_int32), ("stream_chunk", C.c_int32), ("row_schedule", C.c_int32),
                 ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32), ("factor_transpose", C.c_int32),
-                ("gemm_splitk", C.c_int32)]
+                ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -120,12 +120,13 @@ def lib():
         L.stmg_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.stmg_server_destroy.argtypes = [vp]
         L.stmg_profile.argtypes = [vp, ip]
+        L.stmg_set_stream_tuning.argtypes = [vp, ip, ip]
         L.stmg_profile_count.argtypes = [vp, C.POINTER(C.c_int32)]
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_residual", "stmg_level_apply",
                      "stmg_export_matrix", "stmg_export_factor", "stmg_profile", "stmg_profile_count",
-                     "stmg_profile_get", "stmg_server_create", "stmg_submit", "stmg_poll", "stmg_server_wait",
+                     "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create", "stmg_submit", "stmg_poll", "stmg_server_wait",
                      "stmg_server_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -296,6 +297,10 @@ class Solver:
     def profile(self, enable=True):
         _check(lib().stmg_profile(self._h, 1 if enable else 0))
 
+    def set_stream_tuning(self, stream_chunk=0, row_schedule=0):
+        """Residual launch shape on the live handle (see the options of the same names)."""
+        _check(lib().stmg_set_stream_tuning(self._h, stream_chunk, row_schedule))
+
     def profile_report(self):
         """Per-kernel launch statistics gathered since profile(True)."""
         n = C.c_int32()
@@ -311,7 +316,7 @@ class Solver:
         return sorted(out, key=lambda d: -d["ms"])
 
     def export_factor(self, level, which):
-        """Host copy of a factor (host_only handles): dict of numpy arrays."""
+        """Host copy of a factor (host factors, or a device handle's FP64 panels): dict of numpy arrays."""
         n, ns, nr, npan, cpx = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
         refs = [C.byref(x) for x in (n, ns, nr, npan, cpx)]
         _check(lib().stmg_export_factor(self._h, level, which, *refs, *([None] * 6)))

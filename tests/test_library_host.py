@@ -174,6 +174,18 @@ def test_invalid_inputs_are_rejected(stmg):
     bad_parent.levels[1].vertex_parent[5] = [10**6, 0]
     assert _setup_rc(stmg, bad_parent) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, omega=0.0) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, stream_chunk=3) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, row_schedule=2) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, stream_chunk=4, row_schedule=1) == stmg.STMG_OK
+
+
+def test_stream_tuning_values(stmg):
+    h = stmg.Solver(inputs.config_unit_manufactured(2, 4, 1), host_only=1)
+    L = stmg.lib()
+    assert L.stmg_set_stream_tuning(h._h, 8, 1) == stmg.STMG_OK
+    assert L.stmg_set_stream_tuning(h._h, 5, 0) == stmg.STMG_EINVAL
+    assert L.stmg_set_stream_tuning(h._h, 0, -1) == stmg.STMG_EINVAL
+    h.close()
 
 
 def test_device_entry_points_refuse_host_only(stmg):
