@@ -72,6 +72,74 @@ def oracle_sample(args):
                       "s_per_cycle": t_cycle}))
 
 
+def serving_bench(args):
+    """Serving form: a seeded Poisson stream of solve requests through the
+    continuous-batching server (FP32 smoother, FP64 refinement to 1e-8).
+    Arrivals run at 0.8x the single-stream capacity measured on the first
+    requests of the same stream; latency is submission to result."""
+    import numpy as np
+    from paper_1911_09548_amd import inputs, stmg
+    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+    horizons = tuple(int(v) for v in args.serve_horizons.split(","))
+    stream = inputs.request_stream(n_requests=args.serve_requests, rate=1.0, seed=5, sizes=sizes,
+                                   horizons=horizons, degrees=(0, 1))
+    problems = []
+    for r in stream:
+        prob = inputs.config_request(r["n"], r["Nt"], r["pt"], r["seed"])
+        E = inputs.count_edges(prob.levels[0].tets, prob.levels[0].coords.shape[0])
+        rhs = np.random.default_rng(r["seed"]).standard_normal((r["Nt"], r["pt"] + 1, E))
+        problems.append((prob, rhs))
+    opts32 = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
+    opts64 = dict(precision=stmg.FP64, rtol=1e-8, max_cycles=60)
+
+    def one_at_a_time(opts, k):
+        srv = stmg.Server(max_active=1, setup_threads=1)
+        t = time.perf_counter()
+        for prob, rhs in problems[:k]:
+            tk = srv.submit(prob, rhs, **opts)
+            assert srv.wait(tk, 600)
+            rc, _, _ = srv.poll(tk, rhs.shape)
+            assert rc == stmg.STMG_OK, rc
+        dt = (time.perf_counter() - t) / k
+        srv.close()
+        return dt
+
+    k = min(args.serve_probe, len(problems))
+    single32 = one_at_a_time(opts32, k)
+    single64 = one_at_a_time(opts64, k)
+    rate = 0.8 / single32
+    log(f"[bench] serving: single-stream {single32:.3f} s/request (FP32 refined), {single64:.3f} (FP64); "
+        f"arrivals at {rate:.2f} requests/s")
+    srv = stmg.Server(max_active=args.serve_active, setup_threads=args.serve_threads)
+    t0 = time.perf_counter()
+    tickets = []
+    for (prob, rhs), r in zip(problems, stream):
+        delay = r["arrival"] / rate - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(prob, rhs, **opts32))
+    worst, ok = 0.0, True
+    for (prob, rhs), tk in zip(problems, tickets):
+        assert srv.wait(tk, 900)
+        rc, _, rep = srv.poll(tk, rhs.shape)
+        ok &= rc == stmg.STMG_OK
+        worst = max(worst, rep["rel_res"])
+    st = srv.stats()
+    srv.close()
+    log(f"[bench] serving: p50 {st['p50_s']:.3f} s, p99 {st['p99_s']:.3f} s, "
+        f"{st['throughput_req_s']:.2f} requests/s, {st['throughput_dofs']:.3e} DOF-updates/s")
+    return {"form": "continuous batching, fp32 smoother + fp64 refinement to 1e-8",
+            "requests": len(problems),
+            "mix": (f"n in {sizes} (x6 Kuhn tets), N_t in {horizons}, p_t in (0, 1), "
+                    "block-random sigma in [1e-2,1e4], nu in [1e-3,100], Gaussian rhs (seeded)"),
+            "arrivals": f"Poisson, {rate:.3f} requests/s = 0.8x single-stream capacity",
+            "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_s": st["mean_s"],
+            "throughput_req_s": st["throughput_req_s"], "throughput_dof_updates_s": st["throughput_dofs"],
+            "single_stream_s_per_request": {"fp32_refined": single32, "fp64": single64, "requests": k},
+            "max_active": args.serve_active, "hbm_peak_bytes": st["hbm_peak"],
+            "all_converged": bool(ok), "max_final_rel_res": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +153,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-sizes", default="8,12,16")
+    ap.add_argument("--serve-horizons", default="16,64,128")
+    ap.add_argument("--serve-probe", type=int, default=4, help="requests timed one at a time")
+    ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-threads", type=int, default=4)
     ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
                     help="first run one plain device copy of this many MiB (read + write), so that "
                          "hardware byte counters can be scaled by a kernel of known traffic")
@@ -218,6 +293,9 @@ def main():
     }
     if prec:
         out["precision_form"] = prec
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        out["serving_form"] = serving_bench(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         cb = cpu_baseline(args)

@@ -105,7 +105,8 @@ typedef struct {
   int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */
   int32_t factor_transpose;      /* also keep P^T for the backward solves: -1 auto, 0 never, 1 always */
   int32_t gemm_splitk;           /* solve K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
-  int32_t device_factor;         /* 1 (default): numeric factorisation on the GPU; 0: on the host */
+  int32_t device_factor;         /* numeric factorisation: -1 (default) on the GPU when the finest slab
+                                    factor has >= 1e6 entries, else on the host; 1 GPU; 0 host */
 } stmg_options;
 
 typedef struct {

@@ -4,12 +4,16 @@
 // latency percentiles and throughput.
 //
 // Life of a request: submitted (host copies of its inputs) -> host setup on
-// a worker thread (assembly, orderings, factorisations; no HIP calls) ->
-// admitted by the scheduler thread once its estimated device bytes fit the
-// HBM budget (device setup on its own stream, right-hand side uploaded) ->
-// iterations (one in flight per request; the residual norm comes back
+// a worker thread (assembly, hierarchy, orderings, symbolic factorisation,
+// front plans; no HIP calls) -> admitted by the scheduler thread once its
+// estimated device bytes fit the HBM budget and a slot is free -> device
+// setup on a worker thread, on the request's own stream (numeric
+// factorisation on the GPU, uploads, right-hand side) -> iterations driven
+// by the scheduler (one in flight per request; the residual norm comes back
 // through pinned memory and an event, polled without blocking) -> result
 // copied to pinned host memory -> device memory released on its stream.
+// Device setup never runs on the scheduler thread, so a large request's
+// factorisation does not stall the iterations of the requests in flight.
 // Every request runs exactly the kernels it would run alone, in the same
 // order, so its result does not depend on the mix.
 #include <hip/hip_runtime.h>
@@ -36,7 +40,7 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-enum State { PENDING, HOST_SETUP, READY, RUNNING, FINISHING, DONE, FAILED };
+enum State { PENDING, HOST_SETUP, READY, ADMITTED, DEVICE_SETUP, RUNNING, FINISHING, DONE, FAILED };
 
 // Deep copy of a problem description (the ABI borrows arrays for one call).
 struct ProblemCopy {
@@ -107,8 +111,9 @@ struct stmg_server {
   stmg_server_options opt{};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Request>> pending, ready;
+  std::deque<std::shared_ptr<Request>> pending, ready, admitted;
   std::vector<std::shared_ptr<Request>> active;
+  int32_t n_setting_up = 0;  // admitted requests not yet running
   std::map<uint64_t, std::shared_ptr<Request>> all;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -121,6 +126,8 @@ struct stmg_server {
   int device = 0;
 
   void worker_loop();
+  void host_setup(const std::shared_ptr<Request> &r);
+  void device_setup(const std::shared_ptr<Request> &r);
   void scheduler_loop();
   bool admit_one();
   bool progress(Request &r);
@@ -140,70 +147,77 @@ void stmg_server::worker_loop() {
   hipSetDevice(device);
   for (;;) {
     std::shared_ptr<Request> r;
+    bool dev = false;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      cv_work.wait(lk, [&] { return stop || !admitted.empty() || !pending.empty(); });
       if (stop) return;
-      r = pending.front();
-      pending.pop_front();
-      r->state = HOST_SETUP;
+      if (!admitted.empty()) {  // admitted requests hold reservations: first
+        r = admitted.front();
+        admitted.pop_front();
+        r->state = DEVICE_SETUP;
+        dev = true;
+      } else {
+        r = pending.front();
+        pending.pop_front();
+        r->state = HOST_SETUP;
+      }
     }
-    stmg_handle *h = nullptr;
-    int code = STMG_OK;
-    std::string msg;
-    const double t0 = now_s();
-    try {
-      h = internal::setup_host(&r->pc.prob, &r->opt);
-      r->est_bytes = internal::estimate_bytes(h);
-    } catch (const StmgError &e) {
-      code = e.code;
-      msg = e.what();
-    } catch (const std::bad_alloc &) {
-      code = STMG_ENOMEM;
-      msg = "host allocation failed";
-    } catch (const std::exception &e) {
-      code = STMG_EINVAL;
-      msg = e.what();
-    }
-    std::unique_lock<std::mutex> lk(mu);
-    r->setup_s = now_s() - t0;
-    if (code != STMG_OK) {
-      if (h) internal::destroy(h);
-      r->state = FAILED;
-      r->code = code;
-      r->message = msg;
-      r->t_done = now_s();
-      failed++;
-      cv_done.notify_all();
-      continue;
-    }
-    if (r->est_bytes > opt.hbm_budget) {
-      internal::destroy(h);
-      r->state = FAILED;
-      r->code = STMG_ENOMEM;
-      r->message = "request needs more device memory than the server's budget";
-      r->t_done = now_s();
-      failed++;
-      cv_done.notify_all();
-      continue;
-    }
-    r->h = h;
-    r->state = READY;
-    r->t_ready = now_s();
-    ready.push_back(r);
-    cv_work.notify_all();
+    if (dev)
+      device_setup(r);
+    else
+      host_setup(r);
   }
 }
 
-// Admit the oldest ready request if its device bytes fit (caller holds mu).
-bool stmg_server::admit_one() {
-  if (ready.empty() || (int32_t)active.size() >= opt.max_active) return false;
-  std::shared_ptr<Request> r = ready.front();
-  if (reserved + r->est_bytes > opt.hbm_budget) return false;
-  ready.pop_front();
-  reserved += r->est_bytes;
-  peak = std::max(peak, reserved);
+void stmg_server::host_setup(const std::shared_ptr<Request> &r) {
+  stmg_handle *h = nullptr;
+  int code = STMG_OK;
+  std::string msg;
+  const double t0 = now_s();
+  try {
+    h = internal::setup_host(&r->pc.prob, &r->opt);
+    r->est_bytes = internal::estimate_bytes(h);
+  } catch (const StmgError &e) {
+    code = e.code;
+    msg = e.what();
+  } catch (const std::bad_alloc &) {
+    code = STMG_ENOMEM;
+    msg = "host allocation failed";
+  } catch (const std::exception &e) {
+    code = STMG_EINVAL;
+    msg = e.what();
+  }
+  std::unique_lock<std::mutex> lk(mu);
+  r->setup_s = now_s() - t0;
+  if (code == STMG_OK && r->est_bytes > opt.hbm_budget) {
+    code = STMG_ENOMEM;
+    msg = "request needs more device memory than the server's budget";
+  }
+  if (code != STMG_OK) {
+    if (h) internal::destroy(h);
+    r->state = FAILED;
+    r->code = code;
+    r->message = msg;
+    r->t_done = now_s();
+    failed++;
+    cv_done.notify_all();
+    return;
+  }
+  r->h = h;
+  r->state = READY;
+  r->t_ready = now_s();
+  ready.push_back(r);
+  cv_work.notify_all();
+}
+
+// Device setup of an admitted request on its own stream (worker thread).
+void stmg_server::device_setup(const std::shared_ptr<Request> &r) {
   Request &q = *r;
+  const double t0 = now_s();
+  int code = STMG_OK;
+  std::string msg;
+  double bn = 0.0;
   try {
     hipc(hipStreamCreateWithFlags(&q.stream, hipStreamNonBlocking), "hipStreamCreate");
     q.h->stream_ordered = true;
@@ -226,17 +240,43 @@ bool stmg_server::admit_one() {
     hipc(hipHostMalloc((void **)&q.pin_norm, sizeof(double), hipHostMallocDefault), "hipHostMalloc");
     hipc(hipHostMalloc((void **)&q.pin_x, n * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
     hipc(hipEventCreateWithFlags(&q.ev, hipEventDisableTiming), "hipEventCreate");
-    double bn = 0.0;
-    int rc = stmg_load(q.h, q.d_rhs, q.d_u0, nullptr, &bn);
+    const int rc = stmg_load(q.h, q.d_rhs, q.d_u0, nullptr, &bn);
     if (rc != STMG_OK) fail(rc, internal::last_error());
-    q.bnorm = bn;
-    q.t_admit = now_s();
-    q.state = RUNNING;
-    active.push_back(r);
-    if (bn == 0.0) finish(q, STMG_OK, "");
   } catch (const StmgError &e) {
-    finish(q, e.code, e.what());
+    code = e.code;
+    msg = e.what();
+  } catch (const std::bad_alloc &) {
+    code = STMG_ENOMEM;
+    msg = "host allocation failed";
   }
+  std::unique_lock<std::mutex> lk(mu);
+  n_setting_up--;
+  q.setup_s += now_s() - t0;
+  q.t_admit = now_s();
+  q.state = RUNNING;
+  active.push_back(r);
+  if (code != STMG_OK)
+    finish(q, code, msg.c_str());
+  else {
+    q.bnorm = bn;
+    if (bn == 0.0) finish(q, STMG_OK, "");
+  }
+  cv_work.notify_all();
+}
+
+// Admit the oldest ready request if its device bytes fit and a slot is free
+// (caller holds mu): reserve its bytes and queue its device setup.
+bool stmg_server::admit_one() {
+  if (ready.empty() || (int32_t)active.size() + n_setting_up >= opt.max_active) return false;
+  std::shared_ptr<Request> r = ready.front();
+  if (reserved + r->est_bytes > opt.hbm_budget) return false;
+  ready.pop_front();
+  reserved += r->est_bytes;
+  peak = std::max(peak, reserved);
+  r->state = ADMITTED;
+  n_setting_up++;
+  admitted.push_back(r);
+  cv_work.notify_all();
   return true;
 }
 
@@ -353,7 +393,7 @@ void stmg_server::scheduler_loop() {
                                 [](const std::shared_ptr<Request> &r) { return r->state == DONE || r->state == FAILED; }),
                  active.end());
     if (!moved) {
-      if (active.empty() && ready.empty())
+      if (active.empty())
         cv_work.wait_for(lk, std::chrono::milliseconds(5));
       else {
         lk.unlock();
@@ -484,7 +524,7 @@ int stmg_server_stats(stmg_server *s, stmg_server_stats_t *st) {
   st->completed = s->completed;
   st->failed = s->failed;
   st->active = (int64_t)s->active.size();
-  st->pending = (int64_t)(s->pending.size() + s->ready.size());
+  st->pending = (int64_t)(s->pending.size() + s->ready.size()) + s->n_setting_up;
   std::vector<double> l = s->latencies;
   std::sort(l.begin(), l.end());
   auto pct = [&](double p) {
@@ -521,6 +561,8 @@ void stmg_server_destroy(stmg_server *s) {
     s->release(*r);
   }
   for (auto &r : s->ready)
+    if (r->h) internal::destroy(r->h);
+  for (auto &r : s->admitted)
     if (r->h) internal::destroy(r->h);
   delete s;
 }

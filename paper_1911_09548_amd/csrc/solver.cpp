@@ -107,7 +107,9 @@ struct DevTemp {
   DevTemp &operator=(const DevTemp &) = delete;
 };
 
-bool dev_factor(const stmg_handle *h) { return h->opt.device_factor && !h->opt.host_only; }
+// Set by the host phase from the device_factor option: large factors are
+// factored on the GPU; small ones (launch-latency bound there) on the host.
+bool dev_factor(const stmg_handle *h) { return h->device_factor_on; }
 
 // ------------------------------------------------------------- solve plans
 void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
@@ -259,6 +261,7 @@ template <typename T64, typename T32, typename TH>
 void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, DevFactor &D, bool transpose,
                    bool need64, bool need32) {
   D.f.panel_off = dev_upload(h, F.panel_off);
+  D.h_panel_off = F.panel_off;
   D.f.panel = D.f.panel_t = nullptr;
   D.factor_bytes = 0;
   if (need64) upload_panels<T64>(h, S, F, D.f, transpose, D.factor_bytes);
@@ -368,6 +371,9 @@ void setup_mesh_host(stmg_handle *h, MeshData &md) {
   const Topo &T = S.topo;
   md.nd = nested_dissection(T, h->opt.leaf_size);
   md.sym_e = symbolic_from_tree(md.nd, edge_nodes(T, md.nd), S.M);
+  if (md.index == 0)
+    h->device_factor_on = !h->opt.host_only && (h->opt.device_factor > 0 ||
+                                                (h->opt.device_factor < 0 && md.sym_e.nnz_L >= 1000000));
   const bool has_nodal = T.n_int_verts() > 0;
   if (has_nodal) {
     md.sym_v = symbolic_from_tree(md.nd, vertex_nodes(T, md.nd), S.Kn);
@@ -1067,6 +1073,25 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
   const LevelData &L0 = h->levels[0];
   const int64_t v0 = (int64_t)h->meshes[0].S->topo.n_int_edges() * L0.N * h->q * 8;
   bytes += std::min<int64_t>((int64_t)256 << 20, 4 * v0);  // split-K workspace
+  if (dev_factor(h)) {
+    // the largest set of factorisation temporaries alive at once (one
+    // factor at a time): front, update-matrix arena, plan arrays, values and
+    // the FP64 panels of a level that keeps only FP32 ones; plus rocBLAS's
+    // own workspace
+    int64_t temp = 0;
+    auto factor_temp = [&](const FrontPlan &fp, const Symbolic &S, int64_t nnz, int64_t scal, bool fp64_temp) {
+      const int64_t t = (fp.max_m2 + fp.uoff[S.ns]) * scal + 16 * (int64_t)fp.a_pos.size() +
+                        4 * (int64_t)fp.relpos.size() + nnz * scal + (fp64_temp ? S.panel_entries * scal : 0);
+      temp = std::max(temp, t);
+    };
+    for (const auto &md : h->meshes)
+      if (md.S->topo.n_int_verts() > 0) factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false);
+    for (const auto &L : h->levels) {
+      const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+      factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L));
+    }
+    bytes += temp + ((int64_t)128 << 20);
+  }
   return bytes + bytes / 20 + (1 << 20);
 }
 
@@ -1168,7 +1193,7 @@ void stmg_default_options(stmg_options *o) {
   o->gemm_rows = 0;
   o->factor_transpose = -1;
   o->gemm_splitk = 0;
-  o->device_factor = 1;
+  o->device_factor = -1;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {

@@ -67,7 +67,7 @@ def pair(request):
     from oracle.vcycle import SpaceTimeMultigrid
     prob = CASES[request.param]()
     print(f"\n[case] device factorisation {request.param}", flush=True)
-    dev = stmg.Solver(prob)
+    dev = stmg.Solver(prob, device_factor=1)
     host = stmg.Solver(prob, host_only=1)
     ora = SpaceTimeMultigrid(prob)
     yield request.param, prob, dev, host, ora

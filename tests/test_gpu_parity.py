@@ -72,11 +72,16 @@ CASES = {
     # backward read from P (no stored transpose) and forced split-K backward
     "block_n8_N32_p1_noT_split3": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=12, block_hexes=4),
     "unit_n4_N16_p0_split2": lambda: inputs.config_unit_manufactured(4, 16, 0),
+    # numeric factorisation on the GPU (automatic only for large factors)
+    "block_n8_N32_p1_devfactor": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=14, block_hexes=4),
+    "jitter_n6_N16_p0_devfactor": lambda: inputs.config_core_box(n=6, Nt=16, pt=0, seed=3, jitter=0.2),
 }
 OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
         "block_n8_N32_p1": dict(gemm_rows=32),
         "block_n8_N32_p1_noT_split3": dict(factor_transpose=0, gemm_splitk=3),
-        "unit_n4_N16_p0_split2": dict(gemm_splitk=2)}
+        "unit_n4_N16_p0_split2": dict(gemm_splitk=2),
+        "block_n8_N32_p1_devfactor": dict(device_factor=1),
+        "jitter_n6_N16_p0_devfactor": dict(device_factor=1)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))

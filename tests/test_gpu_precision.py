@@ -23,7 +23,9 @@ CASES = {
     "unit_n4_N16_p1": lambda: inputs.config_unit_manufactured(4, 16, 1),
     "block_n8_N32_p1": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=5, block_hexes=4),
     "block_n8_N8_p0": lambda: inputs.config_block_random(n=8, Nt=8, pt=0, seed=6, block_hexes=4),
+    "block_n8_N16_p1_devfactor": lambda: inputs.config_block_random(n=8, Nt=16, pt=1, seed=7, block_hexes=4),
 }
+OPTS = {"block_n8_N16_p1_devfactor": dict(device_factor=1)}
 
 
 def _dev(a):
@@ -52,7 +54,7 @@ def pair(request):
     from oracle.vcycle import SpaceTimeMultigrid
     prob = CASES[request.param]()
     print(f"\n[case] {request.param} (precision form)", flush=True)
-    gpu = stmg.Solver(prob, precision=stmg.FP32_REFINED, rtol=1e-8)
+    gpu = stmg.Solver(prob, precision=stmg.FP32_REFINED, rtol=1e-8, **OPTS.get(request.param, {}))
     ora = SpaceTimeMultigrid(prob)
     tols = []
     for lev in ora.levels:

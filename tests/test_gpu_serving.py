@@ -137,3 +137,25 @@ def test_failures_are_status_codes():
     assert rc1 == stmg.STMG_ENOTCONV and rep1["cycles"] == 1
     assert rc2 == stmg.STMG_ENUMERIC
     srv.close()
+
+
+def test_device_factorisation_in_the_mix():
+    """Requests factored on the GPU (device setup on worker threads, on each
+    request's stream) next to host-factored ones: every result equals the
+    plain solver's with the same options, bitwise."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    reqs = [(_request(8, 16, 1, 501), 1), (_request(6, 32, 0, 502), 1), (_request(8, 8, 1, 503), 0),
+            (_request(4, 64, 1, 504), 1), (_request(6, 16, 1, 505), 0)]
+    srv = stmg.Server(max_active=4, setup_threads=3)
+    tickets = [srv.submit(p, r, precision=stmg.FP32_REFINED, device_factor=d) for (p, r), d in reqs]
+    for ((p, r), d), t in zip(reqs, tickets):
+        assert srv.wait(t, 300)
+        rc, x, rep = srv.poll(t, r.shape)
+        assert rc == stmg.STMG_OK, rc
+        s = stmg.Solver(p, precision=stmg.FP32_REFINED, device_factor=d)
+        xs, rep_s = s.solve(torch.from_numpy(r).cuda())
+        s.close()
+        assert rep_s["cycles"] == rep["cycles"]
+        assert np.array_equal(xs.cpu().numpy(), x)
+    srv.close()
