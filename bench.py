@@ -7,7 +7,14 @@ A step is one solver iteration: a full V-cycle over all levels (SAS
 smoothing, nodal auxiliary correction, coarse-grid correction) followed by
 the fine-level residual norm. Inputs are resident in HBM when timing starts.
 
+Besides the FP64 line the run reports the precision form (FP32 V-cycle inside
+FP64 refinement) on the same workload, the serving form (a seeded Poisson
+stream of requests through the continuous-batching server: p50/p99 latency
+and throughput), the roofline of the dominant kernel and of the residual, and
+the CPU oracle on a bounded sample.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 32 --Nt 256 --pt 1]
+    python bench.py --pmc-summary FETCH.csv WRITE.csv   # counter summary, no GPU
 """
 from __future__ import annotations
 
@@ -24,6 +31,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1911_09548_amd", "csrc", "kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_32cube_Nt256_pt1_fp64.md")
 
 
 def log(msg):
@@ -140,6 +149,83 @@ def serving_bench(args):
             "all_converged": bool(ok), "max_final_rel_res": worst}
 
 
+def _source_sha():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _kernel_key(name):
+    """rocprofv3 kernel name -> the profiler's instantiation name."""
+    import re
+    n = name.split("(")[0].replace("void ", "").replace("stmg::", "").replace(" ", "")
+    m = re.match(r"k_sn_gemm<(\w+),(\d+),(\d+),(\d)>", n)
+    if m:
+        return f"k_sn_gemm<{m.group(1)},{m.group(2)},{m.group(3)},{['fwd', 'bwd', 'bwdT'][int(m.group(4))]}>"
+    m = re.match(r"k_residual<(\w+),(\d+),(\d+),(true|false)>", n)
+    if m:
+        return f"k_residual<{m.group(1)},{m.group(2)},{m.group(3)}>"
+    return n
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for the plain copy kernel of known size in the same run
+    (--hbm-calibrate). Prints a markdown table and one machine-readable line
+    per kernel: `traffic <kernel> <fetch B> <write B> <kernels.hip sha>`."""
+    import collections
+    import csv
+
+    def load(path, counter):
+        agg = collections.defaultdict(lambda: [0, 0.0])
+        calib = None
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "neg_kernel" in r["Kernel_Name"]:
+                calib = v
+                continue
+            a = agg[_kernel_key(r["Kernel_Name"])]
+            a[0] += 1
+            a[1] += v
+        return agg, calib
+
+    f, cf = load(fetch_csv, "FETCH_SIZE")
+    w, cw = load(write_csv, "WRITE_SIZE")
+    copy_kib = 1024.0 * 1024.0  # the calibration copy of the counter runs: --hbm-calibrate 1024
+    sf, sw = copy_kib / cf, copy_kib / cw
+    sha = _source_sha()
+    print(f"Calibration: the 1 GiB copy reads FETCH_SIZE {cf:.0f} KiB (scale {sf:.3f}) and WRITE_SIZE "
+          f"{cw:.0f} KiB (scale {sw:.3f}).\n")
+    print("| kernel | dispatches | fetch MB / dispatch | write MB / dispatch |")
+    print("|---|---|---|---|")
+    rows = sorted(f.items(), key=lambda kv: -kv[1][1])
+    for k, (n, tot) in rows[:20]:
+        wn, wt = w.get(k, [1, 0.0])
+        print(f"| `{k}` | {n} | {tot / n * sf / 1024:.1f} | {wt / max(wn, 1) * sw / 1024:.1f} |")
+    print()
+    for k, (n, tot) in rows[:20]:
+        wn, wt = w.get(k, [1, 0.0])
+        print(f"traffic {k} {tot / n * sf * 1024:.0f} {wt / max(wn, 1) * sw * 1024:.0f} {sha}")
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it is absent or the kernel source changed since."""
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    sha = _source_sha()
+    for ln in lines:
+        p = ln.split()
+        if len(p) == 5 and p[0] == "traffic" and p[1] == kernel and p[4] == sha:
+            return float(p[2]) + float(p[3])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +239,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form measurement")
+    ap.add_argument("--factor", choices=("auto", "gpu", "host"), default="auto",
+                    help="where the numeric factorisation of the setup runs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-form measurement")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-sizes", default="8,12,16")
@@ -163,10 +251,15 @@ def main():
     ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
                     help="first run one plain device copy of this many MiB (read + write), so that "
                          "hardware byte counters can be scaled by a kernel of known traffic")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 counter runs (no GPU work)")
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
         oracle_sample(args)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -191,7 +284,8 @@ def main():
     prob = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
     log(f"[bench] setup n={args.n} Nt={args.Nt} pt={args.pt}")
     t0 = time.perf_counter()
-    solver = stmg.Solver(prob, rtol=1e-8, max_cycles=100)
+    dev_factor = {"auto": -1, "gpu": 1, "host": 0}[args.factor]
+    solver = stmg.Solver(prob, rtol=1e-8, max_cycles=100, device_factor=dev_factor)
     setup_s = time.perf_counter() - t0
     levels = [solver.level_info(l) for l in range(solver.n_levels)]
     log(f"[bench] setup {setup_s:.1f}s, levels " +
@@ -232,7 +326,17 @@ def main():
         achieved = top["bytes"] / top["launches"] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof["traffic"] = recorded_traffic(top["kernel"])
     roof.update({"kernel": top["kernel"], "avg_launch_us": avg_s * 1e6, "launches": top["launches"]})
+    # the HBM-bound residual (largest total time among its shapes), against HBM peak
+    res = max((k for k in kernels if k["kernel"].startswith("k_residual")), key=lambda k: k["ms"], default=None)
+    roof_res = None
+    if res:
+        r_avg = res["ms"] * 1e-3 / res["launches"]
+        r_ach = res["bytes"] / res["launches"] / r_avg / 1e9
+        roof_res = {"bound": "hbm", "achieved": r_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": r_ach / HBM_PEAK_GBS, "traffic": recorded_traffic(res["kernel"]),
+                    "kernel": res["kernel"], "avg_launch_us": r_avg * 1e6, "launches": res["launches"]}
     breakdown = [{"kernel": k["kernel"], "ms_per_step": k["ms"] / args.steps,
                   "launches_per_step": k["launches"] // args.steps,
                   "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12,
@@ -256,7 +360,7 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] setup of the precision form (FP32 smoother, FP64 refinement)")
         t0 = time.perf_counter()
-        s32 = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=stmg.FP32_REFINED)
+        s32 = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=stmg.FP32_REFINED, device_factor=dev_factor)
         setup32 = time.perf_counter() - t0
         s32.load(rhs)
         s32.cycles(args.warmup)
@@ -289,6 +393,7 @@ def main():
                    "n_interior_edges": n_e, "space_time_dofs": dofs, "levels": len(levels),
                    "setup_s": setup_s, **extra},
         "roofline": roof,
+        "roofline_residual": roof_res,
         "kernels": breakdown,
     }
     if prec:

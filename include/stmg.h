@@ -217,27 +217,29 @@ int stmg_export_matrix(const stmg_handle *h, int32_t level, int32_t which, int32
  * counters and brackets every subsequent supernode-GEMM and residual launch
  * with HIP events recorded on the handle's stream; stmg_profile(h, 0) stops.
  * stmg_profile_count synchronises the stream and aggregates per kernel
- * (instantiation names as "k_sn_gemm<cd,64,64,bwd>", "k_residual<8,2>");
+ * (instantiation names as "k_sn_gemm<cd,64,64,bwdT>", "k_residual<double,8,2>");
  * stmg_profile_get returns kernel i's name, launch count, summed duration
  * and summed algorithmic work: flops (one multiply-add per factor entry and
  * right-hand side for the solves; two per nonzero and column for M and K in
  * the residual) and bytes (each operand read once, each result written
  * once). Timing adds no synchronisation inside a cycle. */
 int stmg_profile(stmg_handle *h, int32_t enable);
+int stmg_profile_count(stmg_handle *h, int32_t *n_kernels);
+int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
+                     double *total_ms, double *flops, double *bytes);
 
 /* Changes the residual's launch shape after setup (same meaning and values
  * as the stream_chunk and row_schedule options); results do not depend on
  * it except for the summation order of the residual norm. STMG_EINVAL on an
  * unknown value. For tuning on a live handle without a second setup. */
 int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_schedule);
-int stmg_profile_count(stmg_handle *h, int32_t *n_kernels);
-int stmg_profile_get(stmg_handle *h, int32_t i, char *name, int32_t name_len, int64_t *launches,
-                     double *total_ms, double *flops, double *bytes);
 
 /* ------------------------------------------------------------- serving
  * A continuous-batching request server. Requests (problem + rhs on the host)
- * are set up on host worker threads, admitted to the GPU when their
- * estimated device bytes fit the HBM budget and a slot is free, and iterated
+ * get their host setup on worker threads, are admitted to the GPU when their
+ * estimated device bytes fit the HBM budget and a slot is free, get their
+ * device setup (factorisation, uploads) on a worker thread and their own
+ * stream, and are iterated
  * concurrently (one non-blocking HIP stream per active request, one
  * iteration in flight each, convergence polled without blocking); results
  * return to host memory and the request's device memory is released on its
