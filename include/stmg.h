@@ -99,7 +99,8 @@ typedef struct {
   double rtol;                   /* relative residual target of stmg_solve, default 1e-8 */
   int32_t max_cycles;            /* cap of stmg_solve, default 100 */
   int32_t host_only;             /* 1: build host data only (no device), for tests */
-  int32_t stream_chunk;          /* residual row segment: max values per lane, 0 = default, 1..16 */
+  int32_t stream_chunk;          /* residual shape: max values per lane of a row segment, 0 = default (16),
+                                    1..16; 32 = LDS-tiled residual (rows in tiles of 64, union staged in LDS) */
   int32_t row_schedule;          /* residual row visiting order: 0 = Morton order of edge midpoints, 1 = storage order */
   int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
   int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */

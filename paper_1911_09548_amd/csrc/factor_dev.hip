@@ -169,6 +169,60 @@ __global__ __launch_bounds__(FB) void k_diag_chol(T *A, int64_t ld, int kb, int3
   }
 }
 
+// Fronts with w <= NB: one wave factors the w x w diagonal block in LDS
+// (lane i owns row i: right-looking L L^T, then the in-place inverse of the
+// lower triangle column by column from the last), and writes inv(L11) into
+// the panel's top block (zeros above the diagonal).
+template <typename T>
+__global__ __launch_bounds__(64) void k_chol_inv_small(const T *F, int64_t m, int w, T *P, int32_t *flag) {
+  __shared__ T Ls[NB * NB];
+  const int i = threadIdx.x;
+  for (int c = 0; c < w; ++c)
+    if (i < w) Ls[i + c * NB] = i >= c ? F[i + c * m] : f_zero(T{});
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    T p = Ls[j + j * NB];
+    if (f_bad_pivot(p)) {
+      if (i == 0) flag[0] = 1;
+      p = f_one(T{});
+    }
+    const T d = f_sqrt(p), dinv = f_recip(d);
+    T lij = f_zero(T{});
+    __syncthreads();  // everyone has read the pivot
+    if (i == j) Ls[j + j * NB] = d;
+    if (i > j && i < w) {
+      lij = f_mul(Ls[i + j * NB], dinv);
+      Ls[i + j * NB] = lij;
+    }
+    __syncthreads();
+    if (i > j && i < w)
+      for (int c = j + 1; c <= i; ++c) Ls[i + c * NB] = f_fms(Ls[i + c * NB], lij, Ls[c + j * NB]);
+    __syncthreads();
+  }
+  // inverse: for j from the last column, Linv[i][j] = -(sum_{k=j+1..i} Linv[i][k] L[k][j]) / L[j][j]
+  for (int j = w - 1; j >= 0; --j) {
+    const T djinv = f_recip(Ls[j + j * NB]);
+    T acc = f_zero(T{});
+    if (i > j && i < w)
+      for (int k = j + 1; k <= i; ++k) acc = f_fms(acc, Ls[i + k * NB], Ls[k + j * NB]);  // acc -= Linv[i,k] L[k,j]
+    __syncthreads();
+    if (i == j) Ls[j + j * NB] = djinv;
+    if (i > j && i < w) Ls[i + j * NB] = f_mul(acc, djinv);
+    __syncthreads();
+  }
+  for (int c = 0; c < w; ++c)
+    if (i < w) P[i + c * m] = i >= c ? Ls[i + c * NB] : f_zero(T{});
+}
+
+// dst (r x w, ld) = src (r x w, ld)
+template <typename T>
+__global__ __launch_bounds__(FB) void k_copy_block(const T *src, T *dst, int64_t ld, int32_t r, int32_t w) {
+  const int64_t e = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (e >= (int64_t)r * w) return;
+  const int32_t a = (int32_t)(e % r), c = (int32_t)(e / r);
+  dst[a + c * ld] = src[a + c * ld];
+}
+
 // P (w x w, ld) = identity
 template <typename T>
 __global__ __launch_bounds__(FB) void k_set_identity(T *P, int64_t ld, int32_t w) {
@@ -277,6 +331,23 @@ void rb_trmm_neg(rocblas_handle h, int m, int n, const cd *A, int lda, const cd 
            "ztrmm");
 }
 
+// C = B A^T with A lower triangular (right side)
+void rb_trmm_t(rocblas_handle h, int m, int n, const double *A, int lda, const double *B, int ldb, double *C,
+               int ldc) {
+  const double alpha = 1.0;
+  rb_check(rocblas_dtrmm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                         rocblas_diagonal_non_unit, m, n, &alpha, A, lda, B, ldb, C, ldc),
+           "dtrmm");
+}
+void rb_trmm_t(rocblas_handle h, int m, int n, const cd *A, int lda, const cd *B, int ldb, cd *C, int ldc) {
+  const rocblas_double_complex alpha(1.0, 0.0);
+  rb_check(rocblas_ztrmm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                         rocblas_diagonal_non_unit, m, n, &alpha, reinterpret_cast<const rocblas_double_complex *>(A),
+                         lda, reinterpret_cast<const rocblas_double_complex *>(B), ldb,
+                         reinterpret_cast<rocblas_double_complex *>(C), ldc),
+           "ztrmm");
+}
+
 }  // namespace
 
 template <typename T>
@@ -300,6 +371,24 @@ void factor_device(const Symbolic &S, const FrontPlan &fp, const FrontPlanDev &f
       hipLaunchKernelGGL(k_extend_add<T>, dim3(blocks_for((int64_t)rc * rc)), dim3(FB), 0, st, F, (int64_t)m,
                          (const T *)(arena + fp.uoff[ch]), rc, fd.relpos + S.rptr[ch]);
     }
+    T *P = panel + panel_off[s];
+    if (w <= NB) {
+      // small diagonal block: inv(L11) in one kernel, then
+      // L21 = F21 inv(L11)^T (into the panel), F22 -= L21 L21^T,
+      // W21 = -L21 inv(L11) (into F21's place, then the panel)
+      hipLaunchKernelGGL(k_chol_inv_small<T>, dim3(1), dim3(64), 0, st, (const T *)F, (int64_t)m, w, P, flag);
+      if (r > 0) {
+        rb_trmm_t(rb, r, w, P, m, F + w, m, P + w, m);
+        rb_syrk_sub(rb, r, w, P + w, m, F + w + (int64_t)w * m, m);
+        rb_trmm_neg(rb, r, w, P, m, P + w, m, F + w, m);
+        hipLaunchKernelGGL(k_copy_block<T>, dim3(blocks_for((int64_t)r * w)), dim3(FB), 0, st, (const T *)(F + w),
+                           P + w, (int64_t)m, r, w);
+      }
+      if (S.parent[s] >= 0 && r > 0)
+        hipLaunchKernelGGL(k_take_update<T>, dim3(blocks_for((int64_t)r * r)), dim3(FB), 0, st, (const T *)F,
+                           (int64_t)m, w, r, arena + fp.uoff[s]);
+      continue;
+    }
     // 2. partial factorisation of the first w columns
     for (int32_t k0 = 0; k0 < w; k0 += NB) {
       const int32_t kb = std::min(NB, w - k0), rest = m - k0 - kb;
@@ -315,7 +404,6 @@ void factor_device(const Symbolic &S, const FrontPlan &fp, const FrontPlanDev &f
       hipLaunchKernelGGL(k_take_update<T>, dim3(blocks_for((int64_t)r * r)), dim3(FB), 0, st, (const T *)F,
                          (int64_t)m, w, r, arena + fp.uoff[s]);
     // 3. selective inversion into the panel (ld = m)
-    T *P = panel + panel_off[s];
     hipLaunchKernelGGL(k_set_identity<T>, dim3(blocks_for((int64_t)w * w)), dim3(FB), 0, st, P, (int64_t)m, w);
     rb_trsm(rb, rocblas_side_left, rocblas_operation_none, w, w, F, m, P, m);
     hipLaunchKernelGGL(k_zero_upper<T>, dim3(blocks_for((int64_t)w * w)), dim3(FB), 0, st, P, (int64_t)m, w);

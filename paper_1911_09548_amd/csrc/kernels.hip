@@ -203,6 +203,134 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a, int seg,
   }
 }
 
+// LDS-tiled residual: one block per tile of RES_TILE rows of the visiting
+// order. The tile's matrix entries (neighbour position in the tile's union,
+// M and K values) are staged in LDS once; then, segment by segment of
+// RES_TILE_SEG values, the union's x rows are staged in LDS with
+// coalesced 2-value packets and each row of the tile is computed from there
+// (RES_TILE_SEG / 2 lanes per row, every gathered neighbour read from LDS).
+// The DG coupling into a segment's first slab uses the row's end value
+// carried from the previous segment, so one block does all segments of its
+// rows. Each x row is fetched once per tile that needs it (about 3.4 tiles
+// per row at RES_TILE = 64) instead of once per nonzero.
+template <typename R, int Q>
+__global__ __launch_bounds__(BLOCK) void k_residual_tile(ResidualArgsT<R> a) {
+  constexpr int NPK = RES_TILE_SEG / 2;  // packets (lanes) per row segment
+  constexpr int RPP = BLOCK / NPK;       // rows per pass
+  using PK = Pack<R, 2>;
+  using V = typename PK::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *Xs = reinterpret_cast<V *>(smem);                                     // [union][NPK]
+  R *Mv = reinterpret_cast<R *>(Xs + (int64_t)a.tile_union_max * NPK);    // [nnz]
+  R *Kv = Mv + a.tile_nnz_max;
+  R *carry = Kv + a.tile_nnz_max;                                          // [RES_TILE]
+  int32_t *rp = reinterpret_cast<int32_t *>(carry + RES_TILE);             // [RES_TILE + 1]
+  uint16_t *Lc = reinterpret_cast<uint16_t *>(rp + RES_TILE + 1);          // [nnz]
+  const int W = a.N * Q;
+  const int nseg = W / RES_TILE_SEG;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = tile * RES_TILE;
+  const int nrow = min(RES_TILE, a.n_rows - row0);
+  const int u0 = a.tile_ptr[tile], nu = a.tile_ptr[tile + 1] - u0;
+  // stage the tile's matrix entries: row pointers (one wave, prefix sum),
+  // then the entries
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x;
+    int cnt = 0;
+    if (k < nrow) {
+      const int r = a.sched[row0 + k];
+      cnt = (int)(a.ptr[r + 1] - a.ptr[r]);
+    }
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (k >= o) incl += t;
+    }
+    rp[k] = incl - cnt;
+    if (k == 63) rp[RES_TILE] = incl;
+    carry[k] = (R)0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x / 4; k < nrow; k += BLOCK / 4) {
+    const int r = a.sched[row0 + k];
+    const int64_t p0 = a.ptr[r], p1 = a.ptr[r + 1];
+    for (int64_t j = p0 + (threadIdx.x & 3); j < p1; j += 4) {
+      const int d = rp[k] + (int)(j - p0);
+      Lc[d] = a.lcol[j];
+      Mv[d] = a.mval[j];
+      Kv[d] = a.kval[j];
+    }
+  }
+  const R tau = (R)a.tau;
+  double ss = 0.0;
+  const int pk = threadIdx.x % NPK, lr = threadIdx.x / NPK;
+  for (int seg = 0; seg < nseg; ++seg) {
+    __syncthreads();  // previous segment's readers are done with Xs
+    const int64_t c0 = (int64_t)seg * RES_TILE_SEG;
+    for (int e = threadIdx.x; e < nu * NPK; e += BLOCK) {
+      const int u = e / NPK, p = e % NPK;
+      Xs[e] = *reinterpret_cast<const V *>(a.x + (int64_t)a.tile_cols[u0 + u] * W + c0 + 2 * p);
+    }
+    __syncthreads();
+    for (int k = lr; k < RES_TILE; k += RPP) {
+      const bool active = k < nrow;
+      R am0 = 0, am1 = 0, ak0 = 0, ak1 = 0;
+      if (active) {
+        for (int j = rp[k]; j < rp[k + 1]; ++j) {
+          const V v = Xs[(int)Lc[j] * NPK + pk];
+          const R mv = Mv[j], kv = Kv[j];
+          am0 += mv * PK::get(v, 0);
+          am1 += mv * PK::get(v, 1);
+          ak0 += kv * PK::get(v, 0);
+          ak1 += kv * PK::get(v, 1);
+        }
+      }
+      // end value of this packet's last slab; the previous one from the
+      // lane before, or the row's carry for the segment's first packet
+      const R e = Q == 2 ? am0 + am1 : am1;
+      R prev = __shfl_up(e, 1, NPK);
+      if (pk == 0) prev = active ? carry[k] : (R)0;
+      if (active && pk == NPK - 1) carry[k] = e;  // read above by this row's lane 0 (same wave)
+      if (active) {
+        const int r = a.sched[row0 + k];
+        const int64_t off = (int64_t)r * W + c0 + 2 * pk;
+        const V bv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.b + off));
+        V ov;
+        if constexpr (Q == 1) {
+          const R r0 = PK::get(bv, 0) - am0 + prev - tau * ak0;
+          const R r1 = PK::get(bv, 1) - am1 + am0 - tau * ak1;
+          PK::set(ov, 0, r0);
+          PK::set(ov, 1, r1);
+          ss += (double)r0 * r0 + (double)r1 * r1;
+        } else {
+          const R r0 = PK::get(bv, 0) - (am0 + am1) + prev - tau * ak0;
+          const R r1 = PK::get(bv, 1) + am0 - am1 - prev - (tau / (R)3) * ak1;
+          ss += (double)r0 * r0 + (double)r1 * r1;
+          if (a.mode == RES_OUT_SLABRHS) {
+            const R s2 = (R)1.4142135623730951;
+            PK::set(ov, 0, (R)0.5 * r0);
+            PK::set(ov, 1, (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1);
+          } else {
+            PK::set(ov, 0, r0);
+            PK::set(ov, 1, r1);
+          }
+        }
+        __builtin_nontemporal_store(ov, reinterpret_cast<V *>(a.out + off));
+      }
+    }
+  }
+  if (a.partial) {
+    const double t = block_sum(ss);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = t;
+  }
+}
+
+int64_t residual_tile_lds(int32_t union_max, int32_t nnz_max, int32_t scalar_bytes) {
+  const int64_t npk = RES_TILE_SEG / 2;
+  return (int64_t)union_max * npk * 2 * scalar_bytes + 2LL * nnz_max * scalar_bytes + RES_TILE * scalar_bytes +
+         4LL * (RES_TILE + 1) + 2LL * nnz_max + 16;
+}
+
 namespace {
 // Values per lane C and rows-per-wave layout of a row of W = N q values.
 struct ResShape {
@@ -212,7 +340,7 @@ struct ResShape {
 };
 ResShape residual_shape(int W, int q, int chunk) {
   if (W >= 64 * q) {
-    const int cmax = std::max(q, chunk > 0 ? std::min(chunk, 16) : RES_CHUNK_DEFAULT);
+    const int cmax = std::max(q, chunk > 0 && chunk <= 16 ? chunk : RES_CHUNK_DEFAULT);
     const int C = std::min(W / 64, cmax);
     return {C, true, W / (64 * C)};
   }
@@ -256,12 +384,48 @@ static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, const ResSh
   fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", a.N * a.q, a.q);
 }
 
+// The tiled kernel applies to rows of whole segments with a nonzero x when
+// the handle asks for it (chunk RES_CHUNK_TILES) and the mesh has tiles; on
+// the 32^3 workload it measured about 2x slower than the per-wave kernel (each
+// segment's staging waits behind a barrier), so it is not the default.
 template <typename R>
-void launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
+static bool use_tiles(const ResidualArgsT<R> &a) {
   const int W = a.N * a.q;
+  return a.chunk == RES_CHUNK_TILES && a.tile_ptr && a.x && a.sched && W % RES_TILE_SEG == 0 &&
+         residual_tile_lds(a.tile_union_max, a.tile_nnz_max, sizeof(R)) <= 65536;
+}
+
+template <typename R>
+static void launch_residual_tiles(const ResidualArgsT<R> &a, hipStream_t s) {
+  const int nt = (a.n_rows + RES_TILE - 1) / RES_TILE;
+  const size_t lds = (size_t)residual_tile_lds(a.tile_union_max, a.tile_nnz_max, sizeof(R));
+  if (a.q == 2)
+    hipLaunchKernelGGL((k_residual_tile<R, 2>), dim3(nt), dim3(BLOCK), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_residual_tile<R, 1>), dim3(nt), dim3(BLOCK), lds, s, a);
+}
+
+template <typename R>
+int launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
+  const int W = a.N * a.q;
+  if (use_tiles(a)) {
+    const int nt = (a.n_rows + RES_TILE - 1) / RES_TILE;
+    if (nt == 0) return 0;
+    if (a.prof) {
+      char name[64];
+      snprintf(name, sizeof name, "k_residual_tile<%s,%d>", sizeof(R) == 8 ? "double" : "float", a.q);
+      a.prof->begin(s);
+      launch_residual_tiles(a, s);
+      const double rows = a.n_rows, cols = W, nnz = (double)a.nnz, sz = sizeof(R);
+      a.prof->end(s, name, 4.0 * nnz * cols, sz * rows * cols * 3.0 + (4.0 + 2.0 * sz) * nnz + 8.0 * (rows + 1));
+      return nt;
+    }
+    launch_residual_tiles(a, s);
+    return nt;
+  }
   const ResShape sh = residual_shape(W, a.q, a.chunk);
   const int nb = residual_blocks_per_launch(a.n_rows, W, sh);
-  if (nb == 0) return;
+  if (nb == 0) return 0;
   if (a.prof) {
     // algorithmic traffic: x, b read once, out written once, the pattern and
     // both value arrays read once; 4 flops per nonzero and column (two FMAs)
@@ -271,12 +435,13 @@ void launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
     launch_residual_inner(a, nb, sh, s);
     const double rows = a.n_rows, cols = W, nnz = (double)a.nnz, sz = sizeof(R);
     a.prof->end(s, name, 4.0 * nnz * cols, sz * rows * cols * (a.x ? 3.0 : 2.0) + (4.0 + 2.0 * sz) * nnz + 8.0 * (rows + 1));
-    return;
+    return nb * sh.nseg;
   }
   launch_residual_inner(a, nb, sh, s);
+  return nb * sh.nseg;
 }
-template void launch_residual<double>(const ResidualArgsT<double> &, hipStream_t);
-template void launch_residual<float>(const ResidualArgsT<float> &, hipStream_t);
+template int launch_residual<double>(const ResidualArgsT<double> &, hipStream_t);
+template int launch_residual<float>(const ResidualArgsT<float> &, hipStream_t);
 
 // --------------------------------------------------------------- reductions
 __global__ __launch_bounds__(BLOCK) void k_sum(const double *p, int32_t n, double *out) {
@@ -358,28 +523,47 @@ void launch_slab_rhs(int32_t n_rows, int32_t N, int32_t q, const R *r, R *w, hip
 }
 
 // ------------------------------------------------------- nodal correction
-// g[v][c] = sum over edges e at v of sign(e, v) r[e][c]  (G^T, entries +-1)
-template <typename R>
+// g[v][c] = sum over edges e at v of sign(e, v) r[e][c]  (G^T, entries +-1).
+// One thread per 2-value packet of a vertex row (W is even except for
+// N = 1, q = 1, which takes the 1-value path); edge lists are broadcast
+// loads shared by the lanes of a row.
+template <typename R, int P>
 __global__ __launch_bounds__(BLOCK) void k_gradT(int32_t n_v, int32_t W, const int64_t *ptr,
                                                  const int32_t *edge, const int8_t *sign, const R *r, R *g) {
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
+  const int32_t WP = W / P;
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= (int64_t)n_v * W) return;
-  const int32_t v = (int32_t)(i / W), c = (int32_t)(i % W);
-  R acc = 0;
-  for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
-    const R t = r[(int64_t)edge[k] * W + c];
-    acc += sign[k] > 0 ? t : -t;
+  if (i >= (int64_t)n_v * WP) return;
+  const int32_t v = (int32_t)(i / WP), c = (int32_t)(i % WP) * P;
+  R acc[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) acc[t] = 0;
+  const int64_t k1 = ptr[v + 1];
+#pragma unroll 4
+  for (int64_t k = ptr[v]; k < k1; ++k) {
+    const V x = *reinterpret_cast<const V *>(r + (int64_t)edge[k] * W + c);
+    const R sg = sign[k] > 0 ? (R)1 : (R)-1;
+#pragma unroll
+    for (int t = 0; t < P; ++t) acc[t] += sg * PK::get(x, t);
   }
-  g[i] = acc;
+  V out;
+#pragma unroll
+  for (int t = 0; t < P; ++t) PK::set(out, t, acc[t]);
+  *reinterpret_cast<V *>(g + (int64_t)v * W + c) = out;
 }
 
 template <typename R>
 void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edge, const int8_t *sign,
                   const R *r, R *g, hipStream_t s) {
-  const int64_t n = (int64_t)n_v * W;
+  const int P = W % 2 == 0 ? 2 : 1;
+  const int64_t n = (int64_t)n_v * (W / P);
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gradT<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_v, W, ptr,
-                     edge, sign, r, g);
+  const dim3 grid((unsigned)((n + BLOCK - 1) / BLOCK));
+  if (P == 2)
+    hipLaunchKernelGGL((k_gradT<R, 2>), grid, dim3(BLOCK), 0, s, n_v, W, ptr, edge, sign, r, g);
+  else
+    hipLaunchKernelGGL((k_gradT<R, 1>), grid, dim3(BLOCK), 0, s, n_v, W, ptr, edge, sign, r, g);
 }
 
 // Inverse of the time operator on the gradient subspace (K_t on the diagonal,
@@ -473,27 +657,45 @@ void launch_time_scan(int32_t n_v, int32_t N, int32_t q, R *g, hipStream_t s) {
   fprintf(stderr, "stmg: unsupported scan shape W=%d q=%d\n", W, q);
 }
 
-// x[e][c] += y[head(e)][c] - y[tail(e)][c]  (G, boundary vertices dropped)
-template <typename R>
+// x[e][c] += y[head(e)][c] - y[tail(e)][c]  (G, boundary vertices dropped);
+// one thread per 2-value packet as in k_gradT.
+template <typename R, int P>
 __global__ __launch_bounds__(BLOCK) void k_grad_add(int32_t n_e, int32_t W, const int32_t *head,
                                                     const int32_t *tail, const R *y, R *x) {
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
+  const int32_t WP = W / P;
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= (int64_t)n_e * W) return;
-  const int32_t e = (int32_t)(i / W), c = (int32_t)(i % W);
-  R d = 0;
+  if (i >= (int64_t)n_e * WP) return;
+  const int32_t e = (int32_t)(i / WP), c = (int32_t)(i % WP) * P;
   const int32_t h = head[e], t = tail[e];
-  if (h >= 0) d += y[(int64_t)h * W + c];
-  if (t >= 0) d -= y[(int64_t)t * W + c];
-  x[i] += d;
+  V d;
+#pragma unroll
+  for (int u = 0; u < P; ++u) PK::set(d, u, (R)0);
+  if (h >= 0) d = *reinterpret_cast<const V *>(y + (int64_t)h * W + c);
+  if (t >= 0) {
+    const V yt = *reinterpret_cast<const V *>(y + (int64_t)t * W + c);
+#pragma unroll
+    for (int u = 0; u < P; ++u) PK::set(d, u, PK::get(d, u) - PK::get(yt, u));
+  }
+  V *xp = reinterpret_cast<V *>(x + (int64_t)e * W + c);
+  V xv = *xp;
+#pragma unroll
+  for (int u = 0; u < P; ++u) PK::set(xv, u, PK::get(xv, u) + PK::get(d, u));
+  *xp = xv;
 }
 
 template <typename R>
 void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const R *y, R *x,
                      hipStream_t s) {
-  const int64_t n = (int64_t)n_e * W;
+  const int P = W % 2 == 0 ? 2 : 1;
+  const int64_t n = (int64_t)n_e * (W / P);
   if (n == 0) return;
-  hipLaunchKernelGGL(k_grad_add<R>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n_e, W,
-                     head, tail, y, x);
+  const dim3 grid((unsigned)((n + BLOCK - 1) / BLOCK));
+  if (P == 2)
+    hipLaunchKernelGGL((k_grad_add<R, 2>), grid, dim3(BLOCK), 0, s, n_e, W, head, tail, y, x);
+  else
+    hipLaunchKernelGGL((k_grad_add<R, 1>), grid, dim3(BLOCK), 0, s, n_e, W, head, tail, y, x);
 }
 
 // ---------------------------------------------------------------- transfers
@@ -1130,9 +1332,18 @@ template <typename T>
 void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, T *U, hipStream_t s) {
   for (int h = 0; h < p.n_heights; ++h) {
     const int64_t t0 = p.h_tgt_off[h], t1 = p.h_tgt_off[h + 1];
-    if (t1 > t0)
+    if (t1 > t0) {
+      if (p.prof) p.prof->begin(s);
       hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(BLOCK), 0, s, p.tgt + t0,
                          t1 - t0, p.src, nc, X, U);
+      if (p.prof) {
+        // each source row read once, each target row read and written once
+        char name[48];
+        snprintf(name, sizeof name, "k_fwd_asm<%s>", Scalar<T>::name);
+        const double rows = (double)(p.h_src_off[h + 1] - p.h_src_off[h]) + 2.0 * (double)(t1 - t0);
+        p.prof->end(s, name, 0.0, rows * nc * sizeof(T));
+      }
+    }
     launch_sn_gemm<T, 0>(f, p.fwd[h], p.tile_rows, p.splitk, p.prof, p.splitk_ws, p.splitk_bytes, nc, X, Z, U,
                          s);
   }

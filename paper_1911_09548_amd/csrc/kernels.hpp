@@ -48,13 +48,26 @@ struct ResidualArgsT {
   int32_t chunk = 0;            // max values per lane of a row segment (0: default)
   void *halo = nullptr;         // 2 * n_rows values of R: segment-to-segment end values
   const int32_t *sched = nullptr;  // visiting order of the rows (null: storage order)
+  // LDS tiles (used when tile_cols is set and chunk == RES_CHUNK_TILES): tile t holds the
+  // rows sched[t*RES_TILE ..], the sorted union of their neighbour rows
+  // tile_cols[tile_ptr[t] .. tile_ptr[t+1]) and, per nonzero in CSR order,
+  // the neighbour's position in that union (lcol)
+  const int32_t *tile_ptr = nullptr, *tile_cols = nullptr;
+  const uint16_t *lcol = nullptr;
+  int32_t tile_union_max = 0, tile_nnz_max = 0;
 };
 using ResidualArgs = ResidualArgsT<double>;
 constexpr int RES_CHUNK_DEFAULT = 16;
+constexpr int RES_CHUNK_TILES = 32;  // stream_chunk value selecting the LDS-tiled residual
+constexpr int RES_TILE = 64;      // rows per LDS tile of the residual
+constexpr int RES_TILE_SEG = 16;  // values per row segment staged in LDS
 enum { RES_OUT_R = 0, RES_OUT_SLABRHS = 1 };
 int residual_blocks(int32_t n_rows, int32_t W, int32_t q, int32_t chunk);
+// LDS bytes of one residual tile (staged union segment + matrix entries).
+int64_t residual_tile_lds(int32_t union_max, int32_t nnz_max, int32_t scalar_bytes);
+// Returns the number of per-block norm partials written (when a.partial).
 template <typename R>
-void launch_residual(const ResidualArgsT<R> &a, hipStream_t s);
+int launch_residual(const ResidualArgsT<R> &a, hipStream_t s);
 
 // Sum of `n` doubles in fixed order (deterministic), result at out[0].
 void launch_sum(const double *partial, int32_t n, double *out, hipStream_t s);
@@ -138,6 +151,7 @@ struct SolvePlan {
   // target's sources [src_begin, next src_begin)
   int32_t n_heights;
   const int64_t *h_tgt_off;      // host [H+1]
+  const int64_t *h_src_off;      // host [H+1] first source of each height
   const AsmTarget *tgt;          // device [n_tgt + 1] (sentinel)
   const int64_t *src;            // device U rows
   // one GEMM launch per height and direction: host descriptors, device tasks

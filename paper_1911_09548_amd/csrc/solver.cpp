@@ -130,9 +130,11 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   std::vector<AsmTarget> tgt;
   std::vector<int64_t> src;
   D.h_tgt_off.assign(H + 1, 0);
+  D.h_src_off.assign(H + 1, 0);
   std::vector<int32_t> pos(S.n, -1);
   for (int32_t hh = 0; hh < H; ++hh) {
     D.h_tgt_off[hh] = (int64_t)tgt.size();
+    D.h_src_off[hh] = (int64_t)src.size();
     for (int32_t s : by_h[hh]) {
       const int32_t c0 = S.col0[s], w = S.width(s), r = S.nrows(s), m = w + r;
       for (int32_t j = 0; j < w; ++j) pos[c0 + j] = j;
@@ -151,6 +153,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
     }
   }
   D.h_tgt_off[H] = (int64_t)tgt.size();
+  D.h_src_off[H] = (int64_t)src.size();
   tgt.push_back({0, (int64_t)src.size()});  // sentinel
   // one forward and one backward GEMM launch per height; task prefixes for
   // 64-row and 32-row tiles
@@ -221,6 +224,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.plan.splitk_ws = nullptr;
   D.plan.splitk_bytes = 0;
   D.plan.h_tgt_off = D.h_tgt_off.data();
+  D.plan.h_src_off = D.h_src_off.data();
   D.plan.tgt = dtg;
   D.plan.src = dsrc;
   D.plan.fwd = D.fwd.data();
@@ -366,6 +370,45 @@ std::vector<int32_t> morton_schedule(const Topo &T, const std::vector<int32_t> &
   return sched;
 }
 
+// LDS tiles of the residual: RES_TILE consecutive rows of the visiting
+// order, the sorted union of their neighbour rows and each nonzero's
+// position in it. Meshes whose largest tile would not fit the LDS budget
+// keep the per-wave residual (no tiles).
+void residual_tiles(MeshData &md) {
+  const Csr &A = md.Mp;
+  const int32_t n = A.n_rows, nt = (n + RES_TILE - 1) / RES_TILE;
+  md.tile_ptr.assign(nt + 1, 0);
+  md.tile_cols.clear();
+  md.lcol.assign(A.nnz(), 0);
+  md.tile_union_max = md.tile_nnz_max = 0;
+  std::vector<int32_t> cols;
+  for (int32_t t = 0; t < nt; ++t) {
+    cols.clear();
+    int32_t nnz = 0;
+    for (int32_t k = t * RES_TILE; k < std::min(n, (t + 1) * RES_TILE); ++k) {
+      const int32_t r = md.sched[k];
+      for (int64_t j = A.ptr[r]; j < A.ptr[r + 1]; ++j) cols.push_back(A.col[j]);
+      nnz += (int32_t)(A.ptr[r + 1] - A.ptr[r]);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    if (cols.size() > 65535) {  // lcol is 16-bit
+      md.tile_ptr.clear();
+      return;
+    }
+    for (int32_t k = t * RES_TILE; k < std::min(n, (t + 1) * RES_TILE); ++k) {
+      const int32_t r = md.sched[k];
+      for (int64_t j = A.ptr[r]; j < A.ptr[r + 1]; ++j)
+        md.lcol[j] = (uint16_t)(std::lower_bound(cols.begin(), cols.end(), A.col[j]) - cols.begin());
+    }
+    md.tile_cols.insert(md.tile_cols.end(), cols.begin(), cols.end());
+    md.tile_ptr[t + 1] = (int32_t)md.tile_cols.size();
+    md.tile_union_max = std::max(md.tile_union_max, (int32_t)cols.size());
+    md.tile_nnz_max = std::max(md.tile_nnz_max, nnz);
+  }
+  if (residual_tile_lds(md.tile_union_max, md.tile_nnz_max, sizeof(double)) > 65536) md.tile_ptr.clear();
+}
+
 void setup_mesh_host(stmg_handle *h, MeshData &md) {
   SpaceLevel &S = *md.S;
   const Topo &T = S.topo;
@@ -387,6 +430,7 @@ void setup_mesh_host(stmg_handle *h, MeshData &md) {
   md.Mp = csr_permute_sym(S.M, md.sym_e.perm);
   md.Kp = csr_permute_sym(S.K, md.sym_e.perm);
   md.sched = morton_schedule(T, md.sym_e.perm);
+  residual_tiles(md);
   if (dev_factor(h)) build_front_plan(md.sym_e, S.M, md.fp_e);
 }
 
@@ -396,6 +440,11 @@ void setup_mesh_device(stmg_handle *h, MeshData &md) {
   const bool has_nodal = T.n_int_verts() > 0;
   md.d_ptr = dev_upload(h, md.Mp.ptr);
   md.d_sched = dev_upload(h, md.sched);
+  if (!md.tile_ptr.empty()) {
+    md.d_tile_ptr = dev_upload(h, md.tile_ptr);
+    md.d_tile_cols = dev_upload(h, md.tile_cols);
+    md.d_lcol = dev_upload(h, md.lcol);
+  }
   md.d_col = dev_upload(h, md.Mp.col);
   md.d_mval = dev_upload(h, md.Mp.val);
   md.d_kval = dev_upload(h, md.Kp.val);
@@ -654,7 +703,8 @@ struct OpsT {
   int32_t W(int l) { return h->levels[l].N * h->q; }
   bool coarsest(int l) { return l + 1 == (int)h->levels.size(); }
 
-  void residual(int l, const R *x, const R *b, R *out, int mode, double *partial) {
+  // returns the number of norm partials written (when partial is set)
+  int residual(int l, const R *x, const R *b, R *out, int mode, double *partial) {
     MeshData &md = mesh(l);
     ResidualArgsT<R> a;
     a.n_rows = ne(l);
@@ -675,7 +725,29 @@ struct OpsT {
     a.chunk = h->opt.stream_chunk;
     a.halo = h->d_halo;
     a.sched = h->opt.row_schedule == 0 ? md.d_sched : nullptr;
-    launch_residual(a, s);
+    if (a.sched && md.d_tile_ptr) {
+      a.tile_ptr = md.d_tile_ptr;
+      a.tile_cols = md.d_tile_cols;
+      a.lcol = md.d_lcol;
+      a.tile_union_max = md.tile_union_max;
+      a.tile_nnz_max = md.tile_nnz_max;
+    }
+    return launch_residual(a, s);
+  }
+
+  // Streaming kernels under the per-launch profiler (algorithmic bytes:
+  // each operand read once, each result written once).
+  template <typename Fn>
+  void timed(const char *base, double bytes, Fn &&fn) {
+    if (!h->prof_state.on) {
+      fn();
+      return;
+    }
+    char name[64];
+    snprintf(name, sizeof name, "%s<%s>", base, sizeof(R) == 8 ? "double" : "float");
+    h->prof.begin(s);
+    fn();
+    h->prof.end(s, name, 0.0, bytes);
   }
 
   // w <- A_l^{-1} w in place (slab right-hand-side layout)
@@ -696,7 +768,8 @@ struct OpsT {
     LevelData &L = h->levels[l];
     residual(l, x, b, B::w(L), RES_OUT_SLABRHS, nullptr);
     slab_solve(l, B::w(L));
-    launch_slab_update<R>(ne(l), L.N, h->q, h->opt.omega, B::w(L), x, 0, s);
+    timed("k_slab_update", 3.0 * sizeof(R) * ne(l) * W(l),
+          [&] { launch_slab_update<R>(ne(l), L.N, h->q, h->opt.omega, B::w(L), x, 0, s); });
   }
 
   void nodal_A(int l, R *x, const R *b) {
@@ -705,12 +778,15 @@ struct OpsT {
     if (nv(l) == 0) return;
     const int32_t w = W(l);
     residual(l, x, b, B::w(L), RES_OUT_R, nullptr);
-    launch_gradT<R>(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, B::w(L), B::g(L), s);
+    const double sz = sizeof(R);
+    timed("k_gradT", sz * w * ((double)ne(l) + nv(l)),
+          [&] { launch_gradT<R>(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, B::w(L), B::g(L), s); });
     const FactorDev &F = B::fac(md.nodal);
     solve_forward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), B::un(L), s);
     solve_backward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), s);
-    launch_time_scan<R>(nv(l), L.N, h->q, B::g(L), s);
-    launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s);
+    timed("k_time_scan", 2.0 * sz * w * nv(l), [&] { launch_time_scan<R>(nv(l), L.N, h->q, B::g(L), s); });
+    timed("k_grad_add", sz * w * ((double)nv(l) + 2.0 * ne(l)),
+          [&] { launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s); });
   }
 
   void hybrid(int l, R *x, const R *b) {
@@ -723,23 +799,29 @@ struct OpsT {
 
   void restrict_to(int l, const R *rf, R *rc) {
     LevelData &C = h->levels[l + 1];
-    if (C.mesh != h->levels[l].mesh) {
-      MeshData &mc = mesh(l + 1);
-      launch_restrict<R>(ne(l + 1), C.N, h->q, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, rf, rc, s);
-    } else {
-      launch_restrict<R>(ne(l + 1), C.N, h->q, nullptr, nullptr, nullptr, rf, rc, s);
-    }
+    const double bytes = sizeof(R) * ((double)ne(l) * W(l) + (double)ne(l + 1) * W(l + 1));
+    timed("k_restrict", bytes, [&] {
+      if (C.mesh != h->levels[l].mesh) {
+        MeshData &mc = mesh(l + 1);
+        launch_restrict<R>(ne(l + 1), C.N, h->q, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, rf, rc, s);
+      } else {
+        launch_restrict<R>(ne(l + 1), C.N, h->q, nullptr, nullptr, nullptr, rf, rc, s);
+      }
+    });
   }
 
   void prolong_add(int l, const R *ec, R *xf) {
     // from level l+1 to level l
     LevelData &C = h->levels[l + 1];
-    if (C.mesh != h->levels[l].mesh) {
-      MeshData &mc = mesh(l + 1);
-      launch_prolong_add<R>(ne(l), C.N, h->q, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, ec, xf, s);
-    } else {
-      launch_prolong_add<R>(ne(l), C.N, h->q, nullptr, nullptr, nullptr, ec, xf, s);
-    }
+    const double bytes = sizeof(R) * (2.0 * ne(l) * W(l) + (double)ne(l + 1) * W(l + 1));
+    timed("k_prolong_add", bytes, [&] {
+      if (C.mesh != h->levels[l].mesh) {
+        MeshData &mc = mesh(l + 1);
+        launch_prolong_add<R>(ne(l), C.N, h->q, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, ec, xf, s);
+      } else {
+        launch_prolong_add<R>(ne(l), C.N, h->q, nullptr, nullptr, nullptr, ec, xf, s);
+      }
+    });
   }
 
   void vcycle(int l, R *x, const R *b) {
@@ -760,8 +842,8 @@ struct OpsT {
 
   // ||b - L x||^2 into dst (device), FP64 accumulation
   void residual_norm2(int l, const R *x, const R *b, R *out, double *dst) {
-    residual(l, x, b, out, RES_OUT_R, h->d_partial);
-    launch_sum(h->d_partial, residual_blocks(ne(l), W(l), h->q, h->opt.stream_chunk), dst, s);
+    const int nb = residual(l, x, b, out, RES_OUT_R, h->d_partial);
+    launch_sum(h->d_partial, nb, dst, s);
   }
 };
 
@@ -987,8 +1069,8 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
                "gemm_rows must be 0, 32 or 64");
   {
     const int c = h->opt.stream_chunk;
-    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16, STMG_EINVAL,
-                 "stream_chunk must be 0, 1, 2, 4, 8 or 16");
+    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16 || c == RES_CHUNK_TILES, STMG_EINVAL,
+                 "stream_chunk must be 0, 1, 2, 4, 8, 16 or 32");
     STMG_REQUIRE(h->opt.row_schedule == 0 || h->opt.row_schedule == 1, STMG_EINVAL,
                  "row_schedule must be 0 or 1");
   }
@@ -1471,8 +1553,8 @@ int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_sch
   return guard([&] {
     STMG_REQUIRE(h, STMG_EINVAL, "null handle");
     const int c = stream_chunk;
-    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16, STMG_EINVAL,
-                 "stream_chunk must be 0, 1, 2, 4, 8 or 16");
+    STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16 || c == RES_CHUNK_TILES, STMG_EINVAL,
+                 "stream_chunk must be 0, 1, 2, 4, 8, 16 or 32");
     STMG_REQUIRE(row_schedule == 0 || row_schedule == 1, STMG_EINVAL, "row_schedule must be 0 or 1");
     h->opt.stream_chunk = stream_chunk;
     h->opt.row_schedule = row_schedule;

@@ -32,7 +32,7 @@ struct DevFactor {
   int64_t factor_bytes = 0;
   std::vector<int64_t> h_panel_off;  // panel offsets (host copy)
   // host-side plan storage (descriptors point into device arrays)
-  std::vector<int64_t> h_tgt_off;
+  std::vector<int64_t> h_tgt_off, h_src_off;
   std::vector<SolvePlan::Launch> fwd, bwd;
 };
 
@@ -44,9 +44,14 @@ struct MeshData {
   FrontPlan fp_e, fp_v;          // assembly plans of the device factorisation
   Csr Mp, Kp;                    // M, K in factor (internal) numbering
   std::vector<int32_t> sched;    // residual visiting order of the internal rows
+  std::vector<int32_t> tile_ptr, tile_cols;  // residual LDS tiles (see ResidualArgsT)
+  std::vector<uint16_t> lcol;
+  int32_t tile_union_max = 0, tile_nnz_max = 0;
   // device
   int64_t *d_ptr = nullptr;
   int32_t *d_sched = nullptr;
+  int32_t *d_tile_ptr = nullptr, *d_tile_cols = nullptr;
+  uint16_t *d_lcol = nullptr;
   int32_t *d_col = nullptr;
   double *d_mval = nullptr, *d_kval = nullptr;
   float *d_mval32 = nullptr, *d_kval32 = nullptr;

@@ -32,6 +32,8 @@ CASES = {  # name: (Nt, pt, stream_chunk); chunk 0 = the default (2 values per l
     "N2048_p0": (2048, 0, 0),      # 2048 with one value per slab: 16 segments
     "N2048_p0_c1": (2048, 0, 1),   # one value per lane: 32 segments of 64
     "N4096_p1_c8": (4096, 1, 8),   # 8192: 16 segments of 512
+    "N512_p1_tiles": (512, 1, 32), # LDS-tiled residual: 64 segments of 16 values per tile
+    "N1024_p0_tiles": (1024, 0, 32),
 }
 
 

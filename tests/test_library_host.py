@@ -183,6 +183,7 @@ def test_stream_tuning_values(stmg):
     h = stmg.Solver(inputs.config_unit_manufactured(2, 4, 1), host_only=1)
     L = stmg.lib()
     assert L.stmg_set_stream_tuning(h._h, 8, 1) == stmg.STMG_OK
+    assert L.stmg_set_stream_tuning(h._h, 32, 0) == stmg.STMG_OK
     assert L.stmg_set_stream_tuning(h._h, 5, 0) == stmg.STMG_EINVAL
     assert L.stmg_set_stream_tuning(h._h, 0, -1) == stmg.STMG_EINVAL
     h.close()
