@@ -1008,8 +1008,26 @@ __device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
 
 }  // namespace
 
-// Forward assembly (extend-add): each target row of a front receives the
-// children's update rows in a fixed order. One wavefront per target row.
+// Children's contributions to update row i of supernode s, column col, summed
+// in the fixed order of the assembly plan (the extend-add of the update rows,
+// done where the row is written).
+template <typename T, typename R>
+__device__ inline void children_sum(const FactorDev &f, const T *U, int s, int i, int32_t nc, int col, R &ur,
+                                    R &ui) {
+  const int64_t t = f.uasm[s] + i;
+  const int64_t k1 = f.asm_tgt[t + 1].src_begin;
+  ur = ui = 0;
+  for (int64_t k = f.asm_tgt[t].src_begin; k < k1; ++k) {
+    R a, b;
+    split(U[f.asm_src[k] * nc + col], a, b);
+    ur += a;
+    ui += b;
+  }
+}
+
+// Forward assembly (extend-add) of the rows of the supernodes' own columns:
+// each target row receives the children's update rows in a fixed order. One
+// wavefront per target row.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src,
                                                    int32_t nc, T *X, T *U) {
@@ -1206,10 +1224,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
           if (row < w) {
             make(vr, vi, Z[(int64_t)(c0 + row) * nc + col]);
           } else {
-            T *u = U + (f.uoff[s] + (row - w)) * nc + col;
             R ur, ui;
-            split(*u, ur, ui);
-            make(ur + vr, ui + vi, *u);
+            children_sum(f, U, s, row - w, nc, col, ur, ui);
+            make(ur + vr, ui + vi, U[(f.uoff[s] + (row - w)) * nc + col]);
           }
         } else {
           make(vr, vi, X[(int64_t)(c0 + row) * nc + col]);
@@ -1247,10 +1264,9 @@ __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTas
     } else if (row < w) {
       make(ar, ai, Z[(int64_t)(c0 + row) * nc + col]);
     } else {
-      T *u = U + (f.uoff[s] + (row - w)) * nc + col;
       R ur, ui;
-      split(*u, ur, ui);
-      make(ur + ar, ui + ai, *u);
+      children_sum(f, U, s, row - w, nc, col, ur, ui);
+      make(ur + ar, ui + ai, U[(f.uoff[s] + (row - w)) * nc + col]);
     }
   }
 }
@@ -1331,7 +1347,7 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
 template <typename T>
 void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, T *U, hipStream_t s) {
   for (int h = 0; h < p.n_heights; ++h) {
-    const int64_t t0 = p.h_tgt_off[h], t1 = p.h_tgt_off[h + 1];
+    const int64_t t0 = p.h_tgt_off[h], t1 = p.h_xtgt_end[h];
     if (t1 > t0) {
       if (p.prof) p.prof->begin(s);
       hipLaunchKernelGGL((k_fwd_asm<T>), dim3((unsigned)((t1 - t0 + 3) / 4)), dim3(BLOCK), 0, s, p.tgt + t0,
@@ -1340,7 +1356,7 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
         // each source row read once, each target row read and written once
         char name[48];
         snprintf(name, sizeof name, "k_fwd_asm<%s>", Scalar<T>::name);
-        const double rows = (double)(p.h_src_off[h + 1] - p.h_src_off[h]) + 2.0 * (double)(t1 - t0);
+        const double rows = (double)(p.h_xsrc_end[h] - p.h_src_off[h]) + 2.0 * (double)(t1 - t0);
         p.prof->end(s, name, 0.0, rows * nc * sizeof(T));
       }
     }

@@ -126,6 +126,10 @@ void launch_add_float(int64_t n, const float *x, double *y, hipStream_t s);
 // ------------------------------------------------------------------ solves
 // Multifrontal forward/backward solves with a supernodal L (L L^T = A) for
 // `nc` right-hand sides stored as rows of X (one row per matrix row).
+struct AsmTarget {
+  int64_t dst;             // >= 0: X row; < 0: U row (-1 - index)
+  int64_t src_begin;       // into asm_src
+};
 struct FactorDev {
   int32_t ns, n;
   const int32_t *col0;     // [ns+1]
@@ -136,14 +140,16 @@ struct FactorDev {
   const int64_t *uoff;     // [ns] first U row of each supernode
   const void *panel;       // P_s = [inv(L_ss); -L_{R,s} inv(L_ss)], column-major
   const void *panel_t;     // optional P_s^T (w x m, column-major) for the backward solve
+  // forward assembly of update rows in the GEMM epilogue: supernode s's
+  // update row i is target asm_tgt[uasm[s] + i], whose sources (children's
+  // update rows) are asm_src[src_begin .. next target's src_begin)
+  const int64_t *uasm;
+  const AsmTarget *asm_tgt;
+  const int64_t *asm_src;
 };
 struct SolveTask {
   int32_t s;
   int32_t tile_begin;      // prefix of row tiles
-};
-struct AsmTarget {
-  int64_t dst;             // >= 0: X row; < 0: U row (-1 - index)
-  int64_t src_begin;       // into asm_src
 };
 // Kernel launch plan of one factor (all arrays on device, built on the host).
 struct SolvePlan {
@@ -152,6 +158,8 @@ struct SolvePlan {
   int32_t n_heights;
   const int64_t *h_tgt_off;      // host [H+1]
   const int64_t *h_src_off;      // host [H+1] first source of each height
+  const int64_t *h_xtgt_end;     // host [H] end of the column targets (update-row targets follow)
+  const int64_t *h_xsrc_end;     // host [H] end of the column targets' sources
   const AsmTarget *tgt;          // device [n_tgt + 1] (sentinel)
   const int64_t *src;            // device U rows
   // one GEMM launch per height and direction: host descriptors, device tasks

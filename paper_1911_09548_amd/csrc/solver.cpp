@@ -126,15 +126,23 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
     if (S.parent[s] >= 0) kids[S.parent[s]].push_back(s);
     by_h[S.height[s]].push_back(s);
   }
-  // forward assembly targets
+  // forward assembly targets. Per height: first the rows of the supernodes'
+  // own columns that receive children's update rows (k_fwd_asm adds them
+  // into X), then every update row of those supernodes in row order (their
+  // children's contributions are summed by the GEMM epilogue that writes
+  // the row); uasm[s] = index of supernode s's first update-row target
   std::vector<AsmTarget> tgt;
   std::vector<int64_t> src;
+  std::vector<int64_t> uasm(ns, -1);
   D.h_tgt_off.assign(H + 1, 0);
+  D.h_xtgt_end.assign(H, 0);
   D.h_src_off.assign(H + 1, 0);
+  D.h_xsrc_end.assign(H, 0);
   std::vector<int32_t> pos(S.n, -1);
   for (int32_t hh = 0; hh < H; ++hh) {
     D.h_tgt_off[hh] = (int64_t)tgt.size();
     D.h_src_off[hh] = (int64_t)src.size();
+    std::vector<std::vector<std::vector<int64_t>>> per_s;
     for (int32_t s : by_h[hh]) {
       const int32_t c0 = S.col0[s], w = S.width(s), r = S.nrows(s), m = w + r;
       for (int32_t j = 0; j < w; ++j) pos[c0 + j] = j;
@@ -142,13 +150,21 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
       std::vector<std::vector<int64_t>> srcs(m);
       for (int32_t ch : kids[s])
         for (int32_t i = 0; i < S.nrows(ch); ++i) srcs[pos[S.rows[S.rptr[ch] + i]]].push_back(uoff[ch] + i);
-      for (int32_t t = 0; t < m; ++t) {
-        if (t < w && srcs[t].empty()) continue;
-        AsmTarget a;
-        a.dst = t < w ? (int64_t)(c0 + t) : -1 - (uoff[s] + (t - w));
-        a.src_begin = (int64_t)src.size();
-        tgt.push_back(a);
+      for (int32_t t = 0; t < w; ++t) {
+        if (srcs[t].empty()) continue;
+        tgt.push_back({(int64_t)(c0 + t), (int64_t)src.size()});
         src.insert(src.end(), srcs[t].begin(), srcs[t].end());
+      }
+      per_s.push_back(std::move(srcs));
+    }
+    D.h_xtgt_end[hh] = (int64_t)tgt.size();
+    D.h_xsrc_end[hh] = (int64_t)src.size();
+    for (size_t q = 0; q < by_h[hh].size(); ++q) {
+      const int32_t s = by_h[hh][q], w = S.width(s), r = S.nrows(s);
+      if (r > 0) uasm[s] = (int64_t)tgt.size();
+      for (int32_t t = w; t < w + r; ++t) {
+        tgt.push_back({-1 - (uoff[s] + (t - w)), (int64_t)src.size()});
+        src.insert(src.end(), per_s[q][t].begin(), per_s[q][t].end());
       }
     }
   }
@@ -217,6 +233,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.f.rptr = dev_upload(h, S.rptr);
   D.f.rows = dev_upload(h, S.rows);
   D.f.uoff = dev_upload(h, uoff);
+  D.f.uasm = dev_upload(h, uasm);
   D.plan.n_heights = H;
   D.plan.tile_rows = h->opt.gemm_rows;
   D.plan.splitk = h->opt.gemm_splitk;
@@ -225,8 +242,12 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.plan.splitk_bytes = 0;
   D.plan.h_tgt_off = D.h_tgt_off.data();
   D.plan.h_src_off = D.h_src_off.data();
+  D.plan.h_xtgt_end = D.h_xtgt_end.data();
+  D.plan.h_xsrc_end = D.h_xsrc_end.data();
   D.plan.tgt = dtg;
   D.plan.src = dsrc;
+  D.f.asm_tgt = dtg;
+  D.f.asm_src = dsrc;
   D.plan.fwd = D.fwd.data();
   D.plan.bwd = D.bwd.data();
 }

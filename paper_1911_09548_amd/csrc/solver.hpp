@@ -32,7 +32,7 @@ struct DevFactor {
   int64_t factor_bytes = 0;
   std::vector<int64_t> h_panel_off;  // panel offsets (host copy)
   // host-side plan storage (descriptors point into device arrays)
-  std::vector<int64_t> h_tgt_off, h_src_off;
+  std::vector<int64_t> h_tgt_off, h_src_off, h_xtgt_end, h_xsrc_end;
   std::vector<SolvePlan::Launch> fwd, bwd;
 };
 
