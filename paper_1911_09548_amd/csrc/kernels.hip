@@ -9,11 +9,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 
+#include "common.hpp"
 #include "factor.hpp"
 #include "kernels.hpp"
 
 namespace stmg {
+
+// A launch the library cannot make is an error, not a skipped step.
+[[noreturn]] static void fail_launch(const char *what) {
+  fprintf(stderr, "stmg: %s\n", what);
+  throw StmgError(STMG_EHIP, what);
+}
 
 namespace {
 
@@ -381,7 +389,7 @@ static void launch_residual_inner(const ResidualArgsT<R> &a, int nb, const ResSh
   RES_CASE(8, 2, true)
   RES_CASE(16, 2, true)
 #undef RES_CASE
-  fprintf(stderr, "stmg: unsupported residual shape W=%d q=%d\n", a.N * a.q, a.q);
+  fail_launch("residual: unsupported row shape");
 }
 
 // The tiled kernel applies to rows of whole segments with a nonzero x when
@@ -654,7 +662,7 @@ void launch_time_scan(int32_t n_v, int32_t N, int32_t q, R *g, hipStream_t s) {
   SCAN_CASE(8, 2, true)
   SCAN_CASE(16, 2, true)
 #undef SCAN_CASE
-  fprintf(stderr, "stmg: unsupported scan shape W=%d q=%d\n", W, q);
+  fail_launch("time scan: unsupported row shape");
 }
 
 // x[e][c] += y[head(e)][c] - y[tail(e)][c]  (G, boundary vertices dropped);
@@ -1278,16 +1286,17 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
                            Profiler *prof, void *ws, int64_t ws_bytes, int32_t nc, T *X, T *Z, T *U,
                            hipStream_t s) {
   if (L.n_tasks == 0) return;
-  int bn = nc > 32 ? 64 : (nc > 16 ? 32 : 16);
-  const int64_t ct64 = (nc + bn - 1) / bn;
-  bool bm32 = false;
-  if (bn >= 32) {
-    const double eff64 = (double)L.rows / (64.0 * L.n_tiles), eff32 = (double)L.rows / (32.0 * L.n_tiles32);
-    bm32 = (int64_t)L.n_tiles * ct64 < 1024 || eff32 > eff64 + 0.15;
-    if (policy == 64) bm32 = false;
-    if (policy == 32) bm32 = true;
-    if (bm32 && bn == 64 && policy == 0 && (int64_t)L.n_tiles32 * ct64 < 512) bn = 32;
+  // 32 x 32 tiles for every launch with more than 16 columns: on the 32^3
+  // workload they beat the 64-row and 64-column tiles at every tree height
+  // (occupancy 5 against 2 waves per SIMD, 4x the work items, less row
+  // padding); 64-row tiles only when forced (policy 64)
+  int bn = nc > 16 ? 32 : 16;
+  bool bm32 = bn == 32;
+  if (policy == 64) {
+    bm32 = false;
+    bn = nc > 32 ? 64 : bn;
   }
+  if (policy == 32 && bn >= 32) bm32 = true;
   const int ct = (nc + bn - 1) / bn;
   const SolveTask *tasks = bm32 ? L.tasks32 : L.tasks;
   const int64_t tiles = bm32 ? L.n_tiles32 : L.n_tiles;
@@ -1342,6 +1351,8 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   SN_CASE(32, 64)
   SN_CASE(32, 32)
 #undef SN_CASE
+  if (prof) prof->end(s, name, 0.0, 0.0);
+  fail_launch("supernode solve: no kernel for this tile shape");
 }
 
 template <typename T>
