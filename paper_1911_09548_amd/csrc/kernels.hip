@@ -1063,12 +1063,13 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t
   }
 }
 
-// Tiles: BM = 64 rows x BN columns of the output, K in chunks of KC = 16.
+// Tiles: BM rows x BN columns of the output, K in chunks of KC = 16.
 // LDS holds A as [row][k] and B as [col][k] with a row stride of KC + 1
-// doubles, which keeps the stores of both load orders and the MFMA operand
+// scalars, which keeps the stores of both load orders and the MFMA operand
 // reads free of bank conflicts. Complex products use three real MFMAs
-// (re = ArBr - AiBi, im = (Ar+Ai)(Br+Bi) - ArBr - AiBi). The next chunk is
-// fetched into registers while the current one is multiplied.
+// (re = ArBr - AiBi, im = (Ar+Ai)(Br+Bi) - ArBr - AiBi); LDS holds the real
+// and imaginary planes and the sums are formed in registers. The next chunk
+// is fetched into registers while the current one is multiplied.
 // DIR 0: forward (A = P). DIR 1: backward (A = P^T, read from P), DIR 2:
 // backward reading the stored transpose (same access pattern as forward).
 // With nsplit > 1 the K range is cut into nsplit segments of kseg and each
@@ -1081,14 +1082,15 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
   constexpr bool CPX = Scalar<T>::cpx;
   using R = typename Scalar<T>::R;
   using ACC = typename Scalar<T>::acc_t;
-  constexpr int NP = CPX ? 3 : 1;  // planes: re, im, re + im
+  constexpr int NP = CPX ? 3 : 1;  // products: re re, im im, (re + im)(re + im)
+  constexpr int NL = CPX ? 2 : 1;  // LDS planes: re, im (the sum plane is formed in registers)
   constexpr int KC = 16, LD = KC + 1;
   constexpr int WN = BN >= 32 ? 2 : 1, WM = 4 / WN;
   static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile shape");
   constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
   constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
-  __shared__ R As[NP][BM * LD];
-  __shared__ R Bs[NP][BN * LD];
+  __shared__ R As[NL][BM * LD];
+  __shared__ R Bs[NL][BN * LD];
   const int ct = blockIdx.x % ctiles, rs = blockIdx.x / ctiles;
   const int seg = rs % nsplit, rowtile = rs / nsplit;
   const int ti = find_task(tasks, n_tasks, rowtile);
@@ -1146,10 +1148,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       const int e = threadIdx.x + q * BLOCK;
       const int i = DIR != 1 ? e % BM : e / KC, k = DIR != 1 ? e / BM : e % KC;
       As[0][i * LD + k] = ra[q][0];
-      if constexpr (CPX) {
-        As[1][i * LD + k] = ra[q][1];
-        As[2][i * LD + k] = ra[q][0] + ra[q][1];
-      }
+      if constexpr (CPX) As[1][i * LD + k] = ra[q][1];
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
@@ -1157,10 +1156,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       const int j = e % BN, k = e / BN;
       if (k < KC) {
         Bs[0][j * LD + k] = rb[q][0];
-        if constexpr (CPX) {
-          Bs[1][j * LD + k] = rb[q][1];
-          Bs[2][j * LD + k] = rb[q][0] + rb[q][1];
-        }
+        if constexpr (CPX) Bs[1][j * LD + k] = rb[q][1];
       }
     }
   };
@@ -1181,19 +1177,25 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + lane / 16;
+      R av[NL][MI], bv[NL][NI];
 #pragma unroll
-      for (int pl = 0; pl < NP; ++pl) {
-        R av[MI], bv[NI];
+      for (int pl = 0; pl < NL; ++pl) {
 #pragma unroll
-        for (int a = 0; a < MI; ++a) av[a] = As[pl][(wr + a * 16 + (lane & 15)) * LD + kr];
+        for (int a = 0; a < MI; ++a) av[pl][a] = As[pl][(wr + a * 16 + (lane & 15)) * LD + kr];
 #pragma unroll
-        for (int b = 0; b < NI; ++b) bv[b] = Bs[pl][(wc + b * 16 + (lane & 15)) * LD + kr];
-#pragma unroll
-        for (int a = 0; a < MI; ++a)
-#pragma unroll
-          for (int b = 0; b < NI; ++b)
-            acc[pl][a][b] = mfma_op(av[a], bv[b], acc[pl][a][b]);
+        for (int b = 0; b < NI; ++b) bv[pl][b] = Bs[pl][(wc + b * 16 + (lane & 15)) * LD + kr];
       }
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+        for (int a = 0; a < MI; ++a) {
+          const R x = pl < 2 ? av[pl < NL ? pl : 0][a] : av[0][a] + av[NL - 1][a];
+#pragma unroll
+          for (int b = 0; b < NI; ++b) {
+            const R y = pl < 2 ? bv[pl < NL ? pl : 0][b] : bv[0][b] + bv[NL - 1][b];
+            acc[pl][a][b] = mfma_op(x, y, acc[pl][a][b]);
+          }
+        }
     }
     __syncthreads();
   }
