@@ -1327,12 +1327,18 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   // (8 flops complex, 2 real); traffic: the factor panels once, the
   // right-hand-side rows in and out once
   const double scal = (double)sizeof(T);
-  char name[96];
+  // the GEMM launch and the split-K reduce are timed separately; the GEMM
+  // carries the launch's algorithmic work (the whole K range), the reduce
+  // the partial tiles it reads and the rows it writes
+  char name[96], rname[64];
   if (prof) {
-    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>%s", Scalar<T>::name, bmv, bn,
-             DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd"), nsplit > 1 ? "+splitk" : "");
+    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>", Scalar<T>::name, bmv, bn,
+             DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd"));
+    snprintf(rname, sizeof rname, "k_sn_reduce<%s,%d,%s>", Scalar<T>::name, bmv, DIR == 0 ? "fwd" : "bwd");
     prof->begin(s);
   }
+  const double flops = (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz * nc, bytes = scal * (L.nnz + 2.0 * L.rows * nc);
+  const double rbytes = scal * ((double)nsplit + 1.0) * (double)L.rows * nc;
 #define SN_CASE(BMV, BNV)                                                                                  \
   if (bmv == BMV && bn == BNV) {                                                                           \
     if (dir_k == 2)                                                                                        \
@@ -1341,10 +1347,13 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
     else                                                                                                   \
       hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
                          nc, ct, X, Z, U, nsplit, kseg, (T *)ws);                                          \
-    if (nsplit > 1)                                                                                        \
+    if (prof) prof->end(s, name, flops, bytes);                                                            \
+    if (nsplit > 1) {                                                                                      \
+      if (prof) prof->begin(s);                                                                            \
       hipLaunchKernelGGL((k_sn_reduce<T, BMV, DIR>), dim3((unsigned)(tiles * ((nc + 63) / 64))), dim3(BLOCK), \
                          0, s, f, tasks, L.n_tasks, nc, nsplit, (const T *)ws, X, Z, U);                   \
-    if (prof) prof->end(s, name, (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz * nc, scal * (L.nnz + 2.0 * L.rows * nc)); \
+      if (prof) prof->end(s, rname, 0.0, rbytes);                                                          \
+    }                                                                                                      \
     return;                                                                                                \
   }
   SN_CASE(64, 64)
