@@ -211,6 +211,152 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a, int seg,
   }
 }
 
+// Grouped residual for wide rows: one wave per group of RES_GROUP rows of
+// the visiting order. The wave walks the sorted union of the group's
+// neighbour rows and gathers each neighbour's x segment once for every row of
+// the group coupled to it (whose mask bit is set; the test is wave-uniform),
+// instead of once per nonzero: neighbouring rows of the Morton order share
+// most of their neighbours, so a group of 4 gathers about 40% fewer x
+// segments than 4 single rows. Each row sums its nonzeros in ascending
+// neighbour order, as the per-row kernel does. Lane mapping, segments, the
+// hand-over of end values and the outputs are those of the per-row kernel.
+template <typename R, int C, int Q>
+__global__ __launch_bounds__(BLOCK) void k_residual_grp(ResidualArgsT<R> a, int seg, int nseg) {
+  constexpr int G = RES_GROUP;
+  constexpr int P = (C % 2 == 0) ? 2 : 1;
+  constexpr int NP = C / P;
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
+  const int W = a.N * Q;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int grp = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + wave);
+  const int ngrp = (a.n_rows + G - 1) / G;
+  const bool active = grp < ngrp;
+  int row[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int k = grp * G + g;
+    row[g] = active && k < a.n_rows ? __builtin_amdgcn_readfirstlane(a.sched[k]) : -1;
+  }
+  const int64_t c0 = (int64_t)seg * 64 * C;  // first value of the segment
+  R *halo = static_cast<R *>(a.halo);
+  const R *hin = seg > 0 ? halo + (int64_t)((seg - 1) & 1) * a.n_rows : nullptr;
+  R *hout = seg + 1 < nseg ? halo + (int64_t)(seg & 1) * a.n_rows : nullptr;
+  R am[G][C], ak[G][C];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int j = 0; j < C; ++j) am[g][j] = ak[g][j] = 0;
+  if (active && a.x) {
+    // The union entries are read 64 at a time into one register per lane
+    // (neighbour row, mask), so the x gathers of a step wait for no other
+    // load. U entries per step with all their loads issued before the first
+    // FMA; the last step repeats the batch's last entry with an empty mask.
+    constexpr int U = NP >= 4 ? 2 : 4;
+    const int e0 = a.gptr[grp], e1 = a.gptr[grp + 1];
+    for (int eb = e0; eb < e1; eb += 64) {
+      const int nbat = min(64, e1 - eb);
+      const int my_col = lane < nbat ? a.gent[2 * (eb + lane)] : 0;
+      const int my_msk = lane < nbat ? a.gent[2 * (eb + lane) + 1] : 0;
+      for (int e = 0; e < nbat; e += U) {
+        int msk[U];
+        R mv[U][G], kv[U][G];
+        V v[U][NP];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool in = e + u < nbat;
+          const int j = in ? e + u : nbat - 1;
+          const int ee = eb + j;
+          const int c = __builtin_amdgcn_readlane(my_col, j);
+          msk[u] = in ? __builtin_amdgcn_readlane(my_msk, j) : 0;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            mv[u][g] = a.gval[((int64_t)ee * G + g) * 2];
+            kv[u][g] = a.gval[((int64_t)ee * G + g) * 2 + 1];
+          }
+          const R *xr = a.x + (int64_t)c * W + c0;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) v[u][p] = *reinterpret_cast<const V *>(xr + (int64_t)(p * 64 + lane) * P);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            if (!((msk[u] >> g) & 1)) continue;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+              for (int t = 0; t < P; ++t) {
+                am[g][p * P + t] += mv[u][g] * PK::get(v[u][p], t);
+                ak[g][p * P + t] += kv[u][g] * PK::get(v[u][p], t);
+              }
+          }
+      }
+    }
+  }
+  double ss = 0.0;
+  const R tau = (R)a.tau;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (row[g] < 0) continue;
+    // end value of the slab before each packet
+    const R e_in = hin ? hin[row[g]] : (R)0;
+    R prev[NP];
+    R e_last = 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      R e = am[g][p * P + P - 1];
+      if constexpr (Q == 2) e += am[g][p * P];
+      const R up = __shfl_up(e, 1, 64);
+      R wrap = e_in;
+      if (p > 0) {
+        R e1 = am[g][(p - 1) * P + P - 1];
+        if constexpr (Q == 2) e1 += am[g][(p - 1) * P];
+        wrap = __shfl(e1, 63, 64);
+      }
+      prev[p] = lane == 0 ? wrap : up;
+      e_last = e;
+    }
+    if (hout && lane == 63) hout[row[g]] = e_last;
+    const int64_t base = (int64_t)row[g] * W + c0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int64_t off = base + (int64_t)(p * 64 + lane) * P;
+      const V bv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.b + off));
+      V ov;
+      if constexpr (Q == 1) {
+        R eprev = prev[p];
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          const R r = PK::get(bv, t) - am[g][p * P + t] + eprev - tau * ak[g][p * P + t];
+          eprev = am[g][p * P + t];
+          PK::set(ov, t, r);
+          ss += (double)r * r;
+        }
+      } else {
+        const R m0 = am[g][2 * p], m1 = am[g][2 * p + 1];
+        const R r0 = PK::get(bv, 0) - (m0 + m1) + prev[p] - tau * ak[g][2 * p];
+        const R r1 = PK::get(bv, 1) + m0 - m1 - prev[p] - (tau / (R)3) * ak[g][2 * p + 1];
+        ss += (double)r0 * r0 + (double)r1 * r1;
+        if (a.mode == RES_OUT_SLABRHS) {
+          const R s2 = (R)1.4142135623730951;
+          PK::set(ov, 0, (R)0.5 * r0);
+          PK::set(ov, 1, (R)0.25 * s2 * r0 - (R)0.75 * s2 * r1);
+        } else {
+          PK::set(ov, 0, r0);
+          PK::set(ov, 1, r1);
+        }
+      }
+      __builtin_nontemporal_store(ov, reinterpret_cast<V *>(a.out + off));
+    }
+  }
+  if (a.partial) {
+    const double t = block_sum(ss);
+    if (threadIdx.x == 0) a.partial[(int64_t)seg * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // LDS-tiled residual: one block per tile of RES_TILE rows of the visiting
 // order. The tile's matrix entries (neighbour position in the tile's union,
 // M and K values) are staged in LDS once; then, segment by segment of
@@ -413,9 +559,53 @@ static void launch_residual_tiles(const ResidualArgsT<R> &a, hipStream_t s) {
     hipLaunchKernelGGL((k_residual_tile<R, 1>), dim3(nt), dim3(BLOCK), lds, s, a);
 }
 
+// Grouped kernel: wide rows with a nonzero x, when the handle provides row
+// groups; at most 8 values per lane (the group's accumulators stay in
+// registers), longer rows take more segments.
+template <typename R>
+static bool use_groups(const ResidualArgsT<R> &a) {
+  return a.gptr && a.gval && a.x && a.sched && a.chunk != RES_CHUNK_TILES && a.N * a.q >= 64 * a.q;
+}
+
+template <typename R>
+static void launch_residual_groups(const ResidualArgsT<R> &a, int nb, const ResShape &sh, hipStream_t s) {
+#define RESG_CASE(CC, QQ)                                                                       \
+  if (sh.C == CC && a.q == QQ) {                                                                \
+    for (int seg = 0; seg < sh.nseg; ++seg)                                                     \
+      hipLaunchKernelGGL((k_residual_grp<R, CC, QQ>), dim3(nb), dim3(BLOCK), 0, s, a, seg, sh.nseg); \
+    return;                                                                                     \
+  }
+  RESG_CASE(1, 1)
+  RESG_CASE(2, 1)
+  RESG_CASE(4, 1)
+  RESG_CASE(8, 1)
+  RESG_CASE(2, 2)
+  RESG_CASE(4, 2)
+  RESG_CASE(8, 2)
+#undef RESG_CASE
+  fail_launch("grouped residual: unsupported row shape");
+}
+
 template <typename R>
 int launch_residual(const ResidualArgsT<R> &a, hipStream_t s) {
   const int W = a.N * a.q;
+  if (use_groups(a)) {
+    const ResShape sh = residual_shape(W, a.q, a.chunk > 0 && a.chunk < 8 ? a.chunk : 8);
+    const int ngrp = (a.n_rows + RES_GROUP - 1) / RES_GROUP;
+    const int nb = (ngrp + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0) return 0;
+    if (a.prof) {
+      char name[64];
+      snprintf(name, sizeof name, "k_residual_grp<%s,%d,%d>", sizeof(R) == 8 ? "double" : "float", sh.C, a.q);
+      a.prof->begin(s);
+      launch_residual_groups(a, nb, sh, s);
+      const double rows = a.n_rows, cols = W, nnz = (double)a.nnz, sz = sizeof(R);
+      a.prof->end(s, name, 4.0 * nnz * cols, sz * rows * cols * 3.0 + (4.0 + 2.0 * sz) * nnz + 8.0 * (rows + 1));
+    } else {
+      launch_residual_groups(a, nb, sh, s);
+    }
+    return nb * sh.nseg;
+  }
   if (use_tiles(a)) {
     const int nt = (a.n_rows + RES_TILE - 1) / RES_TILE;
     if (nt == 0) return 0;
@@ -1002,18 +1192,6 @@ __device__ inline void make(R re, R, R &out) {
 __device__ inline void make(double re, double im, cd &out) { out = {re, im}; }
 __device__ inline void make(float re, float im, cf &out) { out = {re, im}; }
 
-__device__ inline int find_task(const SolveTask *tasks, int n, int tile) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tasks[mid].tile_begin <= tile)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 }  // namespace
 
 // Children's contributions to update row i of supernode s, column col, summed
@@ -1076,9 +1254,9 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t
 // work item writes its partial tile to ws; k_sn_reduce adds them in order
 // and applies the epilogue.
 template <typename T, int BM, int BN, int DIR>
-__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks,
                                                    int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
-                                                   int32_t nsplit, int32_t kseg, T *ws) {
+                                                   int32_t nsplit, int32_t kseg, T *ws, int32_t n_rs) {
   constexpr bool CPX = Scalar<T>::cpx;
   using R = typename Scalar<T>::R;
   using ACC = typename Scalar<T>::acc_t;
@@ -1091,10 +1269,17 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
   constexpr int AE = BM * KC / BLOCK, BE = (BN * KC + BLOCK - 1) / BLOCK;  // elements per thread
   __shared__ R As[NL][BM * LD];
   __shared__ R Bs[NL][BN * LD];
-  const int ct = blockIdx.x % ctiles, rs = blockIdx.x / ctiles;
+  // Blocks go round-robin to the 8 XCDs (XCD = blockIdx % 8). Row tiles are
+  // dealt over the XCDs in turn while all column tiles of one row tile stay
+  // on one XCD, consecutive in its dispatch order, so they read the row
+  // tile's block of P through one L2. The grid is padded to whole groups of
+  // 8 row tiles; blocks past the last row tile exit.
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int ct = idx % ctiles, rs = (idx / ctiles) * 8 + xcd;
+  if (rs >= n_rs) return;
   const int seg = rs % nsplit, rowtile = rs / nsplit;
-  const int ti = find_task(tasks, n_tasks, rowtile);
-  const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
+  const SolveTask task = tasks[rowtile];
+  const int s = task.s, rt = task.rt;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0, m = f.m[s];
   const T *P = reinterpret_cast<const T *>(DIR == 2 ? f.panel_t : f.panel) + f.panel_off[s];
   const int32_t *Rrows = f.rows + f.rptr[s];
@@ -1248,14 +1433,14 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
 // as the unsplit kernel (forward: Z rows and U update rows; backward: X[C_s]
 // rows). One block per (row tile, chunk of RC columns).
 template <typename T, int BM, int DIR>
-__global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks, int32_t n_tasks,
+__global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks,
                                                      int32_t nc, int32_t nsplit, const T *ws, T *X, T *Z, T *U) {
   using R = typename Scalar<T>::R;
   const int RC = nc < 64 ? nc : 64;  // columns per block
   const int cchunks = (nc + RC - 1) / RC;
   const int rowtile = blockIdx.x / cchunks, cc = blockIdx.x % cchunks;
-  const int ti = find_task(tasks, n_tasks, rowtile);
-  const int s = tasks[ti].s, rt = rowtile - tasks[ti].tile_begin;
+  const SolveTask task = tasks[rowtile];
+  const int s = task.s, rt = task.rt;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0;
   const int rows = DIR == 0 ? f.m[s] : w;
   for (int e = threadIdx.x; e < BM * RC; e += BLOCK) {
@@ -1321,7 +1506,8 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
       if (nsplit < 2 || (int64_t)tiles * nsplit * bmv * nc * (int64_t)sizeof(T) > ws_bytes) nsplit = 1;
     }
   }
-  const unsigned grid = (unsigned)(tiles * nsplit * ct);
+  const int32_t n_rs = (int32_t)(tiles * nsplit);  // row tiles x K segments
+  const unsigned grid = (unsigned)(((n_rs + 7) / 8) * 8 * (int64_t)ct);
   const int dir_k = (DIR == 1 && f.panel_t) ? 2 : DIR;
   // algorithmic work: one multiply-add per factor entry and right-hand side
   // (8 flops complex, 2 real); traffic: the factor panels once, the
@@ -1342,16 +1528,16 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
 #define SN_CASE(BMV, BNV)                                                                                  \
   if (bmv == BMV && bn == BNV) {                                                                           \
     if (dir_k == 2)                                                                                        \
-      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, 2>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, nc, \
-                         ct, X, Z, U, nsplit, kseg, (T *)ws);                                              \
+      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, 2>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, nc,         \
+                         ct, X, Z, U, nsplit, kseg, (T *)ws, n_rs);                                        \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks, L.n_tasks, \
-                         nc, ct, X, Z, U, nsplit, kseg, (T *)ws);                                          \
+      hipLaunchKernelGGL((k_sn_gemm<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, f, tasks,             \
+                         nc, ct, X, Z, U, nsplit, kseg, (T *)ws, n_rs);                                    \
     if (prof) prof->end(s, name, flops, bytes);                                                            \
     if (nsplit > 1) {                                                                                      \
       if (prof) prof->begin(s);                                                                            \
       hipLaunchKernelGGL((k_sn_reduce<T, BMV, DIR>), dim3((unsigned)(tiles * ((nc + 63) / 64))), dim3(BLOCK), \
-                         0, s, f, tasks, L.n_tasks, nc, nsplit, (const T *)ws, X, Z, U);                   \
+                         0, s, f, tasks, nc, nsplit, (const T *)ws, X, Z, U);                               \
       if (prof) prof->end(s, rname, 0.0, rbytes);                                                          \
     }                                                                                                      \
     return;                                                                                                \

@@ -55,8 +55,17 @@ struct ResidualArgsT {
   const int32_t *tile_ptr = nullptr, *tile_cols = nullptr;
   const uint16_t *lcol = nullptr;
   int32_t tile_union_max = 0, tile_nnz_max = 0;
+  // Row groups (used for wide rows when gptr is set): group g holds the rows
+  // sched[g*RES_GROUP .. +RES_GROUP) and the sorted union of their neighbour
+  // rows, entries e in [gptr[g], gptr[g+1]): gent[2e] = neighbour row,
+  // gent[2e+1] = bit mask of the group's rows coupled to it, and
+  // gval[(e*RES_GROUP + j)*2 + {0, 1}] = the M and K entries of the group's
+  // row j (0 where the mask bit is clear)
+  const int32_t *gptr = nullptr, *gent = nullptr;
+  const R *gval = nullptr;
 };
 using ResidualArgs = ResidualArgsT<double>;
+constexpr int RES_GROUP = 4;      // rows per wave of the grouped residual
 constexpr int RES_CHUNK_DEFAULT = 16;
 constexpr int RES_CHUNK_TILES = 32;  // stream_chunk value selecting the LDS-tiled residual
 constexpr int RES_TILE = 64;      // rows per LDS tile of the residual
@@ -147,9 +156,9 @@ struct FactorDev {
   const AsmTarget *asm_tgt;
   const int64_t *asm_src;
 };
-struct SolveTask {
-  int32_t s;
-  int32_t tile_begin;      // prefix of row tiles
+struct SolveTask {          // one row tile of a GEMM launch
+  int32_t s;               // supernode
+  int32_t rt;              // row tile within the supernode
 };
 // Kernel launch plan of one factor (all arrays on device, built on the host).
 struct SolvePlan {
@@ -169,8 +178,8 @@ struct SolvePlan {
     int32_t n_tiles, n_tiles32;  // 64-row and 32-row tiles
     int64_t rows;                // output rows over all supernodes
     int32_t kmax;                // longest K range (backward: max m)
-    const SolveTask *tasks;      // device, prefix over 64-row tiles
-    const SolveTask *tasks32;    // device, prefix over 32-row tiles
+    const SolveTask *tasks;      // device, one per 64-row tile
+    const SolveTask *tasks32;    // device, one per 32-row tile
   };
   int32_t tile_rows;             // 0: choose per launch; 64 or 32: forced
   int32_t splitk;                // 0 auto, -1 never, >= 2 forced

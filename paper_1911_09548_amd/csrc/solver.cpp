@@ -171,8 +171,8 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   D.h_tgt_off[H] = (int64_t)tgt.size();
   D.h_src_off[H] = (int64_t)src.size();
   tgt.push_back({0, (int64_t)src.size()});  // sentinel
-  // one forward and one backward GEMM launch per height; task prefixes for
-  // 64-row and 32-row tiles
+  // one forward and one backward GEMM launch per height; one task (supernode,
+  // row tile) per 64-row and per 32-row tile
   std::vector<SolveTask> tasks;
   struct Pending {
     size_t off64, off32, n;
@@ -185,18 +185,18 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
     Pending p{tasks.size(), 0, 0, 0, 0, 0, 0.0, 0};
     for (int32_t s : by_h[hh]) {
       const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
-      tasks.push_back({s, p.tiles64});
+      for (int32_t t = 0; t < (rows + 63) / 64; ++t) tasks.push_back({s, t});
       p.tiles64 += (rows + 63) / 64;
       p.rows += rows;
       const double w = S.width(s), r = S.nrows(s);
       p.nnz += w * (w + 1) / 2 + r * w;
       p.kmax = std::max(p.kmax, fwd ? S.width(s) : S.width(s) + S.nrows(s));
     }
-    p.n = tasks.size() - p.off64;
+    p.n = by_h[hh].size();
     p.off32 = tasks.size();
     for (int32_t s : by_h[hh]) {
       const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
-      tasks.push_back({s, p.tiles32});
+      for (int32_t t = 0; t < (rows + 31) / 32; ++t) tasks.push_back({s, t});
       p.tiles32 += (rows + 31) / 32;
     }
     return p;
@@ -430,6 +430,46 @@ void residual_tiles(MeshData &md) {
   if (residual_tile_lds(md.tile_union_max, md.tile_nnz_max, sizeof(double)) > 65536) md.tile_ptr.clear();
 }
 
+// Row groups of the grouped residual: RES_GROUP consecutive rows of the
+// visiting order, the sorted union of their neighbour rows and, per union
+// entry, the mask of the group's rows coupled to it with their M and K
+// entries (M and K share one pattern).
+void residual_groups(MeshData &md) {
+  const Csr &M = md.Mp, &K = md.Kp;
+  const int32_t n = M.n_rows, ng = (n + RES_GROUP - 1) / RES_GROUP;
+  md.gptr.assign(ng + 1, 0);
+  md.gent.clear();
+  md.gval.clear();
+  std::vector<int32_t> cols;
+  for (int32_t g = 0; g < ng; ++g) {
+    const int32_t k0 = g * RES_GROUP, k1 = std::min(n, k0 + RES_GROUP);
+    cols.clear();
+    for (int32_t k = k0; k < k1; ++k) {
+      const int32_t r = md.sched[k];
+      for (int64_t j = M.ptr[r]; j < M.ptr[r + 1]; ++j) cols.push_back(M.col[j]);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    const size_t base = md.gent.size() / 2;
+    for (int32_t c : cols) {
+      md.gent.push_back(c);
+      md.gent.push_back(0);
+    }
+    md.gval.resize((base + cols.size()) * RES_GROUP * 2, 0.0);
+    for (int32_t k = k0; k < k1; ++k) {
+      const int32_t i = k - k0, r = md.sched[k];
+      for (int64_t j = M.ptr[r]; j < M.ptr[r + 1]; ++j) {
+        const size_t e = base + (size_t)(std::lower_bound(cols.begin(), cols.end(), M.col[j]) - cols.begin());
+        md.gent[2 * e + 1] |= 1 << i;
+        md.gval[(e * RES_GROUP + i) * 2] += M.val[j];
+        md.gval[(e * RES_GROUP + i) * 2 + 1] += K.val[j];
+      }
+    }
+    STMG_REQUIRE(base + cols.size() < (size_t)INT32_MAX, STMG_ENOMEM, "residual row groups exceed 2^31 entries");
+    md.gptr[g + 1] = (int32_t)(base + cols.size());
+  }
+}
+
 void setup_mesh_host(stmg_handle *h, MeshData &md) {
   SpaceLevel &S = *md.S;
   const Topo &T = S.topo;
@@ -452,6 +492,7 @@ void setup_mesh_host(stmg_handle *h, MeshData &md) {
   md.Kp = csr_permute_sym(S.K, md.sym_e.perm);
   md.sched = morton_schedule(T, md.sym_e.perm);
   residual_tiles(md);
+  residual_groups(md);
   if (dev_factor(h)) build_front_plan(md.sym_e, S.M, md.fp_e);
 }
 
@@ -469,10 +510,15 @@ void setup_mesh_device(stmg_handle *h, MeshData &md) {
   md.d_col = dev_upload(h, md.Mp.col);
   md.d_mval = dev_upload(h, md.Mp.val);
   md.d_kval = dev_upload(h, md.Kp.val);
+  md.d_gptr = dev_upload(h, md.gptr);
+  md.d_gent = dev_upload(h, md.gent);
+  md.d_gval = dev_upload(h, md.gval);
   if (h->opt.precision == STMG_FP32_REFINED) {
     std::vector<float> mv(md.Mp.val.begin(), md.Mp.val.end()), kv(md.Kp.val.begin(), md.Kp.val.end());
     md.d_mval32 = dev_upload(h, mv);
     md.d_kval32 = dev_upload(h, kv);
+    std::vector<float> gv(md.gval.begin(), md.gval.end());
+    md.d_gval32 = dev_upload(h, gv);
   }
   const int32_t ne = T.n_int_edges(), nv = T.n_int_verts();
   // G in internal numberings
@@ -692,6 +738,7 @@ struct Bufs<double> {
   static double *un(LevelData &L) { return L.un; }
   static const double *mval(MeshData &m) { return m.d_mval; }
   static const double *kval(MeshData &m) { return m.d_kval; }
+  static const double *gval(MeshData &m) { return m.d_gval; }
   static const FactorDev &fac(DevFactor &d) { return d.f; }
   using C = cd;
 };
@@ -707,6 +754,7 @@ struct Bufs<float> {
   static float *un(LevelData &L) { return L.un32; }
   static const float *mval(MeshData &m) { return m.d_mval32; }
   static const float *kval(MeshData &m) { return m.d_kval32; }
+  static const float *gval(MeshData &m) { return m.d_gval32; }
   static const FactorDev &fac(DevFactor &d) { return d.f32; }
   using C = cf;
 };
@@ -745,7 +793,12 @@ struct OpsT {
     a.prof = h->prof_state.on ? &h->prof : nullptr;
     a.chunk = h->opt.stream_chunk;
     a.halo = h->d_halo;
-    a.sched = h->opt.row_schedule == 0 ? md.d_sched : nullptr;
+    a.sched = h->opt.row_schedule != 1 ? md.d_sched : nullptr;
+    if (h->opt.row_schedule == 0) {
+      a.gptr = md.d_gptr;
+      a.gent = md.d_gent;
+      a.gval = B::gval(md);
+    }
     if (a.sched && md.d_tile_ptr) {
       a.tile_ptr = md.d_tile_ptr;
       a.tile_cols = md.d_tile_cols;
@@ -1092,8 +1145,8 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
     const int c = h->opt.stream_chunk;
     STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16 || c == RES_CHUNK_TILES, STMG_EINVAL,
                  "stream_chunk must be 0, 1, 2, 4, 8, 16 or 32");
-    STMG_REQUIRE(h->opt.row_schedule == 0 || h->opt.row_schedule == 1, STMG_EINVAL,
-                 "row_schedule must be 0 or 1");
+    STMG_REQUIRE(h->opt.row_schedule >= 0 && h->opt.row_schedule <= 2, STMG_EINVAL,
+                 "row_schedule must be 0, 1 or 2");
   }
   if (h->opt.max_cycles <= 0) h->opt.max_cycles = 100;
   h->pt = prob->pt;
@@ -1153,6 +1206,10 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
   for (const auto &md : h->meshes) {
     const int64_t nnz = md.Mp.nnz(), ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
     bytes += nnz * (4 + 8 + 8 + (prec ? 8 : 0)) + 8 * (ne + 1) + 24 * ne + 40 * nv;
+    // residual row groups and LDS tiles
+    const int64_t nent = (int64_t)md.gent.size() / 2;
+    bytes += nent * (8 + RES_GROUP * 2 * (8 + (prec ? 4 : 0))) + 4 * (int64_t)md.gptr.size();
+    bytes += 4 * (int64_t)(md.tile_ptr.size() + md.tile_cols.size()) + 2 * (int64_t)md.lcol.size();
     const int64_t pn = md.sym_v.panel_entries;
     bytes += pn * 8 * 2 + (prec ? pn * 4 * 2 : 0);
   }
@@ -1576,7 +1633,7 @@ int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_sch
     const int c = stream_chunk;
     STMG_REQUIRE(c == 0 || c == 1 || c == 2 || c == 4 || c == 8 || c == 16 || c == RES_CHUNK_TILES, STMG_EINVAL,
                  "stream_chunk must be 0, 1, 2, 4, 8, 16 or 32");
-    STMG_REQUIRE(row_schedule == 0 || row_schedule == 1, STMG_EINVAL, "row_schedule must be 0 or 1");
+    STMG_REQUIRE(row_schedule >= 0 && row_schedule <= 2, STMG_EINVAL, "row_schedule must be 0, 1 or 2");
     h->opt.stream_chunk = stream_chunk;
     h->opt.row_schedule = row_schedule;
   });

@@ -47,11 +47,16 @@ struct MeshData {
   std::vector<int32_t> tile_ptr, tile_cols;  // residual LDS tiles (see ResidualArgsT)
   std::vector<uint16_t> lcol;
   int32_t tile_union_max = 0, tile_nnz_max = 0;
+  std::vector<int32_t> gptr, gent;  // residual row groups (see ResidualArgsT)
+  std::vector<double> gval;
   // device
   int64_t *d_ptr = nullptr;
   int32_t *d_sched = nullptr;
   int32_t *d_tile_ptr = nullptr, *d_tile_cols = nullptr;
   uint16_t *d_lcol = nullptr;
+  int32_t *d_gptr = nullptr, *d_gent = nullptr;
+  double *d_gval = nullptr;
+  float *d_gval32 = nullptr;
   int32_t *d_col = nullptr;
   double *d_mval = nullptr, *d_kval = nullptr;
   float *d_mval32 = nullptr, *d_kval32 = nullptr;

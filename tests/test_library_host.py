@@ -175,7 +175,8 @@ def test_invalid_inputs_are_rejected(stmg):
     assert _setup_rc(stmg, bad_parent) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, omega=0.0) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, stream_chunk=3) == stmg.STMG_EINVAL
-    assert _setup_rc(stmg, good, row_schedule=2) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, row_schedule=3) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, row_schedule=-1) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, stream_chunk=4, row_schedule=1) == stmg.STMG_OK
 
 
@@ -185,7 +186,9 @@ def test_stream_tuning_values(stmg):
     assert L.stmg_set_stream_tuning(h._h, 8, 1) == stmg.STMG_OK
     assert L.stmg_set_stream_tuning(h._h, 32, 0) == stmg.STMG_OK
     assert L.stmg_set_stream_tuning(h._h, 5, 0) == stmg.STMG_EINVAL
+    assert L.stmg_set_stream_tuning(h._h, 16, 2) == stmg.STMG_OK
     assert L.stmg_set_stream_tuning(h._h, 0, -1) == stmg.STMG_EINVAL
+    assert L.stmg_set_stream_tuning(h._h, 0, 3) == stmg.STMG_EINVAL
     h.close()
 
 
