@@ -1495,13 +1495,17 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
     int want = 1;
     // forward partial tiles cover all m rows of a front (the update rows
     // too), so the forward splits only launches that leave most of the GPU idle
-    const int64_t fill = DIR == 0 ? 512 : 2048;
+    // the narrow 64 x 16 tiles (few work items per height) split down to
+    // 128-long K ranges until the launch has 4096 work items
+    const bool narrow = bn == 16;
+    const int64_t fill = narrow ? 4096 : (DIR == 0 ? 512 : 2048);
     if (splitk >= 2)
       want = splitk;
-    else if (tiles * ct < fill && L.kmax >= 512)
-      want = (int)std::min<int64_t>(8, (fill + tiles * ct - 1) / (tiles * ct));
+    else if (tiles * ct < fill && L.kmax >= (narrow ? 256 : 512))
+      want = (int)std::min<int64_t>(narrow ? 16 : 8, (fill + tiles * ct - 1) / (tiles * ct));
     if (want > 1 && L.kmax > 16) {
       kseg = ((L.kmax + want - 1) / want + 15) / 16 * 16;
+      if (narrow && splitk < 2) kseg = std::max(kseg, 128);
       nsplit = (L.kmax + kseg - 1) / kseg;
       if (nsplit < 2 || (int64_t)tiles * nsplit * bmv * nc * (int64_t)sizeof(T) > ws_bytes) nsplit = 1;
     }
