@@ -228,6 +228,45 @@ def recorded_traffic(kernel):
     return None
 
 
+def rate_sweep(args):
+    """Convergence rates against the anisotropy (section 5.1): the power
+    iteration of the SAS V-cycle on a two-mesh Kuhn hierarchy with sigma =
+    nu = 1, coarsened in space on its top level ("Full": lambda_crit = 0)
+    or in time only ("Semi-time"), for tau / h^2 from 2^-7 to 2^5 and both
+    DG degrees. lambda is the library's eq. (3) value of the top level.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1911_09548_amd import inputs, stmg
+
+    n, Nt, cycles = args.sweep_n, args.sweep_Nt, args.sweep_cycles
+    meshes = inputs.kuhn_hierarchy(n)[:2]
+    nt = meshes[0].tets.shape[0]
+    rows = []
+    for pt in (0, 1):
+        for e in range(-7, 6):
+            T = 2.0 ** e * Nt / n ** 2  # tau n^2 = 2^e
+            prob = inputs.Problem(meshes, np.ones(nt), np.ones(nt), T, Nt, pt,
+                                  meta={"name": f"rate sweep n={n} Nt={Nt} pt={pt} T={T}"})
+            row = {"pt": pt, "T": T}
+            for name, opts in (("full", dict(lambda_crit=0.0)), ("semi_time", dict(allow_space_coarsening=0))):
+                s = stmg.Solver(prob, **opts)
+                row["lambda"] = s.level_info(0).lambda_
+                x0 = torch.from_numpy(np.random.default_rng(7).uniform(0.0, 1.0, (Nt, pt + 1, s.n_edges))).cuda()
+                t0 = time.perf_counter()
+                rate, rates = s.power_rate(x0, max_cycles=cycles)
+                dt = time.perf_counter() - t0
+                row[name] = rate
+                row[name + "_ms_per_cycle"] = 1e3 * dt / max(1, len(rates))
+                s.close()
+            rows.append(row)
+            log(f"[sweep] pt={pt} lambda={row['lambda']:.4g}: full {row['full']:.4f}, "
+                f"semi-time {row['semi_time']:.4f}")
+    print(json.dumps({"rate_sweep": {"mesh": f"{n}^3 x 6 Kuhn tets, two meshes, sigma = nu = 1",
+                                     "Nt": Nt, "cycles": cycles, "start": "uniform [0, 1], seed 7",
+                                     "rows": rows}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +294,11 @@ def main():
                          "hardware byte counters can be scaled by a kernel of known traffic")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 counter runs (no GPU work)")
+    ap.add_argument("--rate-sweep", action="store_true",
+                    help="only the convergence-rate sweep against lambda (power iteration)")
+    ap.add_argument("--sweep-n", type=int, default=16)
+    ap.add_argument("--sweep-Nt", type=int, default=64)
+    ap.add_argument("--sweep-cycles", type=int, default=60)
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
@@ -268,6 +312,10 @@ def main():
         print("bench.py: this build measures one GPU only (the multi-GPU time sharding is a design "
               "note, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.rate_sweep:
+        rate_sweep(args)
+        return
 
     import numpy as np
     import torch

@@ -185,6 +185,22 @@ int stmg_load(stmg_handle *h, const double *rhs_dev, const double *u0_dev,
 int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host);
 int stmg_store(stmg_handle *h, double *x_dev);
 
+/* Convergence rate by power iteration (section 5.1, determining the
+ * convergence rates and lambda_crit): V-cycles with a zero right-hand side,
+ * starting from the error x0_dev (device, full layout [Nt][pt+1][n_edges];
+ * only interior edges are read; typically uniform in [0, 1]), with the l2
+ * norm of the iterate taken after every cycle. Runs max_cycles cycles
+ * (1..8192), or stops at the first cycle whose norm is below underflow
+ * times the starting norm. *rate = the largest reduction factor
+ * ||x_k|| / ||x_{k-1}||; rates_host (may be NULL; room for max_cycles
+ * values) receives every factor and *n_done (may be NULL) their number.
+ * FP64 form only: STMG_EINVAL for a handle in the precision form, a zero
+ * x0 or an argument out of range; STMG_ENUMERIC on a non-finite norm. The
+ * handle's loaded right-hand side and iterate are replaced (b = 0, x = the
+ * last iterate). */
+int stmg_power_rate(stmg_handle *h, const double *x0_dev, int32_t max_cycles, double underflow,
+                    double *rate, double *rates_host, int32_t *n_done);
+
 /* r = b - L x on the finest level, full layout (r's boundary entries are 0).
  * u0_dev may be NULL. */
 int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev,

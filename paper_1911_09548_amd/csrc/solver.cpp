@@ -1470,6 +1470,69 @@ int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host) {
   });
 }
 
+int stmg_power_rate(stmg_handle *h, const double *x0_dev, int32_t max_cycles, double underflow, double *rate,
+                    double *rates_host, int32_t *n_done) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(x0_dev && rate, STMG_EINVAL, "x0 or rate is null");
+    STMG_REQUIRE(max_cycles >= 1 && max_cycles <= 8192, STMG_EINVAL, "max_cycles out of range");
+    STMG_REQUIRE(std::isfinite(underflow) && underflow >= 0.0 && underflow < 1.0, STMG_EINVAL,
+                 "underflow must be in [0, 1)");
+    STMG_REQUIRE(h->opt.precision == STMG_FP64, STMG_EINVAL, "the power iteration runs in the FP64 form");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    MeshData &md = op.mesh(0);
+    const int32_t ne = op.ne(0), E = md.S->topo.ne;
+    const int64_t n = (int64_t)ne * op.W(0);
+    launch_fill(L.b, n, 0.0, h->stream);
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, x0_dev, L.x, h->stream);
+    h->bnorm = 0.0;
+    h->history.clear();
+    h->cycles = 0;
+    auto norm2 = [&](double *dst) {
+      const int nb = launch_sumsq(L.x, n, h->d_partial, h->stream);
+      launch_sum(h->d_partial, nb, dst, h->stream);
+    };
+    // cycles run in batches between host reads of their norms
+    constexpr int32_t BATCH = 64;
+    std::vector<double> n2(BATCH);
+    norm2(h->d_scalar);
+    check_launch();
+    hip_check(hipMemcpyAsync(n2.data(), h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    const double start = std::sqrt(n2[0]);
+    STMG_REQUIRE(std::isfinite(start), STMG_ENUMERIC, "non-finite x0");
+    STMG_REQUIRE(start > 0.0, STMG_EINVAL, "x0 is zero on the interior edges");
+    double prev = start, best = 0.0;
+    int32_t done = 0;
+    bool stop = false;
+    while (!stop && done < max_cycles) {
+      const int32_t nbat = std::min(BATCH, max_cycles - done);
+      for (int32_t i = 0; i < nbat; ++i) {
+        op.vcycle(0, L.x, L.b);
+        norm2(h->d_scalar + i);
+      }
+      check_launch();
+      hip_check(hipMemcpyAsync(n2.data(), h->d_scalar, nbat * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                "copy");
+      hip_check(hipStreamSynchronize(h->stream), "sync");
+      for (int32_t i = 0; i < nbat && !stop; ++i) {
+        const double nx = std::sqrt(n2[i]);
+        STMG_REQUIRE(std::isfinite(nx), STMG_ENUMERIC, "non-finite iterate in the power iteration");
+        const double r = nx / prev;
+        if (rates_host) rates_host[done] = r;
+        best = std::max(best, r);
+        prev = nx;
+        ++done;
+        stop = nx < underflow * start;
+      }
+    }
+    h->cycles = done;
+    *rate = best;
+    if (n_done) *n_done = done;
+  });
+}
+
 int stmg_store(stmg_handle *h, double *x_dev) {
   return guard([&] {
     require_device(h);

@@ -121,13 +121,14 @@ def lib():
         L.stmg_server_destroy.argtypes = [vp]
         L.stmg_profile.argtypes = [vp, ip]
         L.stmg_set_stream_tuning.argtypes = [vp, ip, ip]
+        L.stmg_power_rate.argtypes = [vp, vp, ip, C.c_double, dp, dp, C.POINTER(C.c_int32)]
         L.stmg_profile_count.argtypes = [vp, C.POINTER(C.c_int32)]
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
-                     "stmg_load", "stmg_cycles", "stmg_store", "stmg_residual", "stmg_level_apply",
-                     "stmg_export_matrix", "stmg_export_factor", "stmg_profile", "stmg_profile_count",
-                     "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create", "stmg_submit", "stmg_poll", "stmg_server_wait",
-                     "stmg_server_stats"):
+                     "stmg_load", "stmg_cycles", "stmg_store", "stmg_power_rate", "stmg_residual",
+                     "stmg_level_apply", "stmg_export_matrix", "stmg_export_factor", "stmg_profile",
+                     "stmg_profile_count", "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create",
+                     "stmg_submit", "stmg_poll", "stmg_server_wait", "stmg_server_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -355,6 +356,16 @@ class Solver:
         _check(lib().stmg_cycles(self._h, n, res.ctypes.data_as(C.POINTER(C.c_double))
                                  if want_residuals else None))
         return res[:n] if want_residuals else None
+
+    def power_rate(self, x0, max_cycles=200, underflow=1e-100):
+        """Power iteration (section 5.1): V-cycles with zero right-hand side
+        from the error x0 (full layout, device). Returns (largest reduction
+        factor, list of per-cycle factors)."""
+        rates = np.zeros(max_cycles)
+        rate, done = C.c_double(), C.c_int32()
+        _check(lib().stmg_power_rate(self._h, _ptr(x0), max_cycles, underflow, C.byref(rate),
+                                     rates.ctypes.data_as(C.POINTER(C.c_double)), C.byref(done)))
+        return rate.value, list(rates[:done.value])
 
     def store(self, out=None):
         x = self._full() if out is None else out

@@ -1,0 +1,85 @@
+"""GPU power iteration (section 5.1: convergence rates and lambda_crit).
+
+stmg_power_rate runs V-cycles with a zero right-hand side from a start
+error uniform in [0, 1] and returns the per-cycle l2 reduction factors.
+The oracle's power iteration draws the same start error (same generator and
+seed), so both sides run the same linear iteration: every factor is compared
+(the V-cycles agree to 50 kappa u per cycle, so the factors, ratios of two
+norms, agree to far below 1e-8), for the space-time hierarchy with spatial
+coarsening by eq. (3) ("Full" when lambda_crit = 0 forces it on the top
+level of a two-mesh problem) and without it ("Semi-time"), DG degrees 0 and
+1. Also checked: the stop at underflow, argument errors, and that the
+precision form is refused.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_09548_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CYCLES = 30
+
+
+def _two_mesh(n, Nt, pt, T=1.0):
+    levels = inputs.kuhn_hierarchy(n)[:2]
+    nt = levels[0].tets.shape[0]
+    return inputs.Problem(levels, np.ones(nt), np.ones(nt), T, Nt, pt, meta={"name": "two meshes"})
+
+
+CASES = {  # name: (problem factory, library options, oracle options)
+    "full_n4_N16_p1": (lambda: _two_mesh(4, 16, 1), dict(lambda_crit=0.0), dict(lambda_crit=0.0)),
+    "semi_n4_N16_p1": (lambda: _two_mesh(4, 16, 1), dict(allow_space_coarsening=0), dict(allow_space=False)),
+    "full_n4_N16_p0_T8": (lambda: _two_mesh(4, 16, 0, T=8.0), dict(lambda_crit=0.0), dict(lambda_crit=0.0)),
+    "block_n8_N32_p1": (lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=51, block_hexes=4), {}, {}),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_power_rate_matches_oracle(name):
+    import torch
+    from paper_1911_09548_amd import stmg
+    from oracle.vcycle import SpaceTimeMultigrid
+    make, lopts, oopts = CASES[name]
+    prob = make()
+    print(f"\n[case] power iteration {name}", flush=True)
+    gpu = stmg.Solver(prob, **lopts)
+    ora = SpaceTimeMultigrid(prob, **oopts)
+    assert gpu.n_levels == len(ora.specs)
+    seed = 3
+    rate_ref, rates_ref = ora.power_rate(seed=seed, max_cycles=CYCLES)
+    lev = ora.levels[0]
+    x0 = np.random.default_rng(seed).uniform(0.0, 1.0, size=(lev.N, ora.q, ora.fine.n_e))
+    x0_all = torch.from_numpy(ora.to_all(x0)).cuda()
+    rate, rates = gpu.power_rate(x0_all, max_cycles=CYCLES)
+    gpu.close()
+    diff = max(abs(a - b) for a, b in zip(rates, rates_ref))
+    print(f"[power] {name}: levels {len(ora.specs)}, rate {rate:.6f} (oracle {rate_ref:.6f}), "
+          f"max factor difference {diff:.1e}")
+    assert len(rates) == len(rates_ref) == CYCLES
+    assert diff <= 1e-8
+    assert abs(rate - rate_ref) <= 1e-8 and 0.0 < rate < 1.0
+
+
+def test_power_rate_stops_at_underflow_and_checks_arguments():
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_unit_manufactured(4, 16, 1)
+    gpu = stmg.Solver(prob)
+    x0 = torch.rand((16, 2, gpu.n_edges), dtype=torch.float64, device="cuda")
+    rate, rates = gpu.power_rate(x0, max_cycles=200, underflow=1e-6)
+    reduction = np.prod(rates)
+    print(f"[power] underflow 1e-6 after {len(rates)} cycles: reduction {reduction:.2e}, rate {rate:.4f}")
+    assert len(rates) < 200 and reduction < 1e-6 and np.prod(rates[:-1]) >= 1e-6
+    L = stmg.lib()
+    r = stmg.C.c_double()
+    p = stmg.C.c_void_p(x0.data_ptr())
+    assert L.stmg_power_rate(gpu._h, p, 0, 0.0, stmg.C.byref(r), None, None) == stmg.STMG_EINVAL
+    assert L.stmg_power_rate(gpu._h, p, 10, 1.5, stmg.C.byref(r), None, None) == stmg.STMG_EINVAL
+    zero = torch.zeros_like(x0)
+    assert L.stmg_power_rate(gpu._h, stmg.C.c_void_p(zero.data_ptr()), 10, 0.0, stmg.C.byref(r), None,
+                             None) == stmg.STMG_EINVAL
+    gpu.close()
+    fp32 = stmg.Solver(prob, precision=stmg.FP32_REFINED)
+    assert L.stmg_power_rate(fp32._h, p, 10, 0.0, stmg.C.byref(r), None, None) == stmg.STMG_EINVAL
+    fp32.close()

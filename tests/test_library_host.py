@@ -197,6 +197,9 @@ def test_device_entry_points_refuse_host_only(stmg):
     h = stmg.Solver(prob, host_only=1)
     rc = stmg.lib().stmg_cycles(h._h, 1, None)
     assert rc == stmg.STMG_ENOSYS
+    r = stmg.C.c_double()
+    rc = stmg.lib().stmg_power_rate(h._h, stmg.C.c_void_p(16), 10, 0.0, stmg.C.byref(r), None, None)
+    assert rc == stmg.STMG_ENOSYS
     h.close()
 
 
