@@ -233,8 +233,9 @@ def rate_sweep(args):
     iteration of the SAS V-cycle on a two-mesh Kuhn hierarchy with sigma =
     nu = 1, coarsened in space on its top level ("Full": lambda_crit = 0)
     or in time only ("Semi-time"), for tau / h^2 from 2^-7 to 2^5 and both
-    DG degrees. lambda is the library's eq. (3) value of the top level.
-    Prints one JSON line."""
+    DG degrees; then the smoother orders of section 4 at three values of
+    lambda. lambda is the library's eq. (3) value of the top level. Prints
+    one JSON line."""
     import numpy as np
     import torch
     from paper_1911_09548_amd import inputs, stmg
@@ -262,9 +263,28 @@ def rate_sweep(args):
             rows.append(row)
             log(f"[sweep] pt={pt} lambda={row['lambda']:.4g}: full {row['full']:.4f}, "
                 f"semi-time {row['semi_time']:.4f}")
+    # smoother orders (section 4), p_t = 1, hierarchy by the default rule
+    # (lambda_crit = 0.1): rate, time per cycle and the cycles' cost of one
+    # decade of error reduction
+    orders = []
+    for e in (-7, 0, 5):
+        T = 2.0 ** e * Nt / n ** 2
+        prob = inputs.Problem(meshes, np.ones(nt), np.ones(nt), T, Nt, 1,
+                              meta={"name": f"smoother orders n={n} Nt={Nt} T={T}"})
+        for seq, code in stmg.SMOOTHERS.items():
+            s = stmg.Solver(prob, smoother=code)
+            x0 = torch.from_numpy(np.random.default_rng(7).uniform(0.0, 1.0, (Nt, 2, s.n_edges))).cuda()
+            t0 = time.perf_counter()
+            rate, rates = s.power_rate(x0, max_cycles=cycles)
+            ms = 1e3 * (time.perf_counter() - t0) / max(1, len(rates))
+            row = {"lambda": s.level_info(0).lambda_, "smoother": seq, "rate": rate, "ms_per_cycle": ms,
+                   "ms_per_decade": ms * np.log(10.0) / -np.log(rate) if 0.0 < rate < 1.0 else None}
+            s.close()
+            orders.append(row)
+            log(f"[sweep] lambda={row['lambda']:.4g} {seq}: rate {rate:.4f}, {ms:.1f} ms per cycle")
     print(json.dumps({"rate_sweep": {"mesh": f"{n}^3 x 6 Kuhn tets, two meshes, sigma = nu = 1",
                                      "Nt": Nt, "cycles": cycles, "start": "uniform [0, 1], seed 7",
-                                     "rows": rows}}), flush=True)
+                                     "rows": rows, "smoother_orders": orders}}), flush=True)
 
 
 def main():

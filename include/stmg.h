@@ -60,7 +60,21 @@ enum {
 };
 
 enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
-enum { STMG_SMOOTH_SAS = 0, STMG_SMOOTH_S_ONLY = 1 };
+/* Smoother sequences (section 4): the steps S (damped block Jacobi, eq. (2))
+ * and A (nodal auxiliary correction, eq. (8)) applied in order before and
+ * after the coarse-grid correction on every level. SAS is the method's
+ * choice; S_ONLY (= SS) drops A; the others are the orders the paper
+ * compares with SAS in section 4.1. */
+enum {
+  STMG_SMOOTH_SAS = 0,
+  STMG_SMOOTH_S_ONLY = 1,
+  STMG_SMOOTH_SA = 2,
+  STMG_SMOOTH_AS = 3,
+  STMG_SMOOTH_SSA = 4,
+  STMG_SMOOTH_ASS = 5,
+  STMG_SMOOTH_SSAS = 6,
+  STMG_SMOOTH_SSASS = 7
+};
 
 /* One mesh of a nested hierarchy. Coarse meshes (index >= 1) describe their
  * relation to the next finer mesh:
@@ -94,7 +108,7 @@ typedef struct {
   double omega;                  /* smoother damping, 0.5 (eq. (2)) */
   double lambda_crit;            /* spatial coarsening threshold, 0.1 (section 5.1) */
   int32_t allow_space_coarsening;/* 1: apply eq. (3); 0: coarsen in time only */
-  int32_t smoother;              /* STMG_SMOOTH_SAS (default) | STMG_SMOOTH_S_ONLY (ablation: SS) */
+  int32_t smoother;              /* STMG_SMOOTH_* sequence, default STMG_SMOOTH_SAS */
   int32_t precision;             /* STMG_FP64 | STMG_FP32_REFINED */
   double rtol;                   /* relative residual target of stmg_solve, default 1e-8 */
   int32_t max_cycles;            /* cap of stmg_solve, default 100 */

@@ -13,6 +13,8 @@ Vectors are arrays of shape (N, q, n_e): slab, DG component, interior edge.
   as forward substitution slab by slab.
 * Hybrid smoother (section 4): SAS, the same sequence before and after the
   coarse-grid correction; the coarsest level (one slab) is solved exactly.
+  The other orders of S and A that section 4 compares (SA, AS, SSA, ASS,
+  SSAS, SSASS) are selected with the smoother argument.
 * Power iteration for the convergence rate (section 5.1): zero right-hand side,
   random start in [0, 1], up to 200 cycles, maximum l2 reduction factor, stop
   once the total reduction is below 1e-100.
@@ -113,6 +115,19 @@ class Level:
             x = self.nodal_A(x, b)
         return self.smooth_S(x, b, omega)
 
+    def smooth_sequence(self, x, b, seq, omega=0.5):
+        """The steps of seq in order: 'S' = damped block Jacobi (eq. (2)),
+        'A' = nodal auxiliary correction (eq. (8)). Section 4 compares the
+        orders SA, AS, SSA, ASS, SSAS and SSASS with SAS."""
+        for step in seq:
+            if step == "S":
+                x = self.smooth_S(x, b, omega)
+            elif step == "A":
+                x = self.nodal_A(x, b)
+            else:
+                raise ValueError(f"unknown smoother step {step!r}")
+        return x
+
     def solve_exact_single_slab(self, b):
         assert self.N == 1
         return self.slab.solve(b)
@@ -122,10 +137,13 @@ class SpaceTimeMultigrid:
     """The oracle solver for one problem (see module docstring)."""
 
     def __init__(self, problem, lambda_crit=0.1, omega=0.5, slab_solver="real",
-                 allow_space=True, use_nodal=True, space_levels=None):
+                 allow_space=True, use_nodal=True, space_levels=None, smoother=None):
         self.problem = problem
         self.pt, self.q = problem.pt, problem.pt + 1
         self.omega, self.use_nodal = omega, use_nodal
+        # smoother sequence before and after the coarse-grid correction
+        # (section 4); None: SAS, or SS without the nodal correction
+        self.smoother = smoother
         self.space = space_levels if space_levels is not None else build_space_levels(problem)
         self.specs = build_level_specs(self.space, problem.T, problem.Nt, lambda_crit, allow_space)
         self.levels = [Level(s, self.space[s.space], problem.pt, slab_solver) for s in self.specs]
@@ -165,12 +183,17 @@ class SpaceTimeMultigrid:
         lev = self.levels[l]
         if lev.N == 1:
             return lev.solve_exact_single_slab(b)
-        x = lev.smooth_SAS(x, b, self.omega, self.use_nodal)
+        x = self._smooth(lev, x, b)
         r = lev.residual(x, b)
         rc = self.restrict(l, r)
         ec = self.vcycle(l + 1, np.zeros_like(rc), rc)
         x = x + self.prolong(l, ec)
-        return lev.smooth_SAS(x, b, self.omega, self.use_nodal)
+        return self._smooth(lev, x, b)
+
+    def _smooth(self, lev, x, b):
+        if self.smoother is None:
+            return lev.smooth_SAS(x, b, self.omega, self.use_nodal)
+        return lev.smooth_sequence(x, b, self.smoother, self.omega)
 
     # -- ABI-shaped helpers ------------------------------------------------
     def to_interior(self, v_all):

@@ -759,6 +759,21 @@ struct Bufs<float> {
   using C = cf;
 };
 
+// Steps of each smoother option, in application order (section 4).
+const char *smoother_sequence(int32_t v) {
+  switch (v) {
+    case STMG_SMOOTH_SAS: return "SAS";
+    case STMG_SMOOTH_S_ONLY: return "SS";
+    case STMG_SMOOTH_SA: return "SA";
+    case STMG_SMOOTH_AS: return "AS";
+    case STMG_SMOOTH_SSA: return "SSA";
+    case STMG_SMOOTH_ASS: return "ASS";
+    case STMG_SMOOTH_SSAS: return "SSAS";
+    case STMG_SMOOTH_SSASS: return "SSASS";
+    default: return nullptr;
+  }
+}
+
 template <typename R>
 struct OpsT {
   stmg_handle *h;
@@ -863,10 +878,14 @@ struct OpsT {
           [&] { launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s); });
   }
 
+  // the handle's smoother sequence of S and A steps (section 4)
   void hybrid(int l, R *x, const R *b) {
-    smooth_S(l, x, b);
-    if (h->opt.smoother == STMG_SMOOTH_SAS) nodal_A(l, x, b);
-    smooth_S(l, x, b);
+    for (const char *c = smoother_sequence(h->opt.smoother); *c; ++c) {
+      if (*c == 'S')
+        smooth_S(l, x, b);
+      else
+        nodal_A(l, x, b);
+    }
   }
 
   void exact(int l, R *x, const R *b);
@@ -1136,6 +1155,7 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   else
     stmg_default_options(&h->opt);
   STMG_REQUIRE(h->opt.omega > 0 && h->opt.omega <= 1.0, STMG_EINVAL, "omega must be in (0, 1]");
+  STMG_REQUIRE(smoother_sequence(h->opt.smoother) != nullptr, STMG_EINVAL, "unknown smoother sequence");
   STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
                "unknown precision form");
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libstmg.so")
 
 STMG_OK, STMG_EINVAL, STMG_ENOMEM, STMG_ENOTCONV, STMG_ENUMERIC, STMG_EHIP, STMG_EAGAIN, STMG_ENOSYS = range(8)
 FP64, FP32_REFINED = 0, 1
-SMOOTH_SAS, SMOOTH_S_ONLY = 0, 1
+SMOOTH_SAS, SMOOTH_S_ONLY, SMOOTH_SA, SMOOTH_AS, SMOOTH_SSA, SMOOTH_ASS, SMOOTH_SSAS, SMOOTH_SSASS = range(8)
+SMOOTHERS = {"SAS": SMOOTH_SAS, "SS": SMOOTH_S_ONLY, "SA": SMOOTH_SA, "AS": SMOOTH_AS, "SSA": SMOOTH_SSA,
+             "ASS": SMOOTH_ASS, "SSAS": SMOOTH_SSAS, "SSASS": SMOOTH_SSASS}
 OP_RESIDUAL, OP_SMOOTH_S, OP_NODAL_A, OP_SAS, OP_SLAB_SOLVE, OP_RESTRICT, OP_PROLONG, OP_VCYCLE = range(8)
 MAT_M, MAT_K, MAT_G, MAT_KN, MAT_PE = range(5)
 

@@ -83,3 +83,24 @@ def test_power_rate_stops_at_underflow_and_checks_arguments():
     fp32 = stmg.Solver(prob, precision=stmg.FP32_REFINED)
     assert L.stmg_power_rate(fp32._h, p, 10, 0.0, stmg.C.byref(r), None, None) == stmg.STMG_EINVAL
     fp32.close()
+
+
+@pytest.mark.parametrize("seq", ["SS", "SA", "AS", "SSA", "ASS", "SSAS", "SSASS"])
+def test_smoother_orders_match_oracle(seq):
+    """Section 4's smoother orders: the library's V-cycle with each order gives
+    the oracle's power-iteration factors from the same start error."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    from oracle.vcycle import SpaceTimeMultigrid
+    prob = inputs.config_block_random(n=4, Nt=16, pt=1, seed=61, block_hexes=2)
+    print(f"\n[case] smoother order {seq}", flush=True)
+    gpu = stmg.Solver(prob, smoother=stmg.SMOOTHERS[seq])
+    ora = SpaceTimeMultigrid(prob, smoother=seq)
+    rate_ref, rates_ref = ora.power_rate(seed=5, max_cycles=20)
+    lev = ora.levels[0]
+    x0 = np.random.default_rng(5).uniform(0.0, 1.0, size=(lev.N, ora.q, ora.fine.n_e))
+    rate, rates = gpu.power_rate(torch.from_numpy(ora.to_all(x0)).cuda(), max_cycles=20)
+    gpu.close()
+    diff = max(abs(a - b) for a, b in zip(rates, rates_ref))
+    print(f"[power] smoother {seq}: rate {rate:.6f} (oracle {rate_ref:.6f}), max factor difference {diff:.1e}")
+    assert len(rates) == len(rates_ref) and diff <= 1e-8

@@ -174,6 +174,9 @@ def test_invalid_inputs_are_rejected(stmg):
     bad_parent.levels[1].vertex_parent[5] = [10**6, 0]
     assert _setup_rc(stmg, bad_parent) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, omega=0.0) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, smoother=8) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, smoother=-1) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, smoother=stmg.SMOOTH_SSASS) == stmg.STMG_OK
     assert _setup_rc(stmg, good, stream_chunk=3) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, row_schedule=3) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, row_schedule=-1) == stmg.STMG_EINVAL

@@ -12,6 +12,9 @@
   spatial coarsening without the nodal correction is ineffective (section 3.1,
   rate near 1) and works again with it (section 3.4/4).
 * Manufactured solution: the discretisation error falls under refinement.
+* Smoother orders (section 4): SAS through the sequence path is the same
+  arithmetic as the SAS smoother; every order's V-cycle converges to the
+  direct solution and contracts the error.
 """
 import numpy as np
 import pytest
@@ -146,3 +149,25 @@ def test_manufactured_error_decreases():
         errs.append(np.sqrt(e @ M @ e) / np.sqrt(uT[s.fine.ie] @ M @ uT[s.fine.ie]))
     # at least first order in h (tau shrinks like h^2 here)
     assert errs[1] < 0.5 * errs[0]
+
+
+def test_smoother_sequence_sas_is_the_sas_smoother():
+    s = _solver(4, 8, 1)
+    lev = s.levels[0]
+    rng = np.random.default_rng(4)
+    x, b = rng.standard_normal((2, 8, 2, s.fine.n_e))
+    assert np.array_equal(lev.smooth_sequence(x, b, "SAS"), lev.smooth_SAS(x, b))
+    assert np.array_equal(lev.smooth_sequence(x, b, "SS"), lev.smooth_SAS(x, b, use_nodal=False))
+
+
+@pytest.mark.parametrize("seq", ["SA", "AS", "SSA", "ASS", "SSAS", "SSASS"])
+def test_every_smoother_order_converges_to_direct_solution(seq):
+    s = _solver(4, 8, 1, smoother=seq)
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal((8, 2, s.fine.n_e))
+    x, hist = s.solve(b, rtol=1e-12, max_cycles=80)
+    xd = direct_solve(s, b)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    rate, _ = s.power_rate(seed=0, max_cycles=15)
+    assert rate < 0.6, (seq, rate)
