@@ -87,6 +87,15 @@ def vertex_prolongation(fine: Topology, coarse: Topology, vertex_parent: np.ndar
     return P
 
 
+def finest_space(problem):
+    """SpaceData of the problem's finest mesh alone (no coarse meshes)."""
+    lev = problem.levels[0]
+    topo0 = Topology(lev.coords, lev.tets)
+    M, K = assemble_edge_matrices(topo0, problem.sigma, problem.nu)
+    ie = topo0.interior_edges
+    return SpaceData(topo0, M[ie][:, ie], K[ie][:, ie], problem.nu / problem.sigma)
+
+
 def build_space_levels(problem):
     """SpaceData for every mesh of the problem's nested hierarchy (finest first)."""
     levs = problem.levels

@@ -78,6 +78,18 @@ class Level:
             self.slab = SlabSolverReal(M, K, self.Kt, self.Mt)
         self.Kn_lu = spla.splu(sp.csc_matrix(space.Kn))
 
+    @classmethod
+    def operator_only(cls, space, pt, N, tau):
+        """A level that applies L and its residual but factorises nothing
+        (for checks at sizes where the exact slab and nodal factors are too
+        costly for the oracle)."""
+        lev = cls.__new__(cls)
+        lev.spec, lev.space, lev.pt = None, space, pt
+        lev.q = pt + 1
+        lev.N, lev.tau = N, tau
+        lev.Kt, lev.Mt, lev.Nt = time_matrices(pt, tau)
+        return lev
+
     # -- operators -------------------------------------------------------
     def apply_L(self, x):
         """(L x)_n = A x_n - (N_t (x) M) x_{n-1}."""
@@ -90,6 +102,14 @@ class Level:
 
     def residual(self, x, b):
         return b - self.apply_L(x)
+
+    def apply_slab(self, z):
+        """(I (x) A) z, A = K_t (x) M + M_t (x) K: the slab block that the
+        smoother of eq. (2) inverts, slab by slab."""
+        M, K = self.space.M, self.space.K
+        Mz = np.stack([(M @ z[:, k].T).T for k in range(self.q)], axis=1)
+        Kz = np.stack([(K @ z[:, k].T).T for k in range(self.q)], axis=1)
+        return np.einsum("lk,nkj->nlj", self.Kt, Mz) + np.einsum("lk,nkj->nlj", self.Mt, Kz)
 
     def smooth_S(self, x, b, omega=0.5):
         return x + omega * self.slab.solve(self.residual(x, b))

@@ -171,3 +171,27 @@ def test_every_smoother_order_converges_to_direct_solution(seq):
     assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
     rate, _ = s.power_rate(seed=0, max_cycles=15)
     assert rate < 0.6, (seq, rate)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_slab_operator_inverts_the_slab_solve(pt):
+    """apply_slab is the block whose exact inverse the smoother applies: both
+    slab solvers (the real 2n block LU, and for p_t = 1 the complex
+    diagonalised one, checked against each other above) invert it."""
+    s = _solver(4, 4, pt, slab_solver="complex") if pt == 1 else _solver(4, 4, pt)
+    lev = s.levels[0]
+    r = np.random.default_rng(8).standard_normal((4, pt + 1, s.fine.n_e))
+    z = lev.slab.solve(r)
+    assert np.linalg.norm(lev.apply_slab(z) - r) <= 1e-12 * np.linalg.norm(r)
+
+
+def test_operator_only_level_matches_full_level():
+    from oracle.hierarchy import finest_space
+    from oracle.vcycle import Level
+    prob = inputs.config_block_random(n=4, Nt=8, pt=1, seed=11, block_hexes=2)
+    s = SpaceTimeMultigrid(prob)
+    lev = Level.operator_only(finest_space(prob), 1, 8, prob.T / 8)
+    rng = np.random.default_rng(9)
+    x, b = rng.standard_normal((2, 8, 2, s.fine.n_e))
+    assert np.array_equal(lev.residual(x, b), s.levels[0].residual(x, b))
+    assert np.array_equal(lev.apply_slab(x), s.levels[0].apply_slab(x))
