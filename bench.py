@@ -287,6 +287,47 @@ def rate_sweep(args):
                                      "rows": rows, "smoother_orders": orders}}), flush=True)
 
 
+def core_box(args):
+    """The unstructured high-contrast case (jittered Kuhn mesh, conducting
+    core box [0.3, 0.7]^3 with sigma = 1e4 and nu = 1e-3 inside, sigma = 1e-2
+    outside) at a size that fits one GPU with exact factors: setup, then the
+    solve to 1e-8 in the FP64 and in the precision form. Prints one JSON
+    line."""
+    import numpy as np
+    import torch
+    from paper_1911_09548_amd import inputs, stmg
+
+    n, Nt, pt = args.core_box, args.core_box_Nt, 1
+    prob = inputs.config_core_box(n=n, Nt=Nt, pt=pt, seed=3, jitter=0.2)
+    rhs = None
+    out = {"workload": f"jittered core box, {n}^3 x 6 Kuhn tets (vertices moved by up to 20% of h), "
+                       f"N_t={Nt}, p_t={pt}, Gaussian rhs", "forms": {}}
+    for form, prec in (("fp64", stmg.FP64), ("fp32_refined", stmg.FP32_REFINED)):
+        log(f"[core box] setup {form} n={n} Nt={Nt}")
+        t0 = time.perf_counter()
+        s = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec)
+        setup_s = time.perf_counter() - t0
+        if "levels" not in out:
+            out["levels"] = [{"mesh": li.mesh, "N": li.N, "lambda": li.lambda_, "n_e": li.n_e}
+                             for li in (s.level_info(l) for l in range(s.n_levels))]
+            rhs = torch.from_numpy(inputs.gaussian_rhs(s.n_edges, Nt, pt, seed=2)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, rep = s.solve(rhs, allow_notconv=True)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+        out["forms"][form] = {"setup_s": setup_s, "cycles": rep["cycles"], "time_to_1e-8_s": solve_s,
+                              "ms_per_cycle": 1e3 * solve_s / max(1, rep["cycles"]),
+                              "final_rel_res": rep["rel_res"], "converged": rep["status"] == stmg.STMG_OK,
+                              "history": rep["history"]}
+        log(f"[core box] {form}: setup {setup_s:.1f}s, {rep['cycles']} cycles, {solve_s:.2f}s, "
+            f"rel res {rep['rel_res']:.2e}")
+        s.close()
+        del x
+        torch.cuda.empty_cache()
+    print(json.dumps({"core_box": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +360,9 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=16)
     ap.add_argument("--sweep-Nt", type=int, default=64)
     ap.add_argument("--sweep-cycles", type=int, default=60)
+    ap.add_argument("--core-box", type=int, default=0, metavar="N",
+                    help="only the jittered high-contrast core-box case on an N^3 mesh")
+    ap.add_argument("--core-box-Nt", type=int, default=128)
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
@@ -335,6 +379,9 @@ def main():
 
     if args.rate_sweep:
         rate_sweep(args)
+        return
+    if args.core_box > 0:
+        core_box(args)
         return
 
     import numpy as np
