@@ -243,11 +243,20 @@ __global__ __launch_bounds__(BLOCK) void k_residual_grp(ResidualArgsT<R> a, int 
   R *halo = static_cast<R *>(a.halo);
   const R *hin = seg > 0 ? halo + (int64_t)((seg - 1) & 1) * a.n_rows : nullptr;
   R *hout = seg + 1 < nseg ? halo + (int64_t)(seg & 1) * a.n_rows : nullptr;
-  R am[G][C], ak[G][C];
+  // Accumulators. q = 1: am = M x, ak = K x per value. q = 2, per slab
+  // (packet) with x0, x1: am[2p] = m0 + m1 (its end value), am[2p+1] = m0 -
+  // m1 - (tau/3) k1, ak[p] = -(m0 + m1) - tau k0 (three per slab instead of
+  // four: the residual needs no other combination).
+  constexpr int CK = Q == 2 ? NP : C;
+  const R tau = (R)a.tau, tau3 = tau / (R)3;
+  R am[G][C], ak[G][CK];
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+  for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int j = 0; j < C; ++j) am[g][j] = ak[g][j] = 0;
+    for (int j = 0; j < C; ++j) am[g][j] = 0;
+#pragma unroll
+    for (int j = 0; j < CK; ++j) ak[g][j] = 0;
+  }
   if (active && a.x) {
     // The union entries are read 64 at a time into one register per lane
     // (neighbour row, mask), so the x gathers of a step wait for no other
@@ -284,19 +293,32 @@ __global__ __launch_bounds__(BLOCK) void k_residual_grp(ResidualArgsT<R> a, int 
 #pragma unroll
           for (int g = 0; g < G; ++g) {
             if (!((msk[u] >> g) & 1)) continue;
+            if constexpr (Q == 2) {
+              const R m = mv[u][g], cp = -m - tau * kv[u][g], cq = -m - tau3 * kv[u][g];
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
-#pragma unroll
-              for (int t = 0; t < P; ++t) {
-                am[g][p * P + t] += mv[u][g] * PK::get(v[u][p], t);
-                ak[g][p * P + t] += kv[u][g] * PK::get(v[u][p], t);
+              for (int p = 0; p < NP; ++p) {
+                const R x0 = PK::get(v[u][p], 0), x1 = PK::get(v[u][p], 1);
+                am[g][2 * p] += m * x0;
+                am[g][2 * p] += m * x1;
+                am[g][2 * p + 1] += m * x0;
+                am[g][2 * p + 1] += cq * x1;
+                ak[g][p] += cp * x0;
+                ak[g][p] -= m * x1;
               }
+            } else {
+#pragma unroll
+              for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int t = 0; t < P; ++t) {
+                  am[g][p * P + t] += mv[u][g] * PK::get(v[u][p], t);
+                  ak[g][p * P + t] += kv[u][g] * PK::get(v[u][p], t);
+                }
+            }
           }
       }
     }
   }
   double ss = 0.0;
-  const R tau = (R)a.tau;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     if (row[g] < 0) continue;
@@ -306,15 +328,10 @@ __global__ __launch_bounds__(BLOCK) void k_residual_grp(ResidualArgsT<R> a, int 
     R e_last = 0;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      R e = am[g][p * P + P - 1];
-      if constexpr (Q == 2) e += am[g][p * P];
+      const R e = Q == 2 ? am[g][2 * p] : am[g][p * P + P - 1];
       const R up = __shfl_up(e, 1, 64);
       R wrap = e_in;
-      if (p > 0) {
-        R e1 = am[g][(p - 1) * P + P - 1];
-        if constexpr (Q == 2) e1 += am[g][(p - 1) * P];
-        wrap = __shfl(e1, 63, 64);
-      }
+      if (p > 0) wrap = __shfl(Q == 2 ? am[g][2 * (p - 1)] : am[g][(p - 1) * P + P - 1], 63, 64);
       prev[p] = lane == 0 ? wrap : up;
       e_last = e;
     }
@@ -335,9 +352,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual_grp(ResidualArgsT<R> a, int 
           ss += (double)r * r;
         }
       } else {
-        const R m0 = am[g][2 * p], m1 = am[g][2 * p + 1];
-        const R r0 = PK::get(bv, 0) - (m0 + m1) + prev[p] - tau * ak[g][2 * p];
-        const R r1 = PK::get(bv, 1) + m0 - m1 - prev[p] - (tau / (R)3) * ak[g][2 * p + 1];
+        const R r0 = PK::get(bv, 0) + ak[g][p] + prev[p];
+        const R r1 = PK::get(bv, 1) + am[g][2 * p + 1] - prev[p];
         ss += (double)r0 * r0 + (double)r1 * r1;
         if (a.mode == RES_OUT_SLABRHS) {
           const R s2 = (R)1.4142135623730951;
