@@ -195,16 +195,30 @@ __global__ __launch_bounds__(64) void k_chol_inv_small(const T *F, int64_t m, in
       Ls[i + j * NB] = lij;
     }
     __syncthreads();
-    if (i > j && i < w)
+    // the update's iterations are independent: unrolled, so that their LDS
+    // reads overlap instead of each waiting for the previous write
+    if (i > j && i < w) {
+#pragma unroll 8
       for (int c = j + 1; c <= i; ++c) Ls[i + c * NB] = f_fms(Ls[i + c * NB], lij, Ls[c + j * NB]);
+    }
     __syncthreads();
   }
   // inverse: for j from the last column, Linv[i][j] = -(sum_{k=j+1..i} Linv[i][k] L[k][j]) / L[j][j]
   for (int j = w - 1; j >= 0; --j) {
     const T djinv = f_recip(Ls[j + j * NB]);
+    // acc -= Linv[i,k] L[k,j] over k, in four interleaved partial sums (k mod 4)
+    // added in a fixed order, so that the FMA chain is not one long dependency
     T acc = f_zero(T{});
-    if (i > j && i < w)
-      for (int k = j + 1; k <= i; ++k) acc = f_fms(acc, Ls[i + k * NB], Ls[k + j * NB]);  // acc -= Linv[i,k] L[k,j]
+    if (i > j && i < w) {
+      T a4[4] = {f_zero(T{}), f_zero(T{}), f_zero(T{}), f_zero(T{})};
+      int k = j + 1;
+      for (; k + 3 <= i; k += 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a4[t] = f_fms(a4[t], Ls[i + (k + t) * NB], Ls[k + t + j * NB]);
+      }
+      for (; k <= i; ++k) a4[0] = f_fms(a4[0], Ls[i + k * NB], Ls[k + j * NB]);
+      acc = f_add(f_add(a4[0], a4[1]), f_add(a4[2], a4[3]));
+    }
     __syncthreads();
     if (i == j) Ls[j + j * NB] = djinv;
     if (i > j && i < w) Ls[i + j * NB] = f_mul(acc, djinv);
