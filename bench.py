@@ -373,7 +373,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the multi-GPU time sharding is a design "
+        print("bench.py: measures one GPU only (the multi-GPU time sharding is a design "
               "note, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

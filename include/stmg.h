@@ -56,7 +56,7 @@ enum {
   STMG_ENUMERIC = 4,  /* NaN/Inf in data or residual, zero pivot in a factorisation */
   STMG_EHIP = 5,      /* HIP runtime error (no device, launch failure ...) */
   STMG_EAGAIN = 6,    /* serving: result not ready yet */
-  STMG_ENOSYS = 7     /* entry point not available in this build/handle */
+  STMG_ENOSYS = 7     /* entry point not available for this handle (e.g. built with host_only) */
 };
 
 enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
