@@ -115,9 +115,11 @@ typedef struct {
   int32_t host_only;             /* 1: build host data only (no device), for tests */
   int32_t stream_chunk;          /* residual shape: max values per lane of a row segment, 0 = default (16),
                                     1..16; 32 = LDS-tiled residual (rows in tiles of 64, union staged in LDS) */
-  int32_t row_schedule;          /* residual row visiting order: 0 = Morton order of edge midpoints with wide rows
+  int32_t row_schedule;          /* residual row visiting order: 0 = Hilbert order of edge midpoints with wide rows
                                     in groups of 4 per wavefront (default), 1 = storage order, one row per
-                                    wavefront, 2 = Morton order, one row per wavefront */
+                                    wavefront, 2 = Hilbert order, one row per wavefront, 3 = Morton order, groups
+                                    of 4; the curve is fixed at setup (stmg_set_stream_tuning switches only
+                                    between values with the same curve, or to 1) */
   int32_t leaf_size;             /* nested-dissection leaf size in vertices, default 8 */
   int32_t gemm_rows;             /* supernode GEMM row tile: 0 = chosen per launch, 64 or 32 forced */
   int32_t factor_transpose;      /* also keep P^T for the backward solves: -1 auto, 0 never, 1 always */

@@ -78,9 +78,9 @@ __device__ inline double block_sum(double v) {
 // an XCD is then one segment wide and stays in its L2. Launch s hands the end
 // value E of its last slab to launch s + 1 through halo[row] (two alternating
 // n_rows arrays). Narrow rows: 64 / LPR rows per wave, one segment.
-// Rows are visited in the order sched[] (a Morton order of the edge
-// midpoints): the rows in flight on an XCD then form a compact patch of the
-// mesh whose neighbour rows are gathered while still in its L2.
+// Rows are visited in the order sched[] (a space-filling-curve order of the
+// edge midpoints): the rows in flight on an XCD then form a compact patch of
+// the mesh whose neighbour rows are gathered while still in its L2.
 namespace {
 template <typename R, int P>
 struct Pack;
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(ResidualArgsT<R> a, int seg,
 // the visiting order. The wave walks the sorted union of the group's
 // neighbour rows and gathers each neighbour's x segment once for every row of
 // the group coupled to it (whose mask bit is set; the test is wave-uniform),
-// instead of once per nonzero: neighbouring rows of the Morton order share
-// most of their neighbours, so a group of 4 gathers about 40% fewer x
+// instead of once per nonzero: neighbouring rows along the curve share most
+// of their neighbours, so a group of 4 gathers about 40% fewer x
 // segments than 4 single rows. Each row sums its nonzeros in ascending
 // neighbour order, as the per-row kernel does. Lane mapping, segments, the
 // hand-over of end values and the outputs are those of the per-row kernel.

@@ -135,6 +135,7 @@ struct stmg_handle {
   double setup_s = 0.0, solve_s = 0.0;
   rocblas_handle rb = nullptr;          // during the device setup phase only
   bool device_factor_on = false;        // numeric factorisation on the GPU (from device_factor)
+  bool rows_hilbert = true;             // residual rows in Hilbert order (else Morton), fixed at setup
   stmg::ProfState prof_state;
   stmg::Profiler prof;
   int32_t cycles = 0;

@@ -1,14 +1,14 @@
 """GPU parity for long time horizons: rows of 256 to 8192 values per spatial DOF.
 
 The residual reads a row of N q values as interleaved 2-value packets (one
-wave per row, or per group of 4 rows of the Morton order, from N q = 64 q
+wave per row, or per group of 4 rows of the Hilbert order, from N q = 64 q
 on) and splits rows longer than 64 C values (C the values per lane: the
 stream_chunk option, at most 8 for grouped rows) into segments run as
 consecutive launches, each handing the end value of its last slab to the next
 for the DG coupling; the nodal time scan carries its running sum across
 packets and segments.
 These cases put every lane-chunk width (1, 2, 4, 8, 16 values per lane), 1 to
-32 segments, the grouped and the per-row kernel and both visiting orders
+32 segments, the grouped and the per-row kernel and all visiting orders
 through the residual, the nodal correction and a whole V-cycle, on a 4^3 mesh
 so the oracle stays fast. Tolerances as in the main parity suite: 1e-13 for
 sparse-only steps, 50 kappa u for steps through a triangular solve.
@@ -33,12 +33,13 @@ CASES = {  # name: (Nt, pt, stream_chunk, row_schedule); chunk 0 = the default
     "N2048_p0": (2048, 0, 0, 0),       # 2048 with one value per slab: 4 segments
     "N2048_p0_c1": (2048, 0, 1, 0),    # one value per lane: 32 segments of 64
     "N4096_p1_c8": (4096, 1, 8, 0),    # 8192: 16 segments of 512
-    # one row per wave, Morton order (row_schedule 2) or storage order (1)
+    # one row per wave, Hilbert order (row_schedule 2) or storage order (1); Morton groups (3)
     "N512_p1_c16_rows": (512, 1, 16, 2),    # 1024: one segment, 16 per lane
     "N1024_p1_c16_rows": (1024, 1, 16, 2),  # 2048: 2 segments of 1024
     "N1024_p0_rows": (1024, 0, 0, 2),       # 1024 one value per slab: one segment of 16 per lane
     "N2048_p0_c1_rows": (2048, 0, 1, 2),    # 32 segments of 64
     "N256_p1_storage": (256, 1, 0, 1),      # 512: one segment, storage order
+    "N256_p1_morton": (256, 1, 0, 3),       # 512: grouped rows in Morton order
     "N512_p1_tiles": (512, 1, 32, 0),  # LDS-tiled residual: 64 segments of 16 values per tile
     "N1024_p0_tiles": (1024, 0, 32, 0),
 }

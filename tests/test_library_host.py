@@ -178,7 +178,8 @@ def test_invalid_inputs_are_rejected(stmg):
     assert _setup_rc(stmg, good, smoother=-1) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, smoother=stmg.SMOOTH_SSASS) == stmg.STMG_OK
     assert _setup_rc(stmg, good, stream_chunk=3) == stmg.STMG_EINVAL
-    assert _setup_rc(stmg, good, row_schedule=3) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, row_schedule=4) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, row_schedule=3) == stmg.STMG_OK
     assert _setup_rc(stmg, good, row_schedule=-1) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, stream_chunk=4, row_schedule=1) == stmg.STMG_OK
 
@@ -191,7 +192,8 @@ def test_stream_tuning_values(stmg):
     assert L.stmg_set_stream_tuning(h._h, 5, 0) == stmg.STMG_EINVAL
     assert L.stmg_set_stream_tuning(h._h, 16, 2) == stmg.STMG_OK
     assert L.stmg_set_stream_tuning(h._h, 0, -1) == stmg.STMG_EINVAL
-    assert L.stmg_set_stream_tuning(h._h, 0, 3) == stmg.STMG_EINVAL
+    assert L.stmg_set_stream_tuning(h._h, 0, 3) == stmg.STMG_EINVAL  # Morton groups on a Hilbert setup
+    assert L.stmg_set_stream_tuning(h._h, 0, 4) == stmg.STMG_EINVAL
     h.close()
 
 
