@@ -301,11 +301,12 @@ def core_box(args):
     prob = inputs.config_core_box(n=n, Nt=Nt, pt=pt, seed=3, jitter=0.2)
     rhs = None
     out = {"workload": f"jittered core box, {n}^3 x 6 Kuhn tets (vertices moved by up to 20% of h), "
-                       f"N_t={Nt}, p_t={pt}, Gaussian rhs", "forms": {}}
+                       f"N_t={Nt}, p_t={pt}, Gaussian rhs", "factor_transpose": args.core_box_transpose,
+           "forms": {}}
     for form, prec in (("fp64", stmg.FP64), ("fp32_refined", stmg.FP32_REFINED)):
         log(f"[core box] setup {form} n={n} Nt={Nt}")
         t0 = time.perf_counter()
-        s = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec)
+        s = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec, factor_transpose=args.core_box_transpose)
         setup_s = time.perf_counter() - t0
         if "levels" not in out:
             out["levels"] = [{"mesh": li.mesh, "N": li.N, "lambda": li.lambda_, "n_e": li.n_e}
@@ -363,6 +364,8 @@ def main():
     ap.add_argument("--core-box", type=int, default=0, metavar="N",
                     help="only the jittered high-contrast core-box case on an N^3 mesh")
     ap.add_argument("--core-box-Nt", type=int, default=128)
+    ap.add_argument("--core-box-transpose", type=int, default=-1, choices=(-1, 0, 1),
+                    help="keep P^T for the backward solves: -1 auto, 0 never (half the factor memory)")
     ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
