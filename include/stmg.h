@@ -9,8 +9,10 @@
  *     A = K_t (x) M + M_t (x) K, coupling -N_t (x) M (section 2.1, eq. (1));
  *   - damped block-Jacobi smoother S with exact slab solves (eq. (2));
  *   - nodal auxiliary-space correction A = G Sigma_t K_n^{-1} G^T (eq. (8));
- *   - hybrid smoother SAS (section 4), V-cycle over time meshes with spatial
- *     coarsening where the local anisotropy rule (eq. (3)) holds.
+ *   - hybrid smoother SAS (section 4; the other orders it compares are
+ *     options), V-cycle over time meshes with spatial coarsening where the
+ *     local anisotropy rule (eq. (3)) holds;
+ *   - convergence rates by power iteration (section 5.1).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
