@@ -104,3 +104,17 @@ def test_smoother_orders_match_oracle(seq):
     diff = max(abs(a - b) for a, b in zip(rates, rates_ref))
     print(f"[power] smoother {seq}: rate {rate:.6f} (oracle {rate_ref:.6f}), max factor difference {diff:.1e}")
     assert len(rates) == len(rates_ref) and diff <= 1e-8
+
+
+def test_power_rate_single_slab_is_exact():
+    """One slab: the V-cycle is the exact slab solve, the first factor is 0
+    and the iteration stops there (as the oracle's)."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=4, Nt=1, pt=1, seed=71, block_hexes=2)
+    gpu = stmg.Solver(prob)
+    x0 = torch.rand((1, 2, gpu.n_edges), dtype=torch.float64, device="cuda")
+    rate, rates = gpu.power_rate(x0, max_cycles=10)
+    gpu.close()
+    print(f"[power] single slab: factors {rates}")
+    assert rates == [0.0] and rate == 0.0

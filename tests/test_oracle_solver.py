@@ -195,3 +195,12 @@ def test_operator_only_level_matches_full_level():
     x, b = rng.standard_normal((2, 8, 2, s.fine.n_e))
     assert np.array_equal(lev.residual(x, b), s.levels[0].residual(x, b))
     assert np.array_equal(lev.apply_slab(x), s.levels[0].apply_slab(x))
+
+
+def test_power_rate_of_a_single_slab_is_zero():
+    """With one slab the V-cycle is the exact solve: from any start error the
+    first cycle leaves exactly zero (b = 0), so the rate is 0 and the
+    iteration stops at the underflow test after one cycle."""
+    s = _solver(4, 1, 1)
+    rate, rates = s.power_rate(seed=2, max_cycles=10)
+    assert rates == [0.0] and rate == 0.0
