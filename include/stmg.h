@@ -62,11 +62,12 @@ enum {
 };
 
 enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
-/* Smoother sequences (section 4): the steps S (damped block Jacobi, eq. (2))
- * and A (nodal auxiliary correction, eq. (8)) applied in order before and
- * after the coarse-grid correction on every level. SAS is the method's
- * choice; S_ONLY (= SS) drops A; the others are the orders the paper
- * compares with SAS in section 4.1. */
+/* Smoother sequences (section 4) of the steps S (damped block Jacobi,
+ * eq. (2)) and A (nodal auxiliary correction, eq. (8)). A name reads like a
+ * product of matrices, right to left: before the coarse-grid correction SA
+ * applies A, then S; after it the same steps run in reversed order (S, then
+ * A). SAS is the method's choice; S_ONLY (= SS) drops A; the others are the
+ * orders the paper compares with SAS in section 4.1. */
 enum {
   STMG_SMOOTH_SAS = 0,
   STMG_SMOOTH_S_ONLY = 1,
@@ -228,7 +229,8 @@ int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev,
  *   STMG_OP_RESIDUAL  out = b - L_l x                    (in = x, in2 = b)
  *   STMG_OP_SMOOTH_S  out = x + omega A_l^{-1}(b - L_l x) (eq. (2))
  *   STMG_OP_NODAL_A   out = x + G Sigma_t K_n^{-1} G^T (b - L_l x) (eq. (8))
- *   STMG_OP_SAS       out = S(A(S(x)))                    (section 4)
+ *   STMG_OP_SAS       out = the handle's pre-smoother (S(A(S(x))) for SAS,
+ *                     section 4)
  *   STMG_OP_SLAB_SOLVE out = (I (x) A_l^{-1}) in          (in2 unused)
  *   STMG_OP_RESTRICT  out (level l+1) = (P_t^T (x) P_s^T) in (level l)
  *   STMG_OP_PROLONG   out (level l-1) = (P_t (x) P_s) in (level l)

@@ -11,10 +11,14 @@ Vectors are arrays of shape (N, q, n_e): slab, DG component, interior edge.
   subspace (block bidiagonal, K_t on the diagonal, -N_t below); for implicit
   Euler it is the running sum over time steps of eq. (8). Here it is applied
   as forward substitution slab by slab.
-* Hybrid smoother (section 4): SAS, the same sequence before and after the
-  coarse-grid correction; the coarsest level (one slab) is solved exactly.
-  The other orders of S and A that section 4 compares (SA, AS, SSA, ASS,
-  SSAS, SSASS) are selected with the smoother argument.
+* Hybrid smoother (section 4): SAS before and after the coarse-grid
+  correction; the coarsest level (one slab) is solved exactly. The other
+  orders of S and A that section 4 compares (SA, AS, SSA, ASS, SSAS, SSASS)
+  are selected with the smoother argument. Section 4 reads a name like a
+  product of matrices, right to left (SA = A first, then S), and smooths
+  after the coarse-grid correction with the same steps in reversed order:
+  the pre-smoother applies the name's letters from the last to the first,
+  the post-smoother from the first to the last.
 * Power iteration for the convergence rate (section 5.1): zero right-hand side,
   random start in [0, 1], up to 200 cycles, maximum l2 reduction factor, stop
   once the total reduction is below 1e-100.
@@ -136,9 +140,10 @@ class Level:
         return self.smooth_S(x, b, omega)
 
     def smooth_sequence(self, x, b, seq, omega=0.5):
-        """The steps of seq in order: 'S' = damped block Jacobi (eq. (2)),
-        'A' = nodal auxiliary correction (eq. (8)). Section 4 compares the
-        orders SA, AS, SSA, ASS, SSAS and SSASS with SAS."""
+        """The steps of seq in the order given (first letter first): 'S' =
+        damped block Jacobi (eq. (2)), 'A' = nodal auxiliary correction
+        (eq. (8)). The V-cycle passes a smoother's name reversed before the
+        coarse-grid correction and as written after it (section 4)."""
         for step in seq:
             if step == "S":
                 x = self.smooth_S(x, b, omega)
@@ -203,17 +208,20 @@ class SpaceTimeMultigrid:
         lev = self.levels[l]
         if lev.N == 1:
             return lev.solve_exact_single_slab(b)
-        x = self._smooth(lev, x, b)
+        x = self._smooth(lev, x, b, pre=True)
         r = lev.residual(x, b)
         rc = self.restrict(l, r)
         ec = self.vcycle(l + 1, np.zeros_like(rc), rc)
         x = x + self.prolong(l, ec)
-        return self._smooth(lev, x, b)
+        return self._smooth(lev, x, b, pre=False)
 
-    def _smooth(self, lev, x, b):
+    def _smooth(self, lev, x, b, pre):
+        """Pre-smoothing applies the smoother's name right to left (the
+        product reading of section 4), post-smoothing the reversed order."""
         if self.smoother is None:
             return lev.smooth_SAS(x, b, self.omega, self.use_nodal)
-        return lev.smooth_sequence(x, b, self.smoother, self.omega)
+        seq = self.smoother[::-1] if pre else self.smoother
+        return lev.smooth_sequence(x, b, seq, self.omega)
 
     # -- ABI-shaped helpers ------------------------------------------------
     def to_interior(self, v_all):

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <new>
 #include <numeric>
+#include <cstring>
 
 using namespace stmg;
 
@@ -743,6 +744,10 @@ void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
     L.zn = dev_alloc<double>(h, nv * W);
     L.un = dev_alloc<double>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
   }
+  if (prec && first && last) {
+    L.xe = dev_alloc<double>(h, ne * W);
+    L.be = dev_alloc<double>(h, ne * W);
+  }
   if (prec) {
     L.x32 = dev_alloc<float>(h, ne * W);
     L.b32 = dev_alloc<float>(h, ne * W);
@@ -796,7 +801,8 @@ struct Bufs<float> {
   using C = cf;
 };
 
-// Steps of each smoother option, in application order (section 4).
+// Name of each smoother option as section 4 writes it (a product of S and A
+// steps, applied right to left when pre-smoothing).
 const char *smoother_sequence(int32_t v) {
   switch (v) {
     case STMG_SMOOTH_SAS: return "SAS";
@@ -915,10 +921,14 @@ struct OpsT {
           [&] { launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s); });
   }
 
-  // the handle's smoother sequence of S and A steps (section 4)
-  void hybrid(int l, R *x, const R *b) {
-    for (const char *c = smoother_sequence(h->opt.smoother); *c; ++c) {
-      if (*c == 'S')
+  // The handle's smoother of S and A steps (section 4). Its name reads like
+  // a product of matrices, right to left (SA = A, then S), before the
+  // coarse-grid correction; after it the same steps run in reversed order.
+  void hybrid(int l, R *x, const R *b, bool pre) {
+    const char *seq = smoother_sequence(h->opt.smoother);
+    const int n = (int)strlen(seq);
+    for (int i = 0; i < n; ++i) {
+      if (seq[pre ? n - 1 - i : i] == 'S')
         smooth_S(l, x, b);
       else
         nodal_A(l, x, b);
@@ -960,14 +970,14 @@ struct OpsT {
       exact(l, x, b);
       return;
     }
-    hybrid(l, x, b);
+    hybrid(l, x, b, true);
     residual(l, x, b, B::w(L), RES_OUT_R, nullptr);
     LevelData &C = h->levels[l + 1];
     restrict_to(l, B::w(L), B::b(C));
     launch_fill<R>(B::x(C), (int64_t)ne(l + 1) * W(l + 1), 0.0, s);
     vcycle(l + 1, B::x(C), B::b(C));
     prolong_add(l, B::x(C), x);
-    hybrid(l, x, b);
+    hybrid(l, x, b, false);
   }
 
   // ||b - L x||^2 into dst (device), FP64 accumulation
@@ -987,14 +997,17 @@ void OpsT<double>::exact(int l, double *x, const double *b) {
 }
 
 // The precision form keeps the coarsest solve in FP64: widen b, solve with
-// the FP64 factor, narrow x.
+// the FP64 factor, narrow x. When the coarsest level is level 0 (one slab),
+// its x and b hold the outer FP64 iterate and right-hand side, so the solve
+// works in buffers of its own.
 template <>
 void OpsT<float>::exact(int l, float *x, const float *b) {
   LevelData &L = h->levels[l];
   const int64_t n = (int64_t)ne(l) * W(l);
-  launch_to_double(n, b, L.b, s);
-  OpsT<double>{h, s}.exact(l, L.x, L.b);
-  launch_to_float(n, L.x, x, s);
+  double *xd = L.xe ? L.xe : L.x, *bd = L.be ? L.be : L.b;
+  launch_to_double(n, b, bd, s);
+  OpsT<double>{h, s}.exact(l, xd, bd);
+  launch_to_float(n, xd, x, s);
 }
 
 using Ops = OpsT<double>;
@@ -1082,7 +1095,7 @@ void apply_op(stmg_handle *h, int level, int op_code, R *t0, R *t1, R *t2) {
       hip_check(hipMemcpyAsync(t2, t0, bytes, hipMemcpyDeviceToDevice, s), "copy");
       if (op_code == STMG_OP_SMOOTH_S) op.smooth_S(level, t2, t1);
       if (op_code == STMG_OP_NODAL_A) op.nodal_A(level, t2, t1);
-      if (op_code == STMG_OP_SAS) op.hybrid(level, t2, t1);
+      if (op_code == STMG_OP_SAS) op.hybrid(level, t2, t1, true);
       if (op_code == STMG_OP_VCYCLE) op.vcycle(level, t2, t1);
       break;
     case STMG_OP_SLAB_SOLVE:
@@ -1285,6 +1298,7 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
       bytes += 4 * W * (4 * ne + urow + 2 * nv + md.sym_v.rptr[md.sym_v.ns]);
       if (l == 0 || last) bytes += 8 * W * 3 * ne;
       if (last) bytes += 8 * W * (ne + urow);
+      if (l == 0 && last) bytes += 8 * W * 2 * ne;
     }
   }
   const LevelData &L0 = h->levels[0];

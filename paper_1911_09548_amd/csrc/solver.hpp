@@ -89,6 +89,9 @@ struct LevelData {
   double *g = nullptr, *zn = nullptr, *un = nullptr;
   float *x32 = nullptr, *b32 = nullptr, *w32 = nullptr, *z32 = nullptr, *u32 = nullptr;
   float *g32 = nullptr, *zn32 = nullptr, *un32 = nullptr;
+  // precision form with one level (N_t = 1): the FP64 coarsest solve's own
+  // iterate and right-hand side, apart from the outer x and b of level 0
+  double *xe = nullptr, *be = nullptr;
 };
 
 // Event-pair timing of individual launches (see Profiler).

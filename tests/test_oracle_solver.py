@@ -14,7 +14,12 @@
 * Manufactured solution: the discretisation error falls under refinement.
 * Smoother orders (section 4): SAS through the sequence path is the same
   arithmetic as the SAS smoother; every order's V-cycle converges to the
-  direct solution and contracts the error.
+  direct solution and contracts the error; a name is applied right to left
+  before the coarse-grid correction and in reversed order after it.
+* Transfers: restriction after the fine operator after prolongation is the
+  coarse operator (R L_f P = L_c), assembled column by column from unit
+  vectors, on a level pair that coarsens in space and time and on one that
+  coarsens in time only.
 """
 import numpy as np
 import pytest
@@ -204,3 +209,51 @@ def test_power_rate_of_a_single_slab_is_zero():
     s = _solver(4, 1, 1)
     rate, rates = s.power_rate(seed=2, max_cycles=10)
     assert rates == [0.0] and rate == 0.0
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_restrict_fine_operator_prolong_is_coarse_operator(pt):
+    """Galerkin identity of the hierarchy: the oracle's restriction and
+    prolongation (P_t (x) P_s and its transpose) around the fine level's L
+    give the coarse level's L (time operators rediscretised at 2 tau, spatial
+    M and K Galerkin). Level 0 -> 1 of the 4^3 problem coarsens in space and
+    time (eq. (3) holds), 1 -> 2 in time only."""
+    s = SpaceTimeMultigrid(inputs.config_unit_manufactured(4, 8, pt))
+    assert s.specs[1].space != s.specs[0].space and s.specs[2].space == s.specs[1].space
+    for l in (0, 1):
+        fine, coarse = s.levels[l], s.levels[l + 1]
+        shape = (coarse.N, s.q, coarse.space.n_e)
+        n = int(np.prod(shape))
+        RLP = np.empty((n, n))
+        Lc = np.empty((n, n))
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            e = e.reshape(shape)
+            RLP[:, j] = s.restrict(l, fine.apply_L(s.prolong(l, e))).reshape(-1)
+            Lc[:, j] = coarse.apply_L(e).reshape(-1)
+        assert np.abs(RLP - Lc).max() <= 1e-13 * np.abs(Lc).max(), (pt, l)
+        assert np.abs(Lc).max() > 0
+
+
+def test_smoother_names_read_right_to_left():
+    """Section 4 writes smoothers as products (SA = A, then S) and uses the
+    reversed order after the coarse-grid correction: one two-level cycle with
+    SA is A, S, coarse correction, S, A; with AS the mirror image."""
+    s_sa = _solver(4, 2, 1, smoother="SA")
+    s_as = _solver(4, 2, 1, smoother="AS")
+    lev = s_sa.levels[0]
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((2, 2, s_sa.fine.n_e))
+    b = rng.standard_normal(x.shape)
+
+    def two_level(s, first, second):
+        y = second(first(x, b), b)
+        rc = s.restrict(0, lev.residual(y, b))
+        y = y + s.prolong(0, s.levels[1].solve_exact_single_slab(rc))
+        return first(second(y, b), b)
+
+    S, A = lev.smooth_S, lev.nodal_A
+    assert s_sa.levels[1].N == 1
+    assert np.array_equal(s_sa.vcycle(0, x, b), two_level(s_sa, A, S))
+    assert np.array_equal(s_as.vcycle(0, x, b), two_level(s_as, S, A))
