@@ -9,16 +9,18 @@ here in seconds: its space-time operator L of eq. (1) and the slab block of
 eq. (2) (assembly of M and K, the row formulas in the DG(1) time basis):
 * the GPU residual b - L x against the oracle's, every entry (relative
   1e-13, as in the small parity suites);
-* the level-0 slab solve, the path of the dominant kernels: the oracle's slab
-  block applied to the GPU's result gives back the right-hand side to a
-  relative residual of 1e-10 (the FP64 target);
-* the solve to 1e-8 in the FP64 and the precision form: the oracle's
-  relative residual of the GPU's final iterate is <= 1e-8.
+* the level-0 slab solve, the path of the dominant kernels: its normwise
+  backward error against the oracle's slab block is <= 1e-14 (a bound that
+  does not depend on the conditioning);
+* the FP64 solve to 1e-10: the oracle's relative residual of the GPU's final
+  iterate is <= 1e-10 (the FP64 parity target); the precision form's solve
+  to 1e-8 likewise <= 1e-8, with its distance to the FP64 solution printed.
 """
 import numpy as np
 import pytest
 
 from paper_1911_09548_amd import inputs
+from _parity import BWD64, SPARSE64, fwd, slab_backward_error
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +49,7 @@ def full():
     print("\n[case] full size 32^3 x 256, p_t = 1", flush=True)
     space = finest_space(prob)
     lev = Level.operator_only(space, PT, N, prob.T / N)
-    gpu = stmg.Solver(prob, rtol=1e-8, max_cycles=100)
+    gpu = stmg.Solver(prob, rtol=1e-10, max_cycles=100)
     assert gpu.level_info(0).n_e == space.n_e and gpu.level_info(0).N == N
     yield prob, space, lev, gpu
     gpu.close()
@@ -60,8 +62,8 @@ def test_residual_full_size(full):
     b_all = rng.standard_normal((N, PT + 1, gpu.n_edges))
     got = _host(gpu.residual(_dev(x_all), _dev(b_all)))[..., space.ie]
     ref = lev.residual(x_all[..., space.ie], b_all[..., space.ie])
-    print(f"[full] residual: rel {_rel(got, ref):.2e}")
-    assert _rel(got, ref) <= 1e-13
+    print(f"[full] residual: rel {fwd(got, ref):.2e}")
+    assert fwd(got, ref) <= SPARSE64
 
 
 def test_slab_solve_full_size(full):
@@ -69,9 +71,12 @@ def test_slab_solve_full_size(full):
     prob, space, lev, gpu = full
     r = np.random.default_rng(22).standard_normal((N, PT + 1, space.n_e))
     z = _host(gpu.level_apply(0, stmg.OP_SLAB_SOLVE, _dev(r)))
-    res = _rel(lev.apply_slab(z), r)
-    print(f"[full] slab solve: relative residual {res:.2e}")
-    assert res <= 1e-10
+    eta = slab_backward_error(lev, z, r)
+    print(f"[full] slab solve: backward error {eta:.2e}, relative residual {_rel(lev.apply_slab(z), r):.2e}")
+    assert eta <= BWD64
+
+
+_X64 = {}
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32_refined"])
@@ -85,16 +90,25 @@ def test_solve_full_size(full, form):
     if solver is not gpu:
         solver.close()
     b = b_all[..., space.ie]
-    rr = np.linalg.norm(lev.residual(_host(x)[..., space.ie], b)) / np.linalg.norm(b)
-    print(f"[full] solve {form}: {rep['cycles']} cycles, library {rep['rel_res']:.2e}, oracle residual {rr:.2e}")
-    assert rep["rel_res"] <= 1e-8 and rr <= 1e-8 * (1 + 1e-6)
+    xi = _host(x)[..., space.ie]
+    rr = np.linalg.norm(lev.residual(xi, b)) / np.linalg.norm(b)
+    target = 1e-10 if form == "fp64" else 1e-8
+    extra = ""
+    if form == "fp64":
+        _X64["x"] = xi
+    elif "x" in _X64:
+        extra = f", |x - x_fp64| / |x_fp64| = {_rel(xi, _X64['x']):.2e}"
+    print(f"[full] solve {form}: {rep['cycles']} cycles, library {rep['rel_res']:.2e}, "
+          f"oracle residual {rr:.2e}{extra}")
+    assert rep["rel_res"] <= target and rr <= target * (1 + 1e-6)
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32_refined"])
 def test_core_box_solve(form):
     """The jittered high-contrast core box (sigma 1e4 / 1e-2, nu 1e-3 / 1) at
     24^3 x 128 slabs, larger than the parity suites' 6^3: the oracle's
-    relative residual of the GPU's final iterate is <= 1e-8 in both forms."""
+    relative residual of the GPU's final iterate is <= 1e-10 in the FP64
+    form and <= 1e-8 in the precision form."""
     from paper_1911_09548_amd import stmg
     from oracle.hierarchy import finest_space
     from oracle.vcycle import Level
@@ -103,7 +117,8 @@ def test_core_box_solve(form):
     space = finest_space(prob)
     lev = Level.operator_only(space, 1, 128, prob.T / 128)
     prec = stmg.FP64 if form == "fp64" else stmg.FP32_REFINED
-    gpu = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec)
+    target = 1e-10 if form == "fp64" else 1e-8
+    gpu = stmg.Solver(prob, rtol=target, max_cycles=100, precision=prec)
     b_all = inputs.gaussian_rhs(gpu.n_edges, 128, 1, seed=2)
     x, rep = gpu.solve(_dev(b_all))
     levels = [(gpu.level_info(l).mesh, gpu.level_info(l).N) for l in range(gpu.n_levels)]
@@ -112,4 +127,4 @@ def test_core_box_solve(form):
     rr = np.linalg.norm(lev.residual(_host(x)[..., space.ie], b)) / np.linalg.norm(b)
     print(f"[core box] {form}: levels {levels}, {rep['cycles']} cycles, library {rep['rel_res']:.2e}, "
           f"oracle residual {rr:.2e}")
-    assert rep["rel_res"] <= 1e-8 and rr <= 1e-8 * (1 + 1e-6)
+    assert rep["rel_res"] <= target and rr <= target * (1 + 1e-6)

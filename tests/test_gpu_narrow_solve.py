@@ -2,22 +2,21 @@
 
 Levels with at most 16 slabs solve with 64 x 16 GEMM tiles, whose columns
 beyond the level's width are padding. On 8^3 meshes with N_t = 16 (widths
-16, 8, 4, 2, 1 over the levels) the slab solve of every level is compared
-with the oracle's sparse direct solve (relative error <= 50 kappa u, kappa
-the condition number of the SPD matrix M + tau K, as in the main parity
-suite) and with the same solve whose backward sweep reads P_s instead of
-the stored transpose (<= 1e-12), with automatic and forced K splits and the
-GPU factorisation.
+16, 8, 4, 2, 1 over the levels) the slab solve of every level is checked
+by its normwise backward error against the oracle's slab block (<= 1e-14),
+its forward difference from the oracle's sparse direct solve (<= 1e-10),
+and against the same solve whose backward sweep reads P_s instead of the
+stored transpose (<= 1e-12), with automatic and forced K splits and the GPU
+factorisation. The nodal correction is checked by the gradient component of
+the new residual and its forward difference (tests/_parity.py).
 """
 import numpy as np
 import pytest
-import scipy.sparse.linalg as spla
 
 from paper_1911_09548_amd import inputs
+from _parity import BWD64, FWD64, fwd, gradient_orthogonality, slab_backward_error
 
 pytestmark = pytest.mark.gpu
-
-U = 2.0 ** -53
 
 CASES = {  # name: (Nt, pt, options)
     "N16_p1": (16, 1, {}),
@@ -39,12 +38,6 @@ def _host(t):
 def _rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
-def _cond_spd(A):
-    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
-    lmin = spla.eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
-    return float(lmax / lmin)
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -71,11 +64,11 @@ def test_slab_solve_every_width(trio):
         ref = lev.slab.solve(r)
         got = _host(gpu.level_apply(l, stmg.OP_SLAB_SOLVE, _dev(r)))
         other = _host(alt.level_apply(l, stmg.OP_SLAB_SOLVE, _dev(r)))
-        tol = max(1e-12, 50 * _cond_spd((lev.space.M + lev.tau * lev.space.K).tocsc()) * U)
-        print(f"[narrow] {name} level {l} (N={lev.N}): oracle {_rel(got, ref):.2e} (tol {tol:.1e}), "
-              f"backward from P {_rel(got, other):.2e}")
-        assert _rel(got, ref) <= tol, (name, l)
-        assert _rel(got, other) <= 1e-12, (name, l)
+        eta = slab_backward_error(lev, got, r)
+        print(f"[narrow] {name} level {l} (N={lev.N}): backward error {eta:.1e}, oracle {fwd(got, ref):.2e}, "
+              f"backward sweep from P {fwd(got, other):.2e}")
+        assert eta <= BWD64 and fwd(got, ref) <= FWD64, (name, l, eta)
+        assert fwd(got, other) <= 1e-12, (name, l)
 
 
 def test_nodal_correction(trio):
@@ -88,9 +81,9 @@ def test_nodal_correction(trio):
         rng = np.random.default_rng(200 + l)
         x = rng.standard_normal((lev.N, ora.q, lev.space.n_e))
         b = rng.standard_normal((lev.N, ora.q, lev.space.n_e))
-        kn = _cond_spd(lev.space.Kn.tocsc())
         got = _host(gpu.level_apply(l, stmg.OP_NODAL_A, _dev(x), _dev(b)))
-        assert _rel(got, lev.nodal_A(x, b)) <= max(1e-12, 50 * kn * U), (name, l)
+        assert gradient_orthogonality(lev, got, b) <= 1e-13, (name, l)
+        assert fwd(got, lev.nodal_A(x, b)) <= FWD64, (name, l)
 
 
 def test_solve_meets_tolerance(trio):

@@ -2,25 +2,31 @@
 
 Each level operation (residual, smoother S, nodal correction A, SAS, slab
 solve, restriction, prolongation, V-cycle) is called through the C ABI on
-seeded inputs and compared element by element with the oracle's result for
-the same inputs. Sizes are chosen so the solves span several supernode
-heights, diagonal blocks of more than 64 columns, several right-hand-side
-column tiles and ragged tails, with both DG degrees.
+seeded inputs and compared with the oracle's result for the same inputs,
+norm-wise and entry by entry. Sizes are chosen so the solves span several
+supernode heights, diagonal blocks of more than 64 columns, several
+right-hand-side column tiles and ragged tails, with both DG degrees.
 
-Tolerances (FP64, relative to the output norm): a step that applies sparse
-operators only is compared at 1e-13; a step that goes through a triangular
-solve at 50 * kappa * u (u = 2^-53, kappa the 2-norm condition number of the
-SPD matrix it factors: M + tau K for the slab block, K_n for the nodal
-correction), never tighter than 1e-12. Backward-stable solves in either
-implementation differ by at most a small multiple of kappa * u.
+Bounds (FP64; none depends on a condition number; see tests/_parity.py):
+* sparse-only steps (residual, transfers): 1e-13 relative, norm-wise and
+  entry-wise;
+* the slab solve: normwise backward error against the oracle's slab block
+  <= 1e-14, and forward difference from the oracle's solve <= 1e-10;
+* S: backward error of A (x' - x) = omega (b - L x) <= 1e-14, forward <= 1e-10;
+* A: the new residual's gradient component (eq. (8) makes it vanish)
+  <= 1e-13 of its rounding scale, forward <= 1e-10;
+* SAS: forward <= 1e-10, and bitwise equal to the GPU's S, A, S applied by
+  three separate calls;
+* V-cycle and solution: forward <= 1e-10; per-cycle residual history within
+  1e-10 relative plus the roundoff level of the residual norm; the oracle's
+  residual of the final iterate <= 1e-10.
 """
-import functools
-
 import numpy as np
 import pytest
-import scipy.sparse.linalg as spla
 
 from paper_1911_09548_amd import inputs
+from _parity import (BWD64, FWD64, SPARSE64, fwd, gradient_orthogonality, history_floor,
+                     slab_backward_error, smoother_backward_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,32 +38,6 @@ def _dev(a):
 
 def _host(t):
     return t.detach().cpu().numpy()
-
-
-U = 2.0 ** -53
-
-
-def _cond_spd(A):
-    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
-    lmin = spla.eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
-    return float(lmax / lmin)
-
-
-@functools.lru_cache(maxsize=None)
-def _tols(name, l):
-    ora = _ORACLES[name]
-    lev = ora.levels[l]
-    ks = _cond_spd((lev.space.M + lev.tau * lev.space.K).tocsc())
-    kn = _cond_spd(lev.space.Kn.tocsc()) if lev.space.n_v > 1 else 1.0
-    return max(1e-12, 50 * ks * U), max(1e-12, 50 * kn * U)
-
-
-_ORACLES = {}
-
-
-def _rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 CASES = {
@@ -92,7 +72,6 @@ def pair(request):
     print(f"\n[case] {request.param}", flush=True)
     gpu = stmg.Solver(prob, **OPTS.get(request.param, {}))
     ora = SpaceTimeMultigrid(prob)
-    _ORACLES[request.param] = ora
     yield request.param, prob, gpu, ora
     gpu.close()
 
@@ -119,19 +98,20 @@ def test_residual(pair):
         x, b = _vec(ora, l, 1), _vec(ora, l, 2)
         ref = ora.levels[l].residual(x, b)
         got = _host(gpu.level_apply(l, stmg.OP_RESIDUAL, _dev(x), _dev(b)))
-        assert _rel(got, ref) <= 1e-13, (name, l)
+        assert fwd(got, ref) <= SPARSE64, (name, l, fwd(got, ref))
 
 
 def test_slab_solve(pair):
     from paper_1911_09548_amd import stmg
     name, prob, gpu, ora = pair
     for l in range(gpu.n_levels):
+        lev = ora.levels[l]
         r = _vec(ora, l, 3)
-        ref = ora.levels[l].slab.solve(r)
         got = _host(gpu.level_apply(l, stmg.OP_SLAB_SOLVE, _dev(r)))
-        tol = _tols(name, l)[0]
-        print(f"[slab] {name} level {l}: rel {_rel(got, ref):.2e} tol {tol:.1e}")
-        assert _rel(got, ref) <= tol, (name, l, _rel(got, ref))
+        eta = slab_backward_error(lev, got, r)
+        d = fwd(got, lev.slab.solve(r))
+        print(f"[slab] {name} level {l}: backward error {eta:.1e}, forward {d:.1e}")
+        assert eta <= BWD64 and d <= FWD64, (name, l, eta, d)
 
 
 @pytest.mark.parametrize("op", ["S", "A", "SAS"])
@@ -142,17 +122,25 @@ def test_smoothers(pair, op):
     for l in range(gpu.n_levels):
         lev = ora.levels[l]
         x, b = _vec(ora, l, 4), _vec(ora, l, 5)
-        if op == "S":
-            ref = lev.smooth_S(x, b, 0.5)
-        elif op == "A":
-            ref = lev.nodal_A(x, b)
-        else:
-            ref = lev.smooth_SAS(x, b, 0.5, True)
         got = _host(gpu.level_apply(l, code, _dev(x), _dev(b)))
-        ts, tn = _tols(name, l)
-        tol = {"S": ts, "A": tn, "SAS": max(ts, tn)}[op]
-        print(f"[{op}] {name} level {l}: rel {_rel(got, ref):.2e} tol {tol:.1e}")
-        assert _rel(got, ref) <= tol, (name, op, l, _rel(got, ref))
+        if op == "S":
+            d = fwd(got, lev.smooth_S(x, b, 0.5))
+            e = smoother_backward_error(lev, x, b, got)
+            print(f"[S] {name} level {l}: forward {d:.1e}, backward error {e:.1e}")
+            assert e <= BWD64, (name, l, e)
+        elif op == "A":
+            d = fwd(got, lev.nodal_A(x, b))
+            e = gradient_orthogonality(lev, got, b) if lev.space.n_v > 0 else 0.0
+            print(f"[A] {name} level {l}: forward {d:.1e}, gradient residual {e:.1e}")
+            assert e <= 1e-13, (name, l, e)
+        else:
+            d = fwd(got, lev.smooth_SAS(x, b, 0.5, True))
+            s1 = gpu.level_apply(l, stmg.OP_SMOOTH_S, _dev(x), _dev(b))
+            a1 = gpu.level_apply(l, stmg.OP_NODAL_A, s1, _dev(b))
+            s2 = _host(gpu.level_apply(l, stmg.OP_SMOOTH_S, a1, _dev(b)))
+            print(f"[SAS] {name} level {l}: forward {d:.1e}")
+            assert np.array_equal(got, s2), (name, l, "SAS != S(A(S)) on the GPU")
+        assert d <= FWD64, (name, op, l, d)
 
 
 def test_transfers(pair):
@@ -162,11 +150,11 @@ def test_transfers(pair):
         r = _vec(ora, l, 6)
         ref = ora.restrict(l, r)
         got = _host(gpu.level_apply(l, stmg.OP_RESTRICT, _dev(r)))
-        assert _rel(got, ref) <= 1e-13, (name, "restrict", l)
+        assert fwd(got, ref) <= SPARSE64, (name, "restrict", l)
         e = _vec(ora, l + 1, 7)
         ref = ora.prolong(l, e)
         got = _host(gpu.level_apply(l + 1, stmg.OP_PROLONG, _dev(e)))
-        assert _rel(got, ref) <= 1e-13, (name, "prolong", l)
+        assert fwd(got, ref) <= SPARSE64, (name, "prolong", l)
 
 
 def test_vcycle(pair):
@@ -175,9 +163,8 @@ def test_vcycle(pair):
     x, b = _vec(ora, 0, 8), _vec(ora, 0, 9)
     ref = ora.vcycle(0, x, b)
     got = _host(gpu.level_apply(0, stmg.OP_VCYCLE, _dev(x), _dev(b)))
-    tol = max(max(_tols(name, l)) for l in range(gpu.n_levels))
-    print(f"[vcycle] {name}: rel {_rel(got, ref):.2e} tol {tol:.1e}")
-    assert _rel(got, ref) <= tol, (name, _rel(got, ref))
+    print(f"[vcycle] {name}: forward {fwd(got, ref):.1e}")
+    assert fwd(got, ref) <= FWD64, (name, fwd(got, ref))
 
 
 def test_full_solve_history_and_solution(pair):
@@ -192,19 +179,18 @@ def test_full_solve_history_and_solution(pair):
     gpu.load(_dev(b_all), _dev(u0))
     hist = gpu.cycles(len(hist_ref))
     x = _host(gpu.store())
-    # per-cycle relative residuals agree to 1e-8 relative, down to a floor of
-    # 1e-15 (roundoff of ||b - Lx|| / ||b|| itself)
+    floor = history_floor(ora.levels[0], x_ref, b)
+    worst = max(abs(h - hr) / (1e-10 * hr + floor) for h, hr in zip(hist, hist_ref))
+    print(f"[history] {name}: {len(hist)} cycles, max |h - h_ref| / (1e-10 h_ref + {floor:.1e}) = {worst:.2f}")
     for k, (h, hr) in enumerate(zip(hist, hist_ref)):
-        assert abs(h - hr) <= 1e-8 * hr + 1e-15, (name, k, h, hr)
+        assert abs(h - hr) <= 1e-10 * hr + floor, (name, k, h, hr)
     assert hist[-1] <= 1e-10
     # the oracle's residual of the GPU solution
     x_int = ora.to_interior(x)
     rr = np.linalg.norm(ora.levels[0].residual(x_int, b)) / np.linalg.norm(b)
+    print(f"[solve] {name}: oracle residual {rr:.2e} |x - x_oracle| {fwd(x_int, x_ref):.2e}")
     assert rr <= 1e-10, (name, rr)
-    tol = max(1e-9, max(max(_tols(name, l)) for l in range(gpu.n_levels)))
-    print(f"[solve] {name}: cycles {len(hist)} oracle-residual {rr:.2e} "
-          f"|x - x_oracle|/|x_oracle| {_rel(x_int, x_ref):.2e} tol {tol:.1e}")
-    assert _rel(x_int, x_ref) <= tol
+    assert fwd(x_int, x_ref) <= FWD64
     bnd = np.ones(E, dtype=bool)
     bnd[ora.fine.ie] = False
     assert np.all(x[..., bnd] == 0.0)
@@ -220,7 +206,7 @@ def test_full_layout_residual(pair):
     r = _host(gpu.residual(_dev(x_all), _dev(b_all), _dev(u0)))
     b = ora.fold_initial(ora.to_interior(b_all), u0)
     ref = ora.levels[0].residual(ora.to_interior(x_all), b)
-    assert _rel(ora.to_interior(r), ref) <= 1e-13
+    assert fwd(ora.to_interior(r), ref) <= SPARSE64
     bnd = np.ones(E, dtype=bool)
     bnd[ora.fine.ie] = False
     assert np.all(r[..., bnd] == 0.0)

@@ -3,9 +3,9 @@
 stmg_power_rate runs V-cycles with a zero right-hand side from a start
 error uniform in [0, 1] and returns the per-cycle l2 reduction factors.
 The oracle's power iteration draws the same start error (same generator and
-seed), so both sides run the same linear iteration: every factor is compared
-(the V-cycles agree to 50 kappa u per cycle, so the factors, ratios of two
-norms, agree to far below 1e-8), for the space-time hierarchy with spatial
+seed), so both sides run the same linear iteration: every factor (a ratio of
+two norms of iterates that agree to rounding) is compared to 1e-10 absolute,
+for the space-time hierarchy with spatial
 coarsening by eq. (3) ("Full" when lambda_crit = 0 forces it on the top
 level of a two-mesh problem) and without it ("Semi-time"), DG degrees 0 and
 1. Also checked: the stop at underflow, argument errors, and that the
@@ -57,8 +57,8 @@ def test_power_rate_matches_oracle(name):
     print(f"[power] {name}: levels {len(ora.specs)}, rate {rate:.6f} (oracle {rate_ref:.6f}), "
           f"max factor difference {diff:.1e}")
     assert len(rates) == len(rates_ref) == CYCLES
-    assert diff <= 1e-8
-    assert abs(rate - rate_ref) <= 1e-8 and 0.0 < rate < 1.0
+    assert diff <= 1e-10
+    assert abs(rate - rate_ref) <= 1e-10 and 0.0 < rate < 1.0
 
 
 def test_power_rate_stops_at_underflow_and_checks_arguments():
@@ -103,7 +103,7 @@ def test_smoother_orders_match_oracle(seq):
     gpu.close()
     diff = max(abs(a - b) for a, b in zip(rates, rates_ref))
     print(f"[power] smoother {seq}: rate {rate:.6f} (oracle {rate_ref:.6f}), max factor difference {diff:.1e}")
-    assert len(rates) == len(rates_ref) and diff <= 1e-8
+    assert len(rates) == len(rates_ref) and diff <= 1e-10
 
 
 def test_power_rate_single_slab_is_exact():

@@ -2,22 +2,26 @@
 solves inside an FP64 refinement loop (FP64 outer residual, FP64 factors
 rounded to FP32, FP64 coarsest solve).
 
-* Each FP32 level operation is compared with the FP64 oracle on the same
-  inputs at 50 * kappa * u32 (u32 = 2^-24, kappa the 2-norm condition number
-  of the SPD matrix the step factors), never tighter than 1e-5; sparse-only
-  steps at 1e-5.
-* A refined solve to 1e-8 must have an oracle-computed relative residual
-  <= 1e-8; its distance to the oracle's FP64 solution is reported per case.
+Each FP32 level operation is checked with bounds that do not depend on a
+condition number (tests/_parity.py):
+* residual: 1e-5 relative, norm-wise and entry-wise (FP32 sparse sums);
+* slab solve: normwise backward error against the oracle's FP64 slab block
+  <= 1e-6 (the coarsest level solves in FP64: <= 1e-14 and forward <= 1e-10);
+* S as a solve A (x' - x) = omega (b - L x): backward error <= 1e-6;
+* A: the new residual's gradient component <= 1e-6 of its rounding scale;
+* SAS: bitwise equal to the GPU's S, A, S applied by three separate calls.
+A refined solve to 1e-8 must have an oracle-computed relative residual
+<= 1e-8; its distance to the oracle's FP64 solution is reported per case.
+One-slab problems (the coarsest level is the finest) are solved in both
+forms and compared with the oracle's direct slab solve.
 """
 import numpy as np
 import pytest
-import scipy.sparse.linalg as spla
 
 from paper_1911_09548_amd import inputs
+from _parity import BWD32, BWD64, FWD64, fwd, gradient_orthogonality, slab_backward_error, smoother_backward_error
 
 pytestmark = pytest.mark.gpu
-
-U32 = 2.0 ** -24
 
 CASES = {
     "unit_n4_N16_p1": lambda: inputs.config_unit_manufactured(4, 16, 1),
@@ -42,12 +46,6 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def _cond_spd(A):
-    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
-    lmin = spla.eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
-    return float(lmax / lmin)
-
-
 @pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
     from paper_1911_09548_amd import stmg
@@ -56,11 +54,7 @@ def pair(request):
     print(f"\n[case] {request.param} (precision form)", flush=True)
     gpu = stmg.Solver(prob, precision=stmg.FP32_REFINED, rtol=1e-8, **OPTS.get(request.param, {}))
     ora = SpaceTimeMultigrid(prob)
-    tols = []
-    for lev in ora.levels:
-        ks = _cond_spd((lev.space.M + lev.tau * lev.space.K).tocsc())
-        kn = _cond_spd(lev.space.Kn.tocsc()) if lev.space.n_v > 1 else 1.0
-        tols.append((max(1e-5, 50 * ks * U32), max(1e-5, 50 * kn * U32)))
+    tols = None
     yield request.param, prob, gpu, ora, tols
     gpu.close()
 
@@ -77,19 +71,28 @@ def test_fp32_steps(pair):
     for l, lev in enumerate(ora.levels):
         x, b = _vec(ora, l, 1), _vec(ora, l, 2)
         got = _host(gpu.level_apply(l, stmg.OP_RESIDUAL, _dev(x), _dev(b)))
-        assert _rel(got, lev.residual(x, b)) <= 1e-5, (name, "residual", l)
+        assert fwd(got, lev.residual(x, b)) <= 1e-5, (name, "residual", l)
         got = _host(gpu.level_apply(l, stmg.OP_SLAB_SOLVE, _dev(x)))
-        tol = tols[l][0] if l < last else 1e-11 * max(1.0, tols[l][0] / 1e-5)  # coarsest: FP64
-        assert _rel(got, lev.slab.solve(x)) <= tol, (name, "slab", l, _rel(got, lev.slab.solve(x)))
+        eta, d = slab_backward_error(lev, got, x), fwd(got, lev.slab.solve(x))
+        print(f"[fp32 slab] {name} level {l}: backward error {eta:.1e}, forward {d:.1e}")
         if l == last:
+            assert eta <= BWD64 and d <= FWD64, (name, "slab", l, eta, d)
             continue
-        ts, tn = tols[l]
-        for code, ref, tol in ((stmg.OP_SMOOTH_S, lev.smooth_S(x, b, 0.5), ts),
-                               (stmg.OP_NODAL_A, lev.nodal_A(x, b), tn),
-                               (stmg.OP_SAS, lev.smooth_SAS(x, b, 0.5, True), max(ts, tn))):
-            got = _host(gpu.level_apply(l, code, _dev(x), _dev(b)))
-            print(f"[fp32 op {code}] {name} level {l}: rel {_rel(got, ref):.2e} tol {tol:.1e}")
-            assert _rel(got, ref) <= tol, (name, code, l, _rel(got, ref))
+        assert eta <= BWD32, (name, "slab", l, eta)
+        got = _host(gpu.level_apply(l, stmg.OP_SMOOTH_S, _dev(x), _dev(b)))
+        e = smoother_backward_error(lev, x, b, got)
+        print(f"[fp32 S] {name} level {l}: backward error {e:.1e}, forward {fwd(got, lev.smooth_S(x, b)):.1e}")
+        assert e <= BWD32, (name, "S", l, e)
+        got = _host(gpu.level_apply(l, stmg.OP_NODAL_A, _dev(x), _dev(b)))
+        if lev.space.n_v > 0:
+            e = gradient_orthogonality(lev, got, b)
+            print(f"[fp32 A] {name} level {l}: gradient residual {e:.1e}, forward {fwd(got, lev.nodal_A(x, b)):.1e}")
+            assert e <= 1e-6, (name, "A", l, e)
+        got = _host(gpu.level_apply(l, stmg.OP_SAS, _dev(x), _dev(b)))
+        s1 = gpu.level_apply(l, stmg.OP_SMOOTH_S, _dev(x), _dev(b))
+        a1 = gpu.level_apply(l, stmg.OP_NODAL_A, s1, _dev(b))
+        s2 = _host(gpu.level_apply(l, stmg.OP_SMOOTH_S, a1, _dev(b)))
+        assert np.array_equal(got, s2), (name, "SAS", l)
 
 
 def test_refined_solve(pair):
@@ -112,3 +115,32 @@ def test_refined_solve(pair):
     assert err <= 1e-6
     fp64_cycles = next(k + 1 for k, h in enumerate(hist_ref) if h <= 1e-8)
     assert rep["cycles"] <= fp64_cycles + 3
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+@pytest.mark.parametrize("form", ["fp64", "fp32_refined"])
+def test_one_slab(pt, form):
+    """N_t = 1: the only level is the coarsest, solved exactly with the FP64
+    factor; in the precision form each refinement iteration solves the FP32
+    residual in FP64. The result is the oracle's direct slab solve."""
+    from paper_1911_09548_amd import stmg
+    from oracle.vcycle import SpaceTimeMultigrid
+    prob = inputs.config_block_random(n=8, Nt=1, pt=pt, seed=31, block_hexes=4)
+    print(f"\n[case] one slab pt={pt} {form}", flush=True)
+    prec = stmg.FP64 if form == "fp64" else stmg.FP32_REFINED
+    gpu = stmg.Solver(prob, precision=prec, rtol=1e-10, max_cycles=20)
+    ora = SpaceTimeMultigrid(prob)
+    assert gpu.n_levels == 1 and len(ora.levels) == 1
+    b_all = np.random.default_rng(32).standard_normal((1, pt + 1, gpu.n_edges))
+    b = ora.to_interior(b_all)
+    x_ref = ora.levels[0].solve_exact_single_slab(b)
+    for rep_i in range(2):  # a second solve on the same handle starts clean
+        x, rep = gpu.solve(_dev(b_all))
+        xi = ora.to_interior(_host(x))
+        rr = np.linalg.norm(ora.levels[0].residual(xi, b)) / np.linalg.norm(b)
+        print(f"[one slab] pt={pt} {form}: cycles {rep['cycles']}, oracle residual {rr:.2e}, "
+              f"forward {fwd(xi, x_ref):.2e}")
+        assert rep["rel_res"] <= 1e-10 and rr <= 1e-10
+        assert fwd(xi, x_ref) <= FWD64
+        assert rep["cycles"] <= (1 if form == "fp64" else 10)
+    gpu.close()
