@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .mesh import Topology
+from .mesh import DIRICHLET, Topology
 from .fem import assemble_edge_matrices
 
 
@@ -87,10 +87,15 @@ def vertex_prolongation(fine: Topology, coarse: Topology, vertex_parent: np.ndar
     return P
 
 
+def problem_bc(problem):
+    """The problem's boundary condition (Dirichlet unless it names Neumann)."""
+    return getattr(problem, "bc", DIRICHLET)
+
+
 def finest_space(problem):
     """SpaceData of the problem's finest mesh alone (no coarse meshes)."""
     lev = problem.levels[0]
-    topo0 = Topology(lev.coords, lev.tets)
+    topo0 = Topology(lev.coords, lev.tets, problem_bc(problem))
     M, K = assemble_edge_matrices(topo0, problem.sigma, problem.nu)
     ie = topo0.interior_edges
     return SpaceData(topo0, M[ie][:, ie], K[ie][:, ie], problem.nu / problem.sigma)
@@ -99,13 +104,14 @@ def finest_space(problem):
 def build_space_levels(problem):
     """SpaceData for every mesh of the problem's nested hierarchy (finest first)."""
     levs = problem.levels
-    topo0 = Topology(levs[0].coords, levs[0].tets)
+    bc = problem_bc(problem)
+    topo0 = Topology(levs[0].coords, levs[0].tets, bc)
     M, K = assemble_edge_matrices(topo0, problem.sigma, problem.nu)
     ie, iv = topo0.interior_edges, topo0.interior_vertices
     out = [SpaceData(topo0, M[ie][:, ie], K[ie][:, ie], problem.nu / problem.sigma)]
     for j in range(1, len(levs)):
         fine = out[-1]
-        topo = Topology(levs[j].coords, levs[j].tets)
+        topo = Topology(levs[j].coords, levs[j].tets, bc)
         Pe_all = edge_prolongation(fine.topo, topo, levs[j].vertex_parent)
         Pn_all = vertex_prolongation(fine.topo, topo, levs[j].vertex_parent)
         Pe = sp.csr_matrix(Pe_all[fine.ie][:, topo.interior_edges])

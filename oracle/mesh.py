@@ -13,6 +13,13 @@ specification):
   curl C (faces x edges);
 * a boundary face belongs to exactly one tetrahedron; boundary edges and
   vertices are those of boundary faces; Dirichlet (u x n = 0) eliminates them.
+* the Neumann condition (mu^{-1} curl u x n = 0, section 3) is natural: every
+  edge stays a degree of freedom. The nodal space then contains the
+  constants, which G maps to zero (G 1 = 0), so G^T M G is singular. One
+  gauge vertex (the lowest-numbered one) is left out of the nodal space: the
+  remaining columns of G span the same range as all of them, so the nodal
+  correction (eq. (8)) is unchanged while the nodal matrix becomes SPD (for a
+  connected mesh).
 """
 from __future__ import annotations
 
@@ -22,8 +29,14 @@ import numpy as np
 import scipy.sparse as sp
 
 
+DIRICHLET, NEUMANN = "dirichlet", "neumann"
+
+
 class Topology:
-    def __init__(self, coords: np.ndarray, tets: np.ndarray):
+    def __init__(self, coords: np.ndarray, tets: np.ndarray, bc: str = DIRICHLET):
+        if bc not in (DIRICHLET, NEUMANN):
+            raise ValueError(f"unknown boundary condition {bc!r}")
+        self.bc = bc
         self.coords = np.asarray(coords, dtype=np.float64)
         self.tets = np.sort(np.asarray(tets, dtype=np.int64), axis=1)
         nv = self.coords.shape[0]
@@ -50,8 +63,13 @@ class Topology:
         bpairs = np.concatenate([bfaces[:, [0, 1]], bfaces[:, [1, 2]], bfaces[:, [0, 2]]])
         bkeys = np.unique(bpairs[:, 0] * nv + bpairs[:, 1])
         self.boundary_edge = np.isin(ekey, bkeys)
-        self.interior_edges = np.flatnonzero(~self.boundary_edge)
-        self.interior_vertices = np.flatnonzero(~self.boundary_vertex)
+        # free degrees of freedom ("interior" in the Dirichlet sense)
+        if bc == DIRICHLET:
+            self.interior_edges = np.flatnonzero(~self.boundary_edge)
+            self.interior_vertices = np.flatnonzero(~self.boundary_vertex)
+        else:
+            self.interior_edges = np.arange(self.n_edges)
+            self.interior_vertices = np.arange(1, nv)   # vertex 0 is the gauge vertex
         self._ekey_sorted = ekey  # sorted ascending by construction
 
     def edge_index(self, a, b):

@@ -93,6 +93,8 @@ class Problem:
     Nt: int
     pt: int
     meta: dict = field(default_factory=dict)
+    # "dirichlet" (u x n = 0) or "neumann" (nu curl u x n = 0)
+    bc: str = "dirichlet"
 
     @property
     def fine(self) -> SpaceLevel:
