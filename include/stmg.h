@@ -21,8 +21,14 @@
  *   (tail, head). The edge DOF is the line integral of the field from tail to
  *   head. The same rule numbers the edges of every coarse mesh.
  * Boundary: a face that belongs to exactly one tetrahedron is a boundary face;
- *   its edges and vertices are boundary DOFs, eliminated by the homogeneous
- *   Dirichlet condition u x n = 0 (section 3).
+ *   its edges and vertices are boundary DOFs. Section 3 allows two homogeneous
+ *   conditions (stmg_problem.bc): Dirichlet, u x n = 0, eliminates them;
+ *   Neumann, mu^{-1} curl u x n = 0, is natural and keeps every edge as a
+ *   DOF. Under Neumann the nodal space of the correction (eq. (8)) leaves out
+ *   the mesh's vertex 0 as a gauge: G maps constants to zero, so the other
+ *   vertices' gradients span the same space and K_n stays SPD (the mesh must
+ *   be connected). "Interior" below means "not eliminated": every edge under
+ *   Neumann.
  * Vectors at the ABI (device pointers, FP64, caller-owned, contiguous):
  *   full layout     [Nt][pt+1][n_edges]   all edges of the finest mesh;
  *                   boundary entries of inputs are ignored, of outputs are 0.
@@ -62,6 +68,10 @@ enum {
 };
 
 enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
+enum { STMG_BC_DIRICHLET = 0, STMG_BC_NEUMANN = 1 };
+/* Nodal solve of the auxiliary correction (eq. (8)): K_n^{-1} applied
+ * exactly with its Cholesky factor, as the analysis of section 4.1 assumes. */
+enum { STMG_NODAL_EXACT = 0 };
 /* Smoother sequences (section 4) of the steps S (damped block Jacobi,
  * eq. (2)) and A (nodal auxiliary correction, eq. (8)). A name reads like a
  * product of matrices, right to left: before the coarse-grid correction SA
@@ -105,6 +115,7 @@ typedef struct {
   double T;                      /* > 0 */
   int32_t Nt;                    /* power of two */
   int32_t pt;                    /* 0 or 1 */
+  int32_t bc;                    /* STMG_BC_DIRICHLET (0) or STMG_BC_NEUMANN (section 3) */
 } stmg_problem;
 
 typedef struct {
@@ -129,6 +140,7 @@ typedef struct {
   int32_t gemm_splitk;           /* solve K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
   int32_t device_factor;         /* numeric factorisation: -1 (default) on the GPU when the finest slab
                                     factor has >= 1e6 entries, else on the host; 1 GPU; 0 host */
+  int32_t nodal;                 /* STMG_NODAL_EXACT (the only value accepted) */
 } stmg_options;
 
 typedef struct {
@@ -203,6 +215,14 @@ int stmg_load(stmg_handle *h, const double *rhs_dev, const double *u0_dev,
               const double *x0_dev, double *bnorm);
 int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host);
 int stmg_store(stmg_handle *h, double *x_dev);
+
+/* One iteration on caller data, for benchmarks: x <- one V-cycle (section
+ * 2.1; in the precision form one refinement step: FP32 V-cycle on the FP64
+ * residual, FP64 update) applied to the iterate x for the right-hand side
+ * rhs, both device pointers in full layout; x is read and overwritten (its
+ * boundary entries become 0). Enqueued on the handle's stream without
+ * synchronising; replaces the handle's loaded right-hand side and iterate. */
+int stmg_vcycle(stmg_handle *h, const double *rhs_dev, double *x_dev);
 
 /* Convergence rate by power iteration (section 5.1, determining the
  * convergence rates and lambda_crit): V-cycles with a zero right-hand side,
@@ -317,6 +337,15 @@ int stmg_server_wait(stmg_server *s, uint64_t ticket, double timeout_s);
 int stmg_server_stats(stmg_server *s, stmg_server_stats_t *stats);
 /* Stops the threads, waits for in-flight device work and frees everything. */
 void stmg_server_destroy(stmg_server *s);
+
+/* Failure injection for tests of the error paths. Arms the k-th allocation
+ * the library makes from now on (k >= 1; device buffers and temporaries,
+ * and the host arrays of topology, assembly, ordering and factorisation) to
+ * fail as if memory were exhausted: the call that reaches it returns
+ * STMG_ENOMEM after releasing everything it had allocated. k <= 0 disarms.
+ * Returns the number of allocations counted since the previous call and
+ * restarts the count. Process-wide; concurrent setups share the count. */
+int64_t stmg_debug_fail_alloc(int64_t k);
 
 /* Host copy of a level's factor: which = 0 slab block (complex for pt = 1:
  * values interleaved re, im), 1 nodal matrix K_n. host_only handles return

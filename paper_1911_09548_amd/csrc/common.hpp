@@ -25,6 +25,11 @@ struct StmgError : std::runtime_error {
     if (!(cond)) ::stmg::fail(code, msg); \
   } while (0)
 
+// Allocation point for failure injection (stmg_debug_fail_alloc): counts
+// the library's device buffers and large host arrays and throws STMG_ENOMEM
+// at the armed one, before the allocation is made.
+void alloc_point(const char *what);
+
 // Compressed sparse rows with 64-bit row pointers.
 struct Csr {
   int32_t n_rows = 0, n_cols = 0;

@@ -142,6 +142,7 @@ void factor_layout(const Symbolic &S, std::vector<int64_t> &panel_off) {
 
 template <typename T>
 void factor_host(const Symbolic &S, const Csr &A, const std::vector<T> &vals, HostFactor<T> &Fo) {
+  alloc_point("host factor panels");
   STMG_REQUIRE((int64_t)vals.size() == A.nnz(), STMG_EINVAL, "factor: value count mismatch");
   Fo.sym = &S;
   factor_layout(S, Fo.panel_off);

@@ -8,6 +8,7 @@
 namespace stmg {
 
 NdTree nested_dissection(const Topo &T, int32_t leaf_size) {
+  alloc_point("nested-dissection tree");
   if (leaf_size < 1) leaf_size = 8;
   const int32_t nv = T.nv;
   // vertex adjacency from the edge list
@@ -127,6 +128,7 @@ std::vector<int32_t> vertex_nodes(const Topo &T, const NdTree &nd) {
 }
 
 Symbolic symbolic_from_tree(const NdTree &nd, const std::vector<int32_t> &dof_node, const Csr &A) {
+  alloc_point("symbolic factor");
   Symbolic S;
   const int32_t n = (int32_t)dof_node.size();
   S.n = n;

@@ -6,15 +6,25 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <new>
 #include <numeric>
 #include <cstring>
 
 using namespace stmg;
 
+namespace stmg {
+void alloc_point(const char *what);
+}
+
 namespace {
 
 thread_local std::string g_err;
+
+// Failure injection (stmg_debug_fail_alloc): allocation points counted
+// since the last arming; the armed one (1-based; 0 = off) throws.
+std::atomic<int64_t> g_alloc_count{0};
+std::atomic<int64_t> g_alloc_fail_at{0};
 
 template <class F>
 int guard(F &&fn) {
@@ -44,6 +54,7 @@ void hip_check(hipError_t e, const char *what) {
 // requests' work; other handles use hipMalloc.
 template <typename T>
 T *dev_alloc(stmg_handle *h, size_t count) {
+  alloc_point("device buffer");
   if (count == 0) count = 1;
   void *p = nullptr;
   if (h->stream_ordered)
@@ -78,6 +89,7 @@ struct DevTemp {
   stmg_handle *h;
   void *p = nullptr;
   DevTemp(stmg_handle *h_, size_t bytes) : h(h_) {
+    alloc_point("device setup temporary");
     if (bytes == 0) bytes = 16;
     if (h->stream_ordered)
       hip_check(hipMallocAsync(&p, bytes, h->stream), "hipMallocAsync");
@@ -472,6 +484,7 @@ void residual_tiles(MeshData &md) {
 // entry, the mask of the group's rows coupled to it with their M and K
 // entries (M and K share one pattern).
 void residual_groups(MeshData &md) {
+  alloc_point("residual row groups");
   const Csr &M = md.Mp, &K = md.Kp;
   const int32_t n = M.n_rows, ng = (n + RES_GROUP - 1) / RES_GROUP;
   md.gptr.assign(ng + 1, 0);
@@ -1189,6 +1202,18 @@ void prof_collect(stmg_handle *h) {
 }
 }  // namespace
 
+namespace stmg {
+void alloc_point(const char *what) {
+  const int64_t k = ++g_alloc_count;
+  const int64_t at = g_alloc_fail_at.load();
+  if (at > 0 && k == at) {
+    char msg[128];
+    snprintf(msg, sizeof msg, "injected allocation failure at allocation %lld (%s)", (long long)k, what);
+    fail(STMG_ENOMEM, msg);
+  }
+}
+}  // namespace stmg
+
 // ============================================================ setup phases
 // Host phase: validation, topology, FP64 assembly, hierarchy (eq. (3)),
 // orderings, symbolic and numeric factorisations. No HIP calls; safe to run
@@ -1198,6 +1223,8 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   STMG_REQUIRE(prob->Nt >= 1 && (prob->Nt & (prob->Nt - 1)) == 0, STMG_EINVAL, "Nt must be a power of two");
   STMG_REQUIRE(prob->pt == 0 || prob->pt == 1, STMG_EINVAL, "pt must be 0 or 1");
   STMG_REQUIRE(prob->T > 0 && std::isfinite(prob->T), STMG_EINVAL, "T must be > 0");
+  STMG_REQUIRE(prob->bc == STMG_BC_DIRICHLET || prob->bc == STMG_BC_NEUMANN, STMG_EINVAL,
+               "bc must be STMG_BC_DIRICHLET or STMG_BC_NEUMANN");
   const double t0 = wall_time();
   std::unique_ptr<stmg_handle> h(new stmg_handle());
   if (opt)
@@ -1208,6 +1235,8 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   STMG_REQUIRE(smoother_sequence(h->opt.smoother) != nullptr, STMG_EINVAL, "unknown smoother sequence");
   STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
                "unknown precision form");
+  STMG_REQUIRE(h->opt.nodal == STMG_NODAL_EXACT, STMG_EINVAL,
+               "nodal must be STMG_NODAL_EXACT (the nodal matrix is factored exactly)");
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
   STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                "gemm_rows must be 0, 32 or 64");
@@ -1425,6 +1454,7 @@ void stmg_default_options(stmg_options *o) {
   o->factor_transpose = -1;
   o->gemm_splitk = 0;
   o->device_factor = -1;
+  o->nodal = STMG_NODAL_EXACT;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -1615,6 +1645,40 @@ int stmg_store(stmg_handle *h, double *x_dev) {
     launch_internal_to_abi(op.ne(0), h->levels[0].N, h->q, E, md.d_map_abi, h->levels[0].x, x_dev, h->stream);
     check_launch();
   });
+}
+
+int stmg_vcycle(stmg_handle *h, const double *rhs_dev, double *x_dev) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(rhs_dev && x_dev, STMG_EINVAL, "null argument");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    MeshData &md = op.mesh(0);
+    const int32_t ne = op.ne(0), E = md.S->topo.ne;
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, rhs_dev, L.b, h->stream);
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, x_dev, L.x, h->stream);
+    if (h->opt.precision == STMG_FP32_REFINED) {
+      // the refinement step starts from the FP64 residual of the iterate
+      op.residual(0, L.x, L.b, L.w, RES_OUT_R, nullptr);
+      OpsT<float> o32{h, h->stream};
+      const int64_t n = (int64_t)ne * op.W(0);
+      launch_to_float(n, L.w, L.b32, h->stream);
+      launch_fill<float>(L.x32, n, 0.0, h->stream);
+      o32.vcycle(0, L.x32, L.b32);
+      launch_add_float(n, L.x32, L.x, h->stream);
+    } else {
+      op.vcycle(0, L.x, L.b);
+    }
+    launch_fill(x_dev, (int64_t)E * op.W(0), 0.0, h->stream);
+    launch_internal_to_abi(ne, L.N, h->q, E, md.d_map_abi, L.x, x_dev, h->stream);
+    check_launch();
+  });
+}
+
+int64_t stmg_debug_fail_alloc(int64_t k) {
+  const int64_t n = g_alloc_count.exchange(0);
+  g_alloc_fail_at.store(k > 0 ? k : 0);
+  return n;
 }
 
 int stmg_solve(stmg_handle *h, const double *rhs_dev, const double *u0_dev, const double *x0_dev,

@@ -36,6 +36,7 @@ Csr csr_transpose(const Csr &A) {
 }
 
 Csr csr_multiply(const Csr &A, const Csr &B) {
+  alloc_point("sparse product");
   STMG_REQUIRE(A.n_cols == B.n_rows, STMG_EINVAL, "csr_multiply: shape mismatch");
   Csr C;
   C.n_rows = A.n_rows;
@@ -130,7 +131,8 @@ double csr_get(const Csr &A, int32_t i, int32_t j) {
 }
 
 // ---------------------------------------------------------------- topology
-void Topo::build(int32_t n_vertices, const double *xyz, int32_t n_tets, const int32_t *t) {
+void Topo::build(int32_t n_vertices, const double *xyz, int32_t n_tets, const int32_t *t, int32_t bc) {
+  alloc_point("mesh topology");
   nv = n_vertices;
   nt = n_tets;
   STMG_REQUIRE(nv > 0 && nt > 0 && xyz && t, STMG_EINVAL, "empty mesh");
@@ -193,13 +195,14 @@ void Topo::build(int32_t n_vertices, const double *xyz, int32_t n_tets, const in
   int_verts.clear();
   edge_to_int.assign(ne, -1);
   vert_to_int.assign(nv, -1);
+  const bool neumann = bc == STMG_BC_NEUMANN;
   for (int32_t i = 0; i < ne; ++i)
-    if (!bnd_edge[i]) {
+    if (neumann || !bnd_edge[i]) {
       edge_to_int[i] = (int32_t)int_edges.size();
       int_edges.push_back(i);
     }
   for (int32_t i = 0; i < nv; ++i)
-    if (!bnd_vert[i]) {
+    if (neumann ? i > 0 : !bnd_vert[i]) {
       vert_to_int[i] = (int32_t)int_verts.size();
       int_verts.push_back(i);
     }
@@ -294,6 +297,7 @@ inline int64_t csr_find(const Csr &A, int32_t i, int32_t j) {
 }
 
 void assemble_fine(const Topo &T, const double *sigma, const double *nu, Csr &M, Csr &K) {
+  alloc_point("edge matrices");
   M = edge_pattern(T);
   K = M;
   for (int32_t e = 0; e < T.nt; ++e) {
@@ -348,6 +352,7 @@ Csr interior_gradient(const Topo &T) {
 // with l = 1 at a coinciding coarse vertex and 1/2 at both ends of the coarse
 // edge whose midpoint the fine vertex is.
 Csr edge_prolongation(const Topo &F, const Topo &C, const int32_t *vparent) {
+  alloc_point("edge prolongation");
   Csr P;
   P.n_rows = F.n_int_edges();
   P.n_cols = C.n_int_edges();
@@ -440,7 +445,7 @@ std::vector<SpaceLevel> build_space_levels(const stmg_problem &prob) {
   for (int32_t j = 0; j < prob.n_meshes; ++j) {
     const stmg_mesh &m = prob.meshes[j];
     SpaceLevel &S = L[j];
-    S.topo.build(m.n_vertices, m.coords, m.n_tets, m.tets);
+    S.topo.build(m.n_vertices, m.coords, m.n_tets, m.tets, prob.bc);
     tet_longest_edges(S.topo, S.h);
     if (j == 0) {
       STMG_REQUIRE(prob.sigma && prob.nu, STMG_EINVAL, "sigma/nu missing");

@@ -20,7 +20,10 @@ struct Topo {
   std::vector<int32_t> edge_to_int, vert_to_int; // -1 on the boundary
   std::vector<int64_t> edge_key;   // tail*nv + head, ascending (for lookup)
 
-  void build(int32_t n_vertices, const double *xyz, int32_t n_tets, const int32_t *t);
+  // bc: STMG_BC_DIRICHLET eliminates boundary edges and vertices;
+  // STMG_BC_NEUMANN keeps every edge and leaves vertex 0 out of the nodal
+  // space (gauge of the constants, which G maps to zero).
+  void build(int32_t n_vertices, const double *xyz, int32_t n_tets, const int32_t *t, int32_t bc);
   int32_t find_edge(int32_t a, int32_t b) const;  // -1 if absent
   int32_t n_int_edges() const { return (int32_t)int_edges.size(); }
   int32_t n_int_verts() const { return (int32_t)int_verts.size(); }

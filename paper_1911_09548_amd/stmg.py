@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libstmg.so")
 
 STMG_OK, STMG_EINVAL, STMG_ENOMEM, STMG_ENOTCONV, STMG_ENUMERIC, STMG_EHIP, STMG_EAGAIN, STMG_ENOSYS = range(8)
 FP64, FP32_REFINED = 0, 1
+BC_DIRICHLET, BC_NEUMANN = 0, 1
+NODAL_EXACT = 0
+BCS = {"dirichlet": BC_DIRICHLET, "neumann": BC_NEUMANN}
 SMOOTH_SAS, SMOOTH_S_ONLY, SMOOTH_SA, SMOOTH_AS, SMOOTH_SSA, SMOOTH_ASS, SMOOTH_SSAS, SMOOTH_SSASS = range(8)
 SMOOTHERS = {"SAS": SMOOTH_SAS, "SS": SMOOTH_S_ONLY, "SA": SMOOTH_SA, "AS": SMOOTH_AS, "SSA": SMOOTH_SSA,
              "ASS": SMOOTH_ASS, "SSAS": SMOOTH_SSAS, "SSASS": SMOOTH_SSASS}
@@ -39,7 +42,7 @@ class _Mesh(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("n_meshes", C.c_int32), ("meshes", C.POINTER(_Mesh)),
                 ("sigma", C.POINTER(C.c_double)), ("nu", C.POINTER(C.c_double)),
-                ("T", C.c_double), ("Nt", C.c_int32), ("pt", C.c_int32)]
+                ("T", C.c_double), ("Nt", C.c_int32), ("pt", C.c_int32), ("bc", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -48,7 +51,7 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("host_only", C.c_int32), ("stream_chunk", C.c_int32), ("row_schedule", C.c_int32),
                 ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32), ("factor_transpose", C.c_int32),
-                ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32)]
+                ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32), ("nodal", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -123,17 +126,27 @@ def lib():
         L.stmg_server_destroy.argtypes = [vp]
         L.stmg_profile.argtypes = [vp, ip]
         L.stmg_set_stream_tuning.argtypes = [vp, ip, ip]
+        L.stmg_vcycle.argtypes = [vp, vp, vp]
+        L.stmg_debug_fail_alloc.argtypes = [C.c_int64]
+        L.stmg_debug_fail_alloc.restype = C.c_int64
         L.stmg_power_rate.argtypes = [vp, vp, ip, C.c_double, dp, dp, C.POINTER(C.c_int32)]
         L.stmg_profile_count.argtypes = [vp, C.POINTER(C.c_int32)]
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_power_rate", "stmg_residual",
+                     "stmg_vcycle",
                      "stmg_level_apply", "stmg_export_matrix", "stmg_export_factor", "stmg_profile",
                      "stmg_profile_count", "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create",
                      "stmg_submit", "stmg_poll", "stmg_server_wait", "stmg_server_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+def debug_fail_alloc(k):
+    """Arm the k-th library allocation to fail (k <= 0 disarms); returns the
+    allocations counted since the previous call."""
+    return int(lib().stmg_debug_fail_alloc(int(k)))
 
 
 def default_options(**kw) -> Options:
@@ -185,7 +198,7 @@ def _marshal_problem(problem, keep):
     keep += [sig, nu, meshes]
     return _Problem(len(problem.levels), meshes, sig.ctypes.data_as(C.POINTER(C.c_double)),
                     nu.ctypes.data_as(C.POINTER(C.c_double)), float(problem.T), int(problem.Nt),
-                    int(problem.pt))
+                    int(problem.pt), BCS[getattr(problem, "bc", "dirichlet")])
 
 
 class Server:
@@ -358,6 +371,11 @@ class Solver:
         _check(lib().stmg_cycles(self._h, n, res.ctypes.data_as(C.POINTER(C.c_double))
                                  if want_residuals else None))
         return res[:n] if want_residuals else None
+
+    def vcycle(self, rhs, x):
+        """One V-cycle (or refinement step) on x in place (enqueued only)."""
+        _check(lib().stmg_vcycle(self._h, _ptr(rhs), _ptr(x)))
+        return x
 
     def power_rate(self, x0, max_cycles=200, underflow=1e-100):
         """Power iteration (section 5.1): V-cycles with zero right-hand side

@@ -40,6 +40,11 @@ def _host(t):
     return t.detach().cpu().numpy()
 
 
+def _neumann(prob):
+    prob.bc = "neumann"
+    return prob
+
+
 CASES = {
     # name: (problem factory, description)
     "unit_n4_N16_p1": lambda: inputs.config_unit_manufactured(4, 16, 1),
@@ -55,13 +60,20 @@ CASES = {
     # numeric factorisation on the GPU (automatic only for large factors)
     "block_n8_N32_p1_devfactor": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=14, block_hexes=4),
     "jitter_n6_N16_p0_devfactor": lambda: inputs.config_core_box(n=6, Nt=16, pt=0, seed=3, jitter=0.2),
+    # Neumann boundary condition (section 3): every edge free, gauged nodal space
+    "neumann_block_n8_N32_p1": lambda: _neumann(inputs.config_block_random(n=8, Nt=32, pt=1, seed=15,
+                                                                           block_hexes=4)),
+    "neumann_unit_n4_N16_p0": lambda: _neumann(inputs.config_unit_manufactured(4, 16, 0)),
+    "neumann_jitter_n6_N16_p1_devfactor": lambda: _neumann(inputs.config_core_box(n=6, Nt=16, pt=1, seed=4,
+                                                                                 jitter=0.2)),
 }
 OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
         "block_n8_N32_p1": dict(gemm_rows=32),
         "block_n8_N32_p1_noT_split3": dict(factor_transpose=0, gemm_splitk=3),
         "unit_n4_N16_p0_split2": dict(gemm_splitk=2),
         "block_n8_N32_p1_devfactor": dict(device_factor=1),
-        "jitter_n6_N16_p0_devfactor": dict(device_factor=1)}
+        "jitter_n6_N16_p0_devfactor": dict(device_factor=1),
+        "neumann_jitter_n6_N16_p1_devfactor": dict(device_factor=1)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
