@@ -45,7 +45,8 @@ def cpu_baseline(args):
     """Time the oracle on a bounded sample (runs in a child process, 1 thread)."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-sample",
-           "--sample-n", str(args.sample_n), "--sample-Nt", str(args.sample_Nt), "--pt", str(args.pt)]
+           "--sample-n", str(args.sample_n), "--sample-Nt", str(args.sample_Nt), "--pt", str(args.pt),
+           "--n", str(args.n), "--Nt", str(args.Nt)]
     r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
     if r.returncode != 0:
         log(r.stderr[-2000:])
@@ -53,11 +54,33 @@ def cpu_baseline(args):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def _host_description():
+    """CPU model, core count and the thread settings the oracle ran with."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    try:
+        from threadpoolctl import threadpool_info
+        threads["blas_pools"] = [{"api": d.get("internal_api"), "num_threads": d.get("num_threads")}
+                                 for d in threadpool_info()]
+    except Exception:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "threads": threads}
+
+
 def oracle_sample(args):
-    """Child: oracle V-cycles on the same material recipe at a smaller mesh."""
+    """Child: oracle V-cycles on the same material recipe at a smaller mesh,
+    then the oracle's residual (eq. (1)) on the benchmark's own inputs."""
     import numpy as np
     from paper_1911_09548_amd import inputs
-    from oracle.vcycle import SpaceTimeMultigrid
+    from oracle.vcycle import SpaceTimeMultigrid, Level
+    from oracle.hierarchy import finest_space
     prob = inputs.config_block_random(n=args.sample_n, Nt=args.sample_Nt, pt=args.pt, seed=1,
                                       block_hexes=max(1, args.sample_n // 4))
     t0 = time.perf_counter()
@@ -75,12 +98,29 @@ def oracle_sample(args):
         times.append(time.perf_counter() - t)
     t_cycle = float(np.median(times))
     dofs = ora.fine.n_e * prob.Nt * (prob.pt + 1)
-    print(json.dumps({"value": dofs / t_cycle, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-                      "sample": (f"oracle V-cycle + residual norm, median of {len(times)} cycles, "
-                                 f"{args.sample_n}^3 Kuhn mesh ({ora.fine.n_e} interior edges), "
-                                 f"N_t={prob.Nt}, p_t={prob.pt}, same block-random material recipe; "
-                                 f"setup {setup:.1f}s excluded; 1 thread (SuperLU, scipy)"),
-                      "s_per_cycle": t_cycle}))
+    out = {"value": dofs / t_cycle, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+           "sample": (f"oracle V-cycle + residual norm, median of {len(times)} cycles, "
+                      f"{args.sample_n}^3 Kuhn mesh ({ora.fine.n_e} interior edges), "
+                      f"N_t={prob.Nt}, p_t={prob.pt}, same block-random material recipe; "
+                      f"setup {setup:.1f}s excluded; 1 thread (SuperLU, scipy)"),
+           "s_per_cycle": t_cycle, "host": _host_description()}
+    if args.n > 0:
+        # the residual of the benchmark's workload itself (the full oracle
+        # V-cycle there needs the complex slab factors of every level: far
+        # beyond a bounded sample)
+        big = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
+        sp = finest_space(big)
+        lev = Level.operator_only(sp, big.pt, big.Nt, big.T / big.Nt)
+        xb = np.random.default_rng(3).standard_normal((big.Nt, big.pt + 1, sp.n_e))
+        bb = np.random.default_rng(2).standard_normal(xb.shape)
+        t = time.perf_counter()
+        lev.residual(xb, bb)
+        t_res = time.perf_counter() - t
+        dofs_big = sp.n_e * big.Nt * (big.pt + 1)
+        out["same_inputs"] = {"workload": f"{args.n}^3 x 6 Kuhn tets, N_t={big.Nt}, p_t={big.pt} (the GPU line's)",
+                              "residual_s": t_res, "residual_dof_per_s": dofs_big / t_res,
+                              "note": "one space-time residual b - L x (eq. (1)), 1 thread"}
+    print(json.dumps(out))
 
 
 def serving_bench(args):
@@ -287,6 +327,47 @@ def rate_sweep(args):
                                      "rows": rows, "smoother_orders": orders}}), flush=True)
 
 
+TWO_LAMBDA_LAMBDAS = (1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625, 0.01)
+TWO_LAMBDA_NU2 = (1.0, 1e1, 1e2, 1e3, 1e4, 1e5, 1e6)
+
+
+def two_lambda(args, lambdas=TWO_LAMBDA_LAMBDAS, nu2s=TWO_LAMBDA_NU2):
+    """The "Two lambda" experiment (section 5.2, Table 2) on Kuhn meshes: the
+    cube's halves carry nu = 1 and nu = nu2 (sigma = 1, Neumann boundary), so
+    the smaller anisotropy lambda = tau / h_T^2 is set by tau alone while nu2
+    raises the other half's. "Full" method: two meshes, coarsened in space
+    and time on the top level (lambda_crit = 0). The rate is the largest
+    per-cycle reduction factor of the power iteration over at most
+    args.two_lambda_cycles cycles from a start uniform in [0, 1] (seed 7).
+    Returns the table as a dict."""
+    import numpy as np
+    import torch
+    from paper_1911_09548_amd import inputs, stmg
+
+    n, Nt, cycles = args.sweep_n, args.sweep_Nt, args.two_lambda_cycles
+    h_T = np.sqrt(3.0) / n   # longest edge of a Kuhn tetrahedron
+    rows = []
+    for nu2 in nu2s:
+        row = {"nu2": nu2, "rates": {}, "ms_per_cycle": {}}
+        for lam in lambdas:
+            T = Nt * lam * h_T ** 2
+            prob = inputs.config_two_lambda(n, Nt, 1, T, nu2)
+            s = stmg.Solver(prob, lambda_crit=0.0)
+            got = s.level_info(0).lambda_
+            assert abs(got - lam) <= 1e-9 * lam, (got, lam)
+            x0 = torch.from_numpy(np.random.default_rng(7).uniform(0.0, 1.0, (Nt, 2, s.n_edges))).cuda()
+            t0 = time.perf_counter()
+            rate, rates = s.power_rate(x0, max_cycles=cycles)
+            row["rates"][f"{lam:g}"] = rate
+            row["ms_per_cycle"][f"{lam:g}"] = 1e3 * (time.perf_counter() - t0) / max(1, len(rates))
+            s.close()
+        rows.append(row)
+        log(f"[two-lambda] nu2={nu2:g}: " + ", ".join(f"{k}: {v:.3f}" for k, v in row["rates"].items()))
+    return {"mesh": f"{n}^3 x 6 Kuhn tets (two meshes), halves x < 1/2 (nu = 1) and x > 1/2 (nu = nu2), "
+                    "sigma = 1, Neumann boundary", "Nt": Nt, "pt": 1, "method": "Full (lambda_crit = 0)",
+            "cycles": cycles, "start": "uniform [0, 1], seed 7", "rows": rows}
+
+
 def core_box(args):
     """The unstructured high-contrast case (jittered Kuhn mesh, conducting
     core box [0.3, 0.7]^3 with sigma = 1e4 and nu = 1e-3 inside, sigma = 1e-2
@@ -361,6 +442,11 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=16)
     ap.add_argument("--sweep-Nt", type=int, default=64)
     ap.add_argument("--sweep-cycles", type=int, default=60)
+    ap.add_argument("--two-lambda", action="store_true",
+                    help="only the full Two-lambda table (section 5.2): 7 values of nu2 x 8 of lambda")
+    ap.add_argument("--two-lambda-cycles", type=int, default=100)
+    ap.add_argument("--no-two-lambda", action="store_true",
+                    help="skip the Two-lambda subset of the default run")
     ap.add_argument("--core-box", type=int, default=0, metavar="N",
                     help="only the jittered high-contrast core-box case on an N^3 mesh")
     ap.add_argument("--core-box-Nt", type=int, default=128)
@@ -382,6 +468,9 @@ def main():
 
     if args.rate_sweep:
         rate_sweep(args)
+        return
+    if args.two_lambda:
+        print(json.dumps({"two_lambda": two_lambda(args)}), flush=True)
         return
     if args.core_box > 0:
         core_box(args)
@@ -443,8 +532,18 @@ def main():
     for k in kernels:
         log(f"[bench]   {k['kernel']:28s} {k['ms'] / args.steps:8.2f} ms/step {k['launches'] // args.steps:5d} launches/step "
             f"{k['flops'] / (k['ms'] * 1e-3) / 1e12:7.2f} TFLOP/s {k['bytes'] / (k['ms'] * 1e-3) / 1e9:8.1f} GB/s")
-    top = kernels[0]
-    avg_s = top["ms"] * 1e-3 / top["launches"]
+    # a supernode GEMM is timed together with its split-K reduce (named
+    # after the GEMM's shape); the dominant kernel has the largest such total
+    by_name = {k["kernel"]: k for k in kernels}
+
+    def combined_ms(k):
+        if k["kernel"].startswith("k_sn_gemm"):
+            red = by_name.get(k["kernel"].replace("k_sn_gemm", "k_sn_reduce"))
+            return k["ms"] + (red["ms"] if red else 0.0)
+        return k["ms"]
+
+    top = max((k for k in kernels if not k["kernel"].startswith("k_sn_reduce")), key=combined_ms)
+    avg_s = combined_ms(top) * 1e-3 / top["launches"]
     if top["kernel"].startswith("k_sn_gemm"):
         achieved = top["flops"] / top["launches"] / avg_s / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -454,7 +553,14 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     roof["traffic"] = recorded_traffic(top["kernel"])
+    red = by_name.get(top["kernel"].replace("k_sn_gemm", "k_sn_reduce"))
     roof.update({"kernel": top["kernel"], "avg_launch_us": avg_s * 1e6, "launches": top["launches"],
+                 "gemm_avg_launch_us": top["ms"] * 1e3 / top["launches"],
+                 "reduce_us_per_launch": (red["ms"] * 1e3 / top["launches"]) if red else 0.0,
+                 "flops_per_launch": top["flops"] / top["launches"],
+                 "work_count": "8 flops per structural nonzero of L and complex right-hand side",
+                 "nnz_L_struct_level0": levels[0].factor_nnz_slab_struct,
+                 "nnz_L_stored_level0": levels[0].factor_nnz_slab,
                  "profiled_ms_per_step": ms_prof})
     # the HBM-bound residual (largest total time among its shapes), against HBM peak
     res = max((k for k in kernels if k["kernel"].startswith("k_residual")), key=lambda k: k["ms"], default=None)
@@ -471,9 +577,10 @@ def main():
                   "gbs": k["bytes"] / (k["ms"] * 1e-3) / 1e9} for k in kernels[:24]]
 
     extra = {}
+    x64 = None
     if not args.no_solve:
         t = time.perf_counter()
-        _, rep = solver.solve(rhs)
+        x64, rep = solver.solve(rhs)
         torch.cuda.synchronize()
         extra = {"time_to_1e-8_s": time.perf_counter() - t, "cycles_to_1e-8": rep["cycles"],
                  "final_rel_res": rep["rel_res"]}
@@ -505,6 +612,10 @@ def main():
         prec = {"form": "fp32 smoother + fp64 refinement", "value": dofs / (ms32 * 1e-3),
                 "ms_per_step": ms32, "time_to_1e-8_s": tts32, "cycles_to_1e-8": rep32["cycles"],
                 "final_rel_res": rep32["rel_res"], "setup_s": setup32}
+        if x64 is not None:
+            # distance to the FP64 form's solution of the same system (both
+            # solved to 1e-8; final_rel_res is already the FP64 residual)
+            prec["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
         log(f"[bench] precision form: {ms32:.2f} ms per iteration, 1e-8 in {rep32['cycles']} cycles "
             f"({tts32:.2f}s)")
         s32.close()
@@ -529,6 +640,9 @@ def main():
     if not args.no_serving:
         torch.cuda.empty_cache()
         out["serving_form"] = serving_bench(args)
+    if not args.no_two_lambda:
+        torch.cuda.empty_cache()
+        out["two_lambda"] = two_lambda(args, lambdas=(1.0, 0.125, 0.015625), nu2s=(1.0, 1e3, 1e6))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         cb = cpu_baseline(args)

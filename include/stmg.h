@@ -166,10 +166,14 @@ typedef struct {
   int32_t n_e;                   /* interior edges of that mesh */
   int32_t n_v;                   /* interior vertices */
   int64_t nnz_pattern;           /* nonzeros of the shared M/K pattern */
-  int64_t factor_nnz_slab;       /* entries of the slab-block factor L (lower incl. diag) */
-  int64_t factor_nnz_nodal;      /* entries of the nodal factor */
+  int64_t factor_nnz_slab;       /* entries of the slab-block factor L as stored (lower incl. diag,
+                                    dense supernode blocks) */
+  int64_t factor_nnz_nodal;      /* the same for the nodal factor */
   int32_t n_supernodes_slab;
   double lambda;                 /* eq. (3) anisotropy of this level (its tau, its mesh) */
+  int64_t factor_nnz_slab_struct;  /* structural nonzeros of the slab factor L (column counts of the
+                                      elimination tree; the zeros of dense supernode blocks excluded) */
+  int64_t factor_nnz_nodal_struct; /* the same for the nodal factor */
 } stmg_level_info_t;
 
 typedef struct stmg_handle stmg_handle;

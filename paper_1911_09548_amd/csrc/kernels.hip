@@ -1529,21 +1529,24 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
   const int32_t n_rs = (int32_t)(tiles * nsplit);  // row tiles x K segments
   const unsigned grid = (unsigned)(((n_rs + 7) / 8) * 8 * (int64_t)ct);
   const int dir_k = (DIR == 1 && f.panel_t) ? 2 : DIR;
-  // algorithmic work: one multiply-add per factor entry and right-hand side
-  // (8 flops complex, 2 real); traffic: the factor panels once, the
-  // right-hand-side rows in and out once
+  // algorithmic work: one multiply-add per structural nonzero of L and
+  // right-hand side (8 flops complex, 2 real; the zeros that the dense
+  // supernode blocks store are not counted); traffic: those factor entries
+  // once, the right-hand-side rows in and out once
   const double scal = (double)sizeof(T);
   // the GEMM launch and the split-K reduce are timed separately; the GEMM
   // carries the launch's algorithmic work (the whole K range), the reduce
-  // the partial tiles it reads and the rows it writes
-  char name[96], rname[64];
+  // (named after its GEMM's shape) the partial tiles it reads and the rows
+  // it writes
+  char name[96], rname[96];
   if (prof) {
-    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>", Scalar<T>::name, bmv, bn,
-             DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd"));
-    snprintf(rname, sizeof rname, "k_sn_reduce<%s,%d,%s>", Scalar<T>::name, bmv, DIR == 0 ? "fwd" : "bwd");
+    const char *dn = DIR == 0 ? "fwd" : (dir_k == 2 ? "bwdT" : "bwd");
+    snprintf(name, sizeof name, "k_sn_gemm<%s,%d,%d,%s>", Scalar<T>::name, bmv, bn, dn);
+    snprintf(rname, sizeof rname, "k_sn_reduce<%s,%d,%d,%s>", Scalar<T>::name, bmv, bn, dn);
     prof->begin(s);
   }
-  const double flops = (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz * nc, bytes = scal * (L.nnz + 2.0 * L.rows * nc);
+  const double flops = (Scalar<T>::cpx ? 8.0 : 2.0) * L.nnz_struct * nc,
+               bytes = scal * (L.nnz_struct + 2.0 * L.rows * nc);
   const double rbytes = scal * ((double)nsplit + 1.0) * (double)L.rows * nc;
 #define SN_CASE(BMV, BNV)                                                                                  \
   if (bmv == BMV && bn == BNV) {                                                                           \

@@ -173,7 +173,8 @@ struct SolvePlan {
   const int64_t *src;            // device U rows
   // one GEMM launch per height and direction: host descriptors, device tasks
   struct Launch {
-    double nnz;                  // factor entries of its supernodes (w(w+1)/2 + r w each)
+    double nnz;                  // factor entries of its supernodes as stored (w(w+1)/2 + r w each)
+    double nnz_struct;           // structural nonzeros of L in its supernodes' columns (work accounting)
     int32_t n_tasks;             // supernodes
     int32_t n_tiles, n_tiles32;  // 64-row and 32-row tiles
     int64_t rows;                // output rows over all supernodes

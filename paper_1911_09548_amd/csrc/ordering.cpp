@@ -127,6 +127,44 @@ std::vector<int32_t> vertex_nodes(const Topo &T, const NdTree &nd) {
   return out;
 }
 
+// Structural nonzeros per column of the Cholesky factor of A(perm, perm)
+// (diagonal included), without the zeros that dense supernode blocks hold:
+// the elimination tree (Liu's algorithm with path compression), then the
+// row subtrees: L(i, j) != 0 exactly for the etree nodes j on the paths from
+// the nonzeros A(i, k), k < i, up to i.
+static std::vector<int64_t> column_counts(const Symbolic &S, const Csr &A) {
+  const int32_t n = S.n;
+  std::vector<int32_t> parent(n, -1), anc(n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t o = S.perm[i];
+    for (int64_t k = A.ptr[o]; k < A.ptr[o + 1]; ++k) {
+      int32_t j = S.iperm[A.col[k]];
+      while (j >= 0 && j < i) {
+        const int32_t next = anc[j];
+        anc[j] = i;
+        if (next < 0) parent[j] = i;
+        j = next;
+      }
+    }
+  }
+  std::vector<int64_t> cc(n, 1);
+  std::vector<int32_t> mark(n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    mark[i] = i;
+    const int32_t o = S.perm[i];
+    for (int64_t k = A.ptr[o]; k < A.ptr[o + 1]; ++k) {
+      int32_t j = S.iperm[A.col[k]];
+      if (j >= i) continue;
+      while (mark[j] != i) {
+        mark[j] = i;
+        ++cc[j];
+        j = parent[j];
+      }
+    }
+  }
+  return cc;
+}
+
 Symbolic symbolic_from_tree(const NdTree &nd, const std::vector<int32_t> &dof_node, const Csr &A) {
   alloc_point("symbolic factor");
   Symbolic S;
@@ -209,6 +247,12 @@ Symbolic symbolic_from_tree(const NdTree &nd, const std::vector<int32_t> &dof_no
     S.panel_entries += (w + rr) * w;
     S.max_front = std::max(S.max_front, (int32_t)(w + rr));
     S.n_heights = std::max(S.n_heights, S.height[s] + 1);
+  }
+  const std::vector<int64_t> cc = column_counts(S, A);
+  S.sn_nnz.assign(S.ns, 0);
+  for (int32_t s = 0; s < S.ns; ++s) {
+    for (int32_t j = S.col0[s]; j < S.col0[s + 1]; ++j) S.sn_nnz[s] += cc[j];
+    S.nnz_L_struct += S.sn_nnz[s];
   }
   return S;
 }

@@ -33,7 +33,9 @@ struct Symbolic {
   std::vector<int32_t> rows;     // below-diagonal row structure R_s, ascending, new numbering
   std::vector<int32_t> height;   // [ns] 0 for leaves, 1 + max over children
   int32_t n_heights = 0;
-  int64_t nnz_L = 0;             // sum w(w+1)/2 + r w
+  int64_t nnz_L = 0;             // sum w(w+1)/2 + r w (dense supernode blocks, as stored)
+  int64_t nnz_L_struct = 0;      // structural nonzeros of L (column counts, diagonal included)
+  std::vector<int64_t> sn_nnz;   // [ns] structural nonzeros of each supernode's columns
   int64_t panel_entries = 0;     // sum (w + r) w  (dense panels as stored)
   int32_t max_front = 0;         // max w + r
 

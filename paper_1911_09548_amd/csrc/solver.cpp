@@ -191,11 +191,11 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
     size_t off64, off32, n;
     int32_t tiles64, tiles32;
     int64_t rows;
-    double nnz;
+    double nnz, nnz_struct;
     int32_t kmax;
   };
   auto make_pending = [&](int32_t hh, bool fwd) {
-    Pending p{tasks.size(), 0, 0, 0, 0, 0, 0.0, 0};
+    Pending p{tasks.size(), 0, 0, 0, 0, 0, 0.0, 0.0, 0};
     for (int32_t s : by_h[hh]) {
       const int32_t rows = fwd ? S.width(s) + S.nrows(s) : S.width(s);
       for (int32_t t = 0; t < (rows + 63) / 64; ++t) tasks.push_back({s, t});
@@ -203,6 +203,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
       p.rows += rows;
       const double w = S.width(s), r = S.nrows(s);
       p.nnz += w * (w + 1) / 2 + r * w;
+      p.nnz_struct += (double)S.sn_nnz[s];
       p.kmax = std::max(p.kmax, fwd ? S.width(s) : S.width(s) + S.nrows(s));
     }
     p.n = by_h[hh].size();
@@ -225,6 +226,7 @@ void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
   auto mk = [&](const Pending &p) {
     SolvePlan::Launch L;
     L.nnz = p.nnz;
+    L.nnz_struct = p.nnz_struct;
     L.kmax = p.kmax;
     L.n_tasks = (int32_t)p.n;
     L.n_tiles = p.tiles64;
@@ -1507,6 +1509,8 @@ int stmg_level_info(const stmg_handle *h, int32_t level, stmg_level_info_t *info
     info->factor_nnz_nodal = md.sym_v.nnz_L;
     info->n_supernodes_slab = md.sym_e.ns;
     info->lambda = L.lambda;
+    info->factor_nnz_slab_struct = md.sym_e.nnz_L_struct;
+    info->factor_nnz_nodal_struct = md.sym_v.nnz_L_struct;
   });
 }
 

@@ -242,3 +242,17 @@ def config_request(n: int, Nt: int, pt: int, seed: int, T: float = 1.0) -> Probl
     nblocks = 4 if n % 4 == 0 else 1
     sigma, nu = block_materials(n, nblocks, (1e-2, 1e4), (1e-3, 100.0), seed)
     return Problem(levels, sigma, nu, T, Nt, pt, meta={"name": f"request n={n} Nt={Nt} pt={pt}"})
+
+
+def config_two_lambda(n: int, Nt: int, pt: int, T: float, nu2: float, n_meshes: int = 2) -> Problem:
+    """Two materials with different anisotropy (the "Two lambda" case): the
+    cube's halves x < 1/2 (nu = 1) and x > 1/2 (nu = nu2 >= 1) by tet
+    centroid, sigma = 1, Neumann boundary, the n^3 Kuhn mesh and its next
+    n_meshes - 1 coarser meshes."""
+    levels = kuhn_hierarchy(n)[:n_meshes]
+    fine = levels[0]
+    cx = fine.coords[fine.tets][:, :, 0].mean(axis=1)
+    nt = fine.tets.shape[0]
+    nu = np.where(cx > 0.5, float(nu2), 1.0)
+    return Problem(levels, np.ones(nt), nu, T, Nt, pt, bc="neumann",
+                   meta={"name": f"two-lambda n={n} Nt={Nt} pt={pt} T={T} nu2={nu2}"})

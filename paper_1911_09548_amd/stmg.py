@@ -68,7 +68,8 @@ class LevelInfo(C.Structure):
     _fields_ = [("mesh", C.c_int32), ("N", C.c_int32), ("tau", C.c_double), ("n_e", C.c_int32),
                 ("n_v", C.c_int32), ("nnz_pattern", C.c_int64), ("factor_nnz_slab", C.c_int64),
                 ("factor_nnz_nodal", C.c_int64), ("n_supernodes_slab", C.c_int32),
-                ("lambda_", C.c_double)]
+                ("lambda_", C.c_double), ("factor_nnz_slab_struct", C.c_int64),
+                ("factor_nnz_nodal_struct", C.c_int64)]
 
 
 class ServerOptions(C.Structure):

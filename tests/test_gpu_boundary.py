@@ -1,0 +1,80 @@
+"""GPU checks of entry points around the solver (no oracle needed):
+
+* stmg_vcycle (one cycle on caller data) gives bitwise the iterate of one
+  cycle of the split form (stmg_load / stmg_cycles / stmg_store) from the
+  same start, in both forms, and k calls give k cycles;
+* allocation failures injected at device allocations of a setup return
+  STMG_ENOMEM and release every device buffer the setup had made: free
+  device memory returns to its level before the call, and a following setup
+  on the same process solves normally.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_09548_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_equals_split_cycles(precision):
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=8, Nt=16, pt=1, seed=21, block_hexes=4)
+    print(f"\n[case] stmg_vcycle, 8^3 x 16, precision {precision}", flush=True)
+    gpu = stmg.Solver(prob, precision=precision)
+    try:
+        rng = np.random.default_rng(4)
+        E = gpu.n_edges
+        b = _dev(rng.standard_normal((prob.Nt, 2, E)))
+        x0 = _dev(rng.standard_normal((prob.Nt, 2, E)))
+        for k in (1, 3):
+            x = x0.clone()
+            for _ in range(k):
+                gpu.vcycle(b, x)
+            gpu.load(b, None, x0)
+            gpu.cycles(k, want_residuals=False)
+            ref = gpu.store()
+            torch.cuda.synchronize()
+            assert torch.equal(x, ref), (precision, k)
+    finally:
+        gpu.close()
+
+
+def test_injected_device_allocation_failures_release_memory():
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=8, Nt=16, pt=1, seed=22, block_hexes=4)
+    print("\n[case] allocation failures, 8^3 x 16", flush=True)
+    torch.cuda.synchronize()
+    stmg.debug_fail_alloc(0)
+    ok = stmg.Solver(prob, device_factor=1)
+    n = stmg.debug_fail_alloc(0)
+    ok.close()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    # every device-phase point sits after the host phase's points; sample
+    # the whole range including the last point
+    ks = sorted(set(list(range(1, n + 1, max(1, n // 12))) + [n]))
+    for k in ks:
+        stmg.debug_fail_alloc(k)
+        with pytest.raises(stmg.StmgError) as e:
+            stmg.Solver(prob, device_factor=1)
+        assert e.value.code == stmg.STMG_ENOMEM, (k, e.value)
+        torch.cuda.synchronize()
+        free = torch.cuda.mem_get_info()[0]
+        assert free0 - free < (64 << 20), (k, free0 - free)
+    stmg.debug_fail_alloc(0)
+    gpu = stmg.Solver(prob, device_factor=1, rtol=1e-8)
+    try:
+        rng = np.random.default_rng(5)
+        b = _dev(rng.standard_normal((prob.Nt, 2, gpu.n_edges)))
+        _, rep = gpu.solve(b)
+        assert rep["rel_res"] <= 1e-8
+    finally:
+        gpu.close()

@@ -20,6 +20,16 @@ Bounds (FP64; none depends on a condition number; see tests/_parity.py):
 * V-cycle and solution: forward <= 1e-10; per-cycle residual history within
   1e-10 relative plus the roundoff level of the residual norm; the oracle's
   residual of the final iterate <= 1e-10.
+
+Forward differences of results that pass through a nodal solve (A, SAS, the
+V-cycle, the solution) keep the 1e-10 cap unless the nodal system itself
+does not allow it: the fixture solves each level's K_n with two independent
+FP64 solvers of the oracle's (SuperLU and dense Cholesky) and, where these
+two disagree by more than 1e-11, the cap is ten times their disagreement.
+Only the Neumann high-contrast case (gauged K_n with a 1e6 jump in sigma,
+condition number about 4e9, spread 1.9e-9) reaches that; its A steps are
+still held to the condition-free gradient check (1e-13) and its solve to
+the oracle residual (1e-10).
 """
 import numpy as np
 import pytest
@@ -84,8 +94,26 @@ def pair(request):
     print(f"\n[case] {request.param}", flush=True)
     gpu = stmg.Solver(prob, **OPTS.get(request.param, {}))
     ora = SpaceTimeMultigrid(prob)
+    ora.nodal_cap = max(FWD64, 10.0 * _nodal_spread(ora))
     yield request.param, prob, gpu, ora
     gpu.close()
+
+
+def _nodal_spread(ora):
+    """Largest relative difference between two independent FP64 solves of
+    the levels' K_n (the oracle's SuperLU factor and a dense Cholesky): the
+    forward accuracy the nodal systems allow at all."""
+    import scipy.linalg as sla
+    spread = 0.0
+    for lev in ora.levels:
+        Kn = lev.space.Kn
+        if lev.space.n_v == 0 or lev.space.n_v > 3000:
+            continue
+        g = np.random.default_rng(0).standard_normal((lev.space.n_v, 4))
+        y1 = lev.Kn_lu.solve(g)
+        y2 = sla.cho_solve(sla.cho_factor(Kn.toarray()), g)
+        spread = max(spread, float(np.linalg.norm(y1 - y2) / np.linalg.norm(y2)))
+    return spread if spread > 1e-11 else 0.0
 
 
 def test_hierarchy_matches(pair):
@@ -152,7 +180,7 @@ def test_smoothers(pair, op):
             s2 = _host(gpu.level_apply(l, stmg.OP_SMOOTH_S, a1, _dev(b)))
             print(f"[SAS] {name} level {l}: forward {d:.1e}")
             assert np.array_equal(got, s2), (name, l, "SAS != S(A(S)) on the GPU")
-        assert d <= FWD64, (name, op, l, d)
+        assert d <= (FWD64 if op == "S" else ora.nodal_cap), (name, op, l, d, ora.nodal_cap)
 
 
 def test_transfers(pair):
@@ -175,8 +203,8 @@ def test_vcycle(pair):
     x, b = _vec(ora, 0, 8), _vec(ora, 0, 9)
     ref = ora.vcycle(0, x, b)
     got = _host(gpu.level_apply(0, stmg.OP_VCYCLE, _dev(x), _dev(b)))
-    print(f"[vcycle] {name}: forward {fwd(got, ref):.1e}")
-    assert fwd(got, ref) <= FWD64, (name, fwd(got, ref))
+    print(f"[vcycle] {name}: forward {fwd(got, ref):.1e} (cap {ora.nodal_cap:.1e})")
+    assert fwd(got, ref) <= ora.nodal_cap, (name, fwd(got, ref))
 
 
 def test_full_solve_history_and_solution(pair):
@@ -202,7 +230,7 @@ def test_full_solve_history_and_solution(pair):
     rr = np.linalg.norm(ora.levels[0].residual(x_int, b)) / np.linalg.norm(b)
     print(f"[solve] {name}: oracle residual {rr:.2e} |x - x_oracle| {fwd(x_int, x_ref):.2e}")
     assert rr <= 1e-10, (name, rr)
-    assert fwd(x_int, x_ref) <= FWD64
+    assert fwd(x_int, x_ref) <= ora.nodal_cap
     bnd = np.ones(E, dtype=bool)
     bnd[ora.fine.ie] = False
     assert np.all(x[..., bnd] == 0.0)

@@ -8,7 +8,8 @@ two norms of iterates that agree to rounding) is compared to 1e-10 absolute,
 for the space-time hierarchy with spatial
 coarsening by eq. (3) ("Full" when lambda_crit = 0 forces it on the top
 level of a two-mesh problem) and without it ("Semi-time"), DG degrees 0 and
-1. Also checked: the stop at underflow, argument errors, and that the
+1, and the "Two lambda" case of section 5.2 (two materials, Neumann
+boundary, Full method). Also checked: the stop at underflow, argument errors, and that the
 precision form is refused.
 """
 import numpy as np
@@ -32,6 +33,12 @@ CASES = {  # name: (problem factory, library options, oracle options)
     "semi_n4_N16_p1": (lambda: _two_mesh(4, 16, 1), dict(allow_space_coarsening=0), dict(allow_space=False)),
     "full_n4_N16_p0_T8": (lambda: _two_mesh(4, 16, 0, T=8.0), dict(lambda_crit=0.0), dict(lambda_crit=0.0)),
     "block_n8_N32_p1": (lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=51, block_hexes=4), {}, {}),
+    # the "Two lambda" case (section 5.2): halves with nu = 1 and nu = 1e3,
+    # Neumann boundary, Full method, lambda = tau / h_T^2 = 2^-3 and 2^-6
+    "two_lambda_n4_N16_p1_lam2m3": (lambda: inputs.config_two_lambda(4, 16, 1, 16 * 0.125 * 3 / 16, 1e3),
+                                    dict(lambda_crit=0.0), dict(lambda_crit=0.0)),
+    "two_lambda_n8_N16_p1_lam2m6": (lambda: inputs.config_two_lambda(8, 16, 1, 16 * 2.0 ** -6 * 3 / 64, 1e6),
+                                    dict(lambda_crit=0.0), dict(lambda_crit=0.0)),
 }
 
 

@@ -294,3 +294,41 @@ def test_allocation_failure_unwinds(stmg, bc):
             stmg.Solver(prob, host_only=1)
     stmg.debug_fail_alloc(0)
     assert _rss_kib() - rss0 < 16 * 1024
+
+
+def _symbolic_nnz_bruteforce(A, perm):
+    """nnz of the Cholesky factor's lower triangle (diagonal included) of
+    A(perm, perm), by boolean elimination on a dense pattern (the stored
+    pattern: entries that cancelled to zero in a product count)."""
+    A = A.copy()
+    A.data[:] = 1.0
+    P = (A.toarray() != 0)[np.ix_(perm, perm)]
+    n = P.shape[0]
+    total = 0
+    for j in range(n):
+        rows = j + 1 + np.flatnonzero(P[j + 1:, j])
+        total += 1 + rows.size
+        P[np.ix_(rows, rows)] = True
+    return total
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_structural_factor_counts(stmg, bc):
+    """The structural nonzeros of L reported per level equal a brute-force
+    symbolic elimination of the pattern in the factor's ordering, for the
+    slab block and K_n; the stored dense-block count is never smaller."""
+    prob = inputs.config_block_random(n=4, Nt=4, pt=1, seed=3, block_hexes=2)
+    prob.bc = bc
+    lib = stmg.Solver(prob, host_only=1)
+    try:
+        li = lib.level_info(0)
+        F = lib.export_factor(0, 0)
+        M = lib.export_matrix(0, stmg.MAT_M)
+        assert li.factor_nnz_slab_struct == _symbolic_nnz_bruteforce(M, F["perm"])
+        assert li.factor_nnz_slab_struct <= li.factor_nnz_slab
+        Fn = lib.export_factor(0, 1)
+        Kn = lib.export_matrix(0, stmg.MAT_KN)
+        assert li.factor_nnz_nodal_struct == _symbolic_nnz_bruteforce(Kn, Fn["perm"])
+        assert li.factor_nnz_nodal_struct <= li.factor_nnz_nodal
+    finally:
+        lib.close()
