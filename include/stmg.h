@@ -249,6 +249,22 @@ int stmg_power_rate(stmg_handle *h, const double *x0_dev, int32_t max_cycles, do
 int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev,
                   const double *u0_dev, double *r_dev);
 
+/* stmg_residual for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, same r = b - L x from the same kernels; the
+ * internal-layout temporaries (x, b and r, n_interior_edges * Nt * (pt+1)
+ * doubles each), which stmg_residual allocates on its first call, come
+ * from a fixed device array of 64 MiB that the library holds on every GPU
+ * it runs on until the process ends. No device memory is allocated or
+ * freed and the stream is not synchronised: r is ready when the handle's
+ * stream reaches it. STMG_EINVAL if 3 * n_interior_edges * Nt * (pt+1)
+ * exceeds 8 Mi doubles, or if the current device is not the one the handle
+ * was set up on. Every call on one GPU uses that GPU's one array and leaves
+ * its contents behind (the next call overwrites all it reads): calls that
+ * overlap on one GPU, from different streams or handles, race. */
+int stmg_residual_noalloc(stmg_handle *h, const double *x_dev, const double *rhs_dev,
+                          const double *u0_dev, double *r_dev);
+
 /* Per-level operations in level layout, for parity tests:
  *   STMG_OP_RESIDUAL  out = b - L_l x                    (in = x, in2 = b)
  *   STMG_OP_SMOOTH_S  out = x + omega A_l^{-1}(b - L_l x) (eq. (2))

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <cstring>
@@ -1216,6 +1217,35 @@ void alloc_point(const char *what) {
 }
 }  // namespace stmg
 
+// ------------------------------------------------- no-allocation scratch
+// Device scratch of stmg_residual_noalloc: the internal-layout copies of x
+// and b and the residual, three vectors of n_e N q doubles each. One copy
+// of the array exists on every GPU the library runs on, for the life of the
+// process. Host code never uses the array's name as an address: each
+// device's address comes from hipGetSymbolAddress, taken once per device
+// at the first setup on it.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)8 << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on the current device (looked up once per device).
+double *scratch_address(int dev) {
+  STMG_REQUIRE(dev >= 0 && dev < MAX_DEVICES, STMG_EHIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    STMG_REQUIRE(ptr != nullptr, STMG_EHIP, "no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // ============================================================ setup phases
 // Host phase: validation, topology, FP64 assembly, hierarchy (eq. (3)),
 // orderings, symbolic and numeric factorisations. No HIP calls; safe to run
@@ -1362,6 +1392,8 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
 void setup_device_phase(stmg_handle *h, hipStream_t stream) {
   const double t0 = wall_time();
   h->stream = stream;
+  hip_check(hipGetDevice(&h->device), "hipGetDevice");
+  h->noalloc_scratch = scratch_address(h->device);
   struct RbGuard {
     stmg_handle *h;
     ~RbGuard() {
@@ -1755,6 +1787,38 @@ int stmg_residual(stmg_handle *h, const double *x_dev, const double *rhs_dev, co
     launch_internal_to_abi(ne, L.N, h->q, E, md.d_map_abi, tr, r_dev, h->stream);
     check_launch();
     hip_check(hipStreamSynchronize(h->stream), "sync");
+  });
+}
+
+int stmg_residual_noalloc(stmg_handle *h, const double *x_dev, const double *rhs_dev, const double *u0_dev,
+                          double *r_dev) {
+  return guard([&] {
+    require_device(h);
+    STMG_REQUIRE(x_dev && rhs_dev && r_dev, STMG_EINVAL, "null argument");
+    STMG_REQUIRE(h->noalloc_scratch, STMG_EHIP, "no scratch address for the handle's device");
+    int cur = -1;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    STMG_REQUIRE(cur == h->device, STMG_EINVAL, "the handle's device is not the current device");
+    Ops op{h, h->stream};
+    LevelData &L = h->levels[0];
+    MeshData &md = op.mesh(0);
+    const int32_t ne = op.ne(0), E = md.S->topo.ne;
+    const size_t n = (size_t)ne * op.W(0);
+    if (3 * n > NOALLOC_SCRATCH_DOUBLES) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "problem too large for the no-allocation residual: 3 x %zu values, limit %zu",
+               n, NOALLOC_SCRATCH_DOUBLES);
+      fail(STMG_EINVAL, msg);
+    }
+    double *tb = h->noalloc_scratch, *tx = tb + n, *tr = tx + n;
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, rhs_dev, tb, h->stream);
+    if (u0_dev)
+      launch_fold_initial(ne, L.N, h->q, md.d_ptr, md.d_col, md.d_mval, md.d_map_abi, u0_dev, tb, h->stream);
+    launch_abi_to_internal(ne, L.N, h->q, E, md.d_map_abi, x_dev, tx, h->stream);
+    op.residual(0, tx, tb, tr, RES_OUT_R, nullptr);
+    launch_fill(r_dev, (int64_t)E * op.W(0), 0.0, h->stream);
+    launch_internal_to_abi(ne, L.N, h->q, E, md.d_map_abi, tr, r_dev, h->stream);
+    check_launch();
   });
 }
 

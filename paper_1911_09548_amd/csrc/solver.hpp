@@ -143,6 +143,8 @@ struct stmg_handle {
   stmg::Profiler prof;
   int32_t cycles = 0;
   double rel_res = 0.0;
+  int device = -1;                      // HIP device current at setup
+  double *noalloc_scratch = nullptr;    // that device's copy of the no-allocation scratch array
 };
 
 namespace stmg {

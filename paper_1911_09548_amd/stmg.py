@@ -114,6 +114,7 @@ def lib():
         L.stmg_cycles.argtypes = [vp, ip, dp]
         L.stmg_store.argtypes = [vp, vp]
         L.stmg_residual.argtypes = [vp, vp, vp, vp, vp]
+        L.stmg_residual_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.stmg_level_apply.argtypes = [vp, ip, ip, vp, vp, vp]
         L.stmg_export_matrix.argtypes = [vp, ip, ip, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), vp, vp, vp]
@@ -135,7 +136,7 @@ def lib():
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_power_rate", "stmg_residual",
-                     "stmg_vcycle",
+                     "stmg_residual_noalloc", "stmg_vcycle",
                      "stmg_level_apply", "stmg_export_matrix", "stmg_export_factor", "stmg_profile",
                      "stmg_profile_count", "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create",
                      "stmg_submit", "stmg_poll", "stmg_server_wait", "stmg_server_stats"):
@@ -397,6 +398,11 @@ class Solver:
         r = self._full()
         _check(lib().stmg_residual(self._h, _ptr(x), _ptr(rhs), _ptr(u0), _ptr(r)))
         return r
+
+    def residual_noalloc(self, x, rhs, out, u0=None):
+        """r = b - L x into `out` without device allocation (enqueued only)."""
+        _check(lib().stmg_residual_noalloc(self._h, _ptr(x), _ptr(rhs), _ptr(u0), _ptr(out)))
+        return out
 
     def level_apply(self, level, op, vin, vin2=None):
         import torch
