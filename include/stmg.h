@@ -228,6 +228,18 @@ int stmg_store(stmg_handle *h, double *x_dev);
  * synchronising; replaces the handle's loaded right-hand side and iterate. */
 int stmg_vcycle(stmg_handle *h, const double *rhs_dev, double *x_dev);
 
+/* stmg_cycles for several handles at once (1 to 8, each loaded with
+ * stmg_load): n_cycles iterations of every handle, with the slab and nodal
+ * solves of each step merged over the handles into one launch per tree
+ * height (the slabs of one level of all handles solved together, each with
+ * its own factor). The handles must share N_t, p_t, the precision form and
+ * the smoother (STMG_EINVAL otherwise, or if a handle appears twice). Runs
+ * on the first handle's stream after synchronising the others' streams, and
+ * returns when done. Every handle's iterates, norms and histories are
+ * bitwise those of stmg_cycles on that handle alone. res_host (may be NULL)
+ * receives [n][n_cycles] relative residuals. */
+int stmg_cycles_batched(stmg_handle *const *hs, int32_t n, int32_t n_cycles, double *res_host);
+
 /* Convergence rate by power iteration (section 5.1, determining the
  * convergence rates and lambda_crit): V-cycles with a zero right-hand side,
  * starting from the error x0_dev (device, full layout [Nt][pt+1][n_edges];

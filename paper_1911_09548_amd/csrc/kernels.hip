@@ -10,6 +10,8 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "factor.hpp"
@@ -1231,10 +1233,10 @@ __device__ inline void children_sum(const FactorDev &f, const T *U, int s, int i
 // each target row receives the children's update rows in a fixed order. One
 // wavefront per target row.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src,
-                                                   int32_t nc, T *X, T *U) {
+__device__ __forceinline__ void fwd_asm_block(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src, int32_t nc,
+                                              T *X, T *U, int bid) {
   using R = typename Scalar<T>::R;
-  const int64_t ti = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+  const int64_t ti = (int64_t)bid * (BLOCK / 64) + (threadIdx.x >> 6);
   if (ti >= n_tgt) return;
   const int lane = threadIdx.x & 63;
   const AsmTarget t = tgt[ti];
@@ -1257,6 +1259,12 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t n_tgt, const int64_t *src,
+                                                   int32_t nc, T *X, T *U) {
+  fwd_asm_block<T>(tgt, n_tgt, src, nc, X, U, blockIdx.x);
+}
+
 // Tiles: BM rows x BN columns of the output, K in chunks of KC = 16.
 // LDS holds A as [row][k] and B as [col][k] with a row stride of KC + 1
 // scalars, which keeps the stores of both load orders and the MFMA operand
@@ -1269,10 +1277,13 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_asm(const AsmTarget *tgt, int64_t
 // With nsplit > 1 the K range is cut into nsplit segments of kseg and each
 // work item writes its partial tile to ws; k_sn_reduce adds them in order
 // and applies the epilogue.
+// One tile of the launch: bid is the block's index within its launch (its
+// position in a grouped launch less the member's first block, a multiple of
+// 8, so the XCD placement below is that of a launch of its own).
 template <typename T, int BM, int BN, int DIR>
-__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks,
-                                                   int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
-                                                   int32_t nsplit, int32_t kseg, T *ws, int32_t n_rs) {
+__device__ __forceinline__ void sn_gemm_tile(const FactorDev &f, const SolveTask *tasks, int32_t nc,
+                                             int32_t ctiles, T *X, T *Z, T *U, int32_t nsplit, int32_t kseg,
+                                             T *ws, int32_t n_rs, int bid) {
   constexpr bool CPX = Scalar<T>::cpx;
   using R = typename Scalar<T>::R;
   using ACC = typename Scalar<T>::acc_t;
@@ -1290,7 +1301,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
   // on one XCD, consecutive in its dispatch order, so they read the row
   // tile's block of P through one L2. The grid is padded to whole groups of
   // 8 row tiles; blocks past the last row tile exit.
-  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int xcd = bid & 7, idx = bid >> 3;
   const int ct = idx % ctiles, rs = (idx / ctiles) * 8 + xcd;
   if (rs >= n_rs) return;
   const int seg = rs % nsplit, rowtile = rs / nsplit;
@@ -1445,16 +1456,23 @@ __global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTa
       }
 }
 
+template <typename T, int BM, int BN, int DIR>
+__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm(FactorDev f, const SolveTask *tasks,
+                                                   int32_t nc, int32_t ctiles, T *X, T *Z, T *U,
+                                                   int32_t nsplit, int32_t kseg, T *ws, int32_t n_rs) {
+  sn_gemm_tile<T, BM, BN, DIR>(f, tasks, nc, ctiles, X, Z, U, nsplit, kseg, ws, n_rs, blockIdx.x);
+}
+
 // Sum of the split-K partial tiles in segment order, then the same epilogue
 // as the unsplit kernel (forward: Z rows and U update rows; backward: X[C_s]
 // rows). One block per (row tile, chunk of RC columns).
 template <typename T, int BM, int DIR>
-__global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks,
-                                                     int32_t nc, int32_t nsplit, const T *ws, T *X, T *Z, T *U) {
+__device__ __forceinline__ void sn_reduce_block(const FactorDev &f, const SolveTask *tasks, int32_t nc,
+                                                int32_t nsplit, const T *ws, T *X, T *Z, T *U, int bid) {
   using R = typename Scalar<T>::R;
   const int RC = nc < 64 ? nc : 64;  // columns per block
   const int cchunks = (nc + RC - 1) / RC;
-  const int rowtile = blockIdx.x / cchunks, cc = blockIdx.x % cchunks;
+  const int rowtile = bid / cchunks, cc = bid % cchunks;
   const SolveTask task = tasks[rowtile];
   const int s = task.s, rt = task.rt;
   const int c0 = f.col0[s], w = f.col0[s + 1] - c0;
@@ -1482,13 +1500,94 @@ __global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTas
   }
 }
 
+template <typename T, int BM, int DIR>
+__global__ __launch_bounds__(BLOCK) void k_sn_reduce(FactorDev f, const SolveTask *tasks,
+                                                     int32_t nc, int32_t nsplit, const T *ws, T *X, T *Z, T *U) {
+  sn_reduce_block<T, BM, DIR>(f, tasks, nc, nsplit, ws, X, Z, U, blockIdx.x);
+}
+
+// ------------------------------------------------ launches merged over solves
+// Several solves (one per member: its factor, plan and right-hand sides) at
+// the same step run as one launch: member i owns the blocks
+// [block_end[i-1], block_end[i]) and each block runs the tile code of a
+// launch of its own with its index within the member. Every output value is
+// computed by the same instructions in the same order as in a separate
+// launch, so merged and separate solves agree bitwise.
+template <typename T>
+struct SnGemmArgs {
+  FactorDev f;
+  const SolveTask *tasks;
+  T *X, *Z, *U, *ws;
+  int32_t nc, ctiles, nsplit, kseg, n_rs;
+};
+template <typename T>
+struct SnGemmGroup {
+  int32_t n;
+  int32_t block_end[SOLVE_GROUP_MAX];
+  SnGemmArgs<T> m[SOLVE_GROUP_MAX];
+};
+template <typename T>
+struct AsmArgs {
+  const AsmTarget *tgt;
+  const int64_t *src;
+  T *X, *U;
+  int64_t n_tgt;
+  int32_t nc;
+};
+template <typename T>
+struct AsmGroup {
+  int32_t n;
+  int32_t block_end[SOLVE_GROUP_MAX];
+  AsmArgs<T> m[SOLVE_GROUP_MAX];
+};
+
+// Member of the block (wave-uniform) and the block's index within it.
+__device__ inline int group_member(const int32_t *block_end, int32_t n, int &bid) {
+  int i = 0;
+  while (i + 1 < n && (int)blockIdx.x >= block_end[i]) ++i;
+  bid = (int)blockIdx.x - (i == 0 ? 0 : block_end[i - 1]);
+  return i;
+}
+
+template <typename T, int BM, int BN, int DIR>
+__global__ __launch_bounds__(BLOCK, 2) void k_sn_gemm_group(SnGemmGroup<T> g) {
+  int bid;
+  const int i = group_member(g.block_end, g.n, bid);
+  const SnGemmArgs<T> &a = g.m[i];
+  sn_gemm_tile<T, BM, BN, DIR>(a.f, a.tasks, a.nc, a.ctiles, a.X, a.Z, a.U, a.nsplit, a.kseg, a.ws, a.n_rs, bid);
+}
+
+template <typename T, int BM, int DIR>
+__global__ __launch_bounds__(BLOCK) void k_sn_reduce_group(SnGemmGroup<T> g) {
+  int bid;
+  const int i = group_member(g.block_end, g.n, bid);
+  const SnGemmArgs<T> &a = g.m[i];
+  sn_reduce_block<T, BM, DIR>(a.f, a.tasks, a.nc, a.nsplit, a.ws, a.X, a.Z, a.U, bid);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fwd_asm_group(AsmGroup<T> g) {
+  int bid;
+  const int i = group_member(g.block_end, g.n, bid);
+  const AsmArgs<T> &a = g.m[i];
+  fwd_asm_block<T>(a.tgt, a.n_tgt, a.src, a.nc, a.X, a.U, bid);
+}
+
+// Launch configuration of one supernode-GEMM launch (tile shape, K split).
+struct SnConfig {
+  int bmv = 0, bn = 0, ct = 0, nsplit = 1, kseg = 0, dir_k = 0;
+  int64_t tiles = 0;
+  int32_t n_rs = 0;
+  unsigned grid = 0;
+  const SolveTask *tasks = nullptr;
+};
+
 // Tile shape per launch: BN from the right-hand-side width; 32-row tiles when
 // 64-row tiles would leave the GPU short of work items or pad many rows.
 template <typename T, int DIR>
-static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t splitk,
-                           Profiler *prof, void *ws, int64_t ws_bytes, int32_t nc, T *X, T *Z, T *U,
-                           hipStream_t s) {
-  if (L.n_tasks == 0) return;
+static SnConfig sn_config(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t splitk,
+                          const void *ws, int64_t ws_bytes, int32_t nc) {
+  SnConfig c;
   // 32 x 32 tiles for every launch with more than 16 columns: on the 32^3
   // workload they beat the 64-row and 64-column tiles at every tree height
   // (occupancy 5 against 2 waves per SIMD, 4x the work items, less row
@@ -1526,9 +1625,30 @@ static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32
       if (nsplit < 2 || (int64_t)tiles * nsplit * bmv * nc * (int64_t)sizeof(T) > ws_bytes) nsplit = 1;
     }
   }
-  const int32_t n_rs = (int32_t)(tiles * nsplit);  // row tiles x K segments
-  const unsigned grid = (unsigned)(((n_rs + 7) / 8) * 8 * (int64_t)ct);
-  const int dir_k = (DIR == 1 && f.panel_t) ? 2 : DIR;
+  c.n_rs = (int32_t)(tiles * nsplit);  // row tiles x K segments
+  c.grid = (unsigned)(((c.n_rs + 7) / 8) * 8 * (int64_t)ct);
+  c.dir_k = (DIR == 1 && f.panel_t) ? 2 : DIR;
+  c.bmv = bmv;
+  c.bn = bn;
+  c.ct = ct;
+  c.nsplit = nsplit;
+  c.kseg = kseg;
+  c.tiles = tiles;
+  c.tasks = tasks;
+  return c;
+}
+
+template <typename T, int DIR>
+static void launch_sn_gemm(const FactorDev &f, const SolvePlan::Launch &L, int32_t policy, int32_t splitk,
+                           Profiler *prof, void *ws, int64_t ws_bytes, int32_t nc, T *X, T *Z, T *U,
+                           hipStream_t s) {
+  if (L.n_tasks == 0) return;
+  const SnConfig c = sn_config<T, DIR>(f, L, policy, splitk, ws, ws_bytes, nc);
+  const int bmv = c.bmv, bn = c.bn, ct = c.ct, nsplit = c.nsplit, kseg = c.kseg, dir_k = c.dir_k;
+  const int32_t n_rs = c.n_rs;
+  const unsigned grid = c.grid;
+  const SolveTask *tasks = c.tasks;
+  const int64_t tiles = c.tiles;
   // algorithmic work: one multiply-add per structural nonzero of L and
   // right-hand side (8 flops complex, 2 real; the zeros that the dense
   // supernode blocks store are not counted); traffic: those factor entries
@@ -1603,9 +1723,123 @@ void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T 
                          nullptr, s);
 }
 
+namespace {
+struct GemmItem {
+  int member;
+  const SolvePlan::Launch *L;
+  SnConfig c;
+};
+
+// One height of merged solves: GEMM launches grouped by tile shape and
+// direction variant, then the split-K reduces of the members that split.
+template <typename T, int DIR>
+void group_gemm_step(const SolveMember<T> *m, const std::vector<GemmItem> &items, hipStream_t s) {
+  std::vector<bool> done(items.size(), false);
+  for (size_t a = 0; a < items.size(); ++a) {
+    if (done[a]) continue;
+    const SnConfig &ca = items[a].c;
+    // members of this shape, in chunks of SOLVE_GROUP_MAX
+    std::vector<size_t> sel;
+    for (size_t b = a; b < items.size(); ++b)
+      if (!done[b] && items[b].c.bmv == ca.bmv && items[b].c.bn == ca.bn && items[b].c.dir_k == ca.dir_k) {
+        sel.push_back(b);
+        done[b] = true;
+      }
+    for (size_t k0 = 0; k0 < sel.size(); k0 += SOLVE_GROUP_MAX) {
+      SnGemmGroup<T> g{};
+      SnGemmGroup<T> r{};  // reduces of the members that split along K
+      unsigned grid = 0, rgrid = 0;
+      for (size_t k = k0; k < std::min(sel.size(), k0 + SOLVE_GROUP_MAX); ++k) {
+        const GemmItem &it = items[sel[k]];
+        const SolveMember<T> &mm = m[it.member];
+        SnGemmArgs<T> arg{*mm.f, it.c.tasks, mm.X, mm.Z, mm.U, (T *)mm.p->splitk_ws, mm.nc, it.c.ct,
+                          it.c.nsplit, it.c.kseg, it.c.n_rs};
+        grid += it.c.grid;
+        g.block_end[g.n] = (int32_t)grid;
+        g.m[g.n++] = arg;
+        if (it.c.nsplit > 1) {
+          rgrid += (unsigned)(it.c.tiles * ((mm.nc + 63) / 64));
+          r.block_end[r.n] = (int32_t)rgrid;
+          r.m[r.n++] = arg;
+        }
+      }
+      if (grid == 0) continue;
+#define SNG_CASE(BMV, BNV)                                                                                   \
+  if (ca.bmv == BMV && ca.bn == BNV) {                                                                       \
+    if (ca.dir_k == 2)                                                                                       \
+      hipLaunchKernelGGL((k_sn_gemm_group<T, BMV, BNV, 2>), dim3(grid), dim3(BLOCK), 0, s, g);               \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_sn_gemm_group<T, BMV, BNV, DIR>), dim3(grid), dim3(BLOCK), 0, s, g);             \
+    if (r.n > 0) hipLaunchKernelGGL((k_sn_reduce_group<T, BMV, DIR>), dim3(rgrid), dim3(BLOCK), 0, s, r);   \
+    continue;                                                                                                \
+  }
+      SNG_CASE(64, 64)
+      SNG_CASE(64, 32)
+      SNG_CASE(64, 16)
+      SNG_CASE(32, 64)
+      SNG_CASE(32, 32)
+#undef SNG_CASE
+      fail_launch("merged supernode solve: no kernel for this tile shape");
+    }
+  }
+}
+}  // namespace
+
+template <typename T>
+void solve_forward_group(const SolveMember<T> *m, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (n > SOLVE_GROUP_MAX) fail_launch("merged solve: too many members");
+  int H = 0;
+  for (int i = 0; i < n; ++i) H = std::max(H, m[i].p->n_heights);
+  for (int h = 0; h < H; ++h) {
+    AsmGroup<T> g{};
+    unsigned grid = 0;
+    std::vector<GemmItem> items;
+    for (int i = 0; i < n; ++i) {
+      const SolvePlan &p = *m[i].p;
+      if (h >= p.n_heights) continue;
+      const int64_t t0 = p.h_tgt_off[h], t1 = p.h_xtgt_end[h];
+      if (t1 > t0) {
+        grid += (unsigned)((t1 - t0 + 3) / 4);
+        g.block_end[g.n] = (int32_t)grid;
+        g.m[g.n++] = AsmArgs<T>{p.tgt + t0, p.src, m[i].X, m[i].U, t1 - t0, m[i].nc};
+      }
+      const SolvePlan::Launch &L = p.fwd[h];
+      if (L.n_tasks > 0)
+        items.push_back({i, &L, sn_config<T, 0>(*m[i].f, L, p.tile_rows, p.splitk, p.splitk_ws, p.splitk_bytes,
+                                                m[i].nc)});
+    }
+    if (grid > 0) hipLaunchKernelGGL((k_fwd_asm_group<T>), dim3(grid), dim3(BLOCK), 0, s, g);
+    group_gemm_step<T, 0>(m, items, s);
+  }
+}
+
+template <typename T>
+void solve_backward_group(const SolveMember<T> *m, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (n > SOLVE_GROUP_MAX) fail_launch("merged solve: too many members");
+  int H = 0;
+  for (int i = 0; i < n; ++i) H = std::max(H, m[i].p->n_heights);
+  for (int t = 0; t < H; ++t) {
+    std::vector<GemmItem> items;
+    for (int i = 0; i < n; ++i) {
+      const SolvePlan &p = *m[i].p;
+      const int h = p.n_heights - 1 - t;
+      if (h < 0) continue;
+      const SolvePlan::Launch &L = p.bwd[h];
+      if (L.n_tasks > 0)
+        items.push_back({i, &L, sn_config<T, 1>(*m[i].f, L, p.tile_rows, p.splitk, p.splitk_ws, p.splitk_bytes,
+                                                m[i].nc)});
+    }
+    group_gemm_step<T, 1>(m, items, s);
+  }
+}
+
 #define SOLVE_INST(T)                                                                                   \
   template void solve_forward<T>(const FactorDev &, const SolvePlan &, int32_t, T *, T *, T *, hipStream_t); \
-  template void solve_backward<T>(const FactorDev &, const SolvePlan &, int32_t, T *, T *, hipStream_t);
+  template void solve_backward<T>(const FactorDev &, const SolvePlan &, int32_t, T *, T *, hipStream_t); \
+  template void solve_forward_group<T>(const SolveMember<T> *, int, hipStream_t);                       \
+  template void solve_backward_group<T>(const SolveMember<T> *, int, hipStream_t);
 SOLVE_INST(double)
 SOLVE_INST(cd)
 SOLVE_INST(float)

@@ -196,4 +196,22 @@ void solve_forward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *
 template <typename T>
 void solve_backward(const FactorDev &f, const SolvePlan &p, int32_t nc, T *X, T *Z, hipStream_t s);
 
+// Solves with several factors (one per member) at the same step, merged: one
+// launch per tree height and tile shape for up to SOLVE_GROUP_MAX members
+// (heights aligned at the leaves for the forward solve, at the roots for the
+// backward solve). Bitwise the same results as separate solves; the plans'
+// profilers are not used.
+constexpr int SOLVE_GROUP_MAX = 8;
+template <typename T>
+struct SolveMember {
+  const FactorDev *f;
+  const SolvePlan *p;
+  int32_t nc;
+  T *X, *Z, *U;
+};
+template <typename T>
+void solve_forward_group(const SolveMember<T> *m, int n, hipStream_t s);
+template <typename T>
+void solve_backward_group(const SolveMember<T> *m, int n, hipStream_t s);
+
 }  // namespace stmg

@@ -1054,6 +1054,146 @@ void solver_iteration(stmg_handle *h, double *dst_norm2) {
   }
 }
 
+// ---------------------------------------------------------- batched cycles
+// One iteration for several handles at once. The members share N_t, p_t,
+// the precision form and the smoother sequence, so their V-cycles take the
+// same sequence of level steps; the streaming steps (residual, Jacobi
+// update, G^T, time scan, G-add, transfers) run per member on the shared
+// stream, the slab and nodal solves of each step run merged over the
+// members (one launch per tree height and tile shape). Each member's values
+// are computed by the same instructions in the same order as in its own
+// iteration, so batched and separate iterations agree bitwise.
+template <typename R>
+struct GroupOps {
+  std::vector<OpsT<R>> ops;
+  hipStream_t s;
+  using B = Bufs<R>;
+  using CX = typename B::C;
+
+  static LevelData &lev(OpsT<R> &o, int l) { return o.h->levels[l]; }
+
+  void slab_solves(int l) {
+    if (lev(ops[0], l).slab.is_complex) {
+      std::vector<SolveMember<CX>> m;
+      for (auto &o : ops) {
+        LevelData &L = lev(o, l);
+        m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, (CX *)B::w(L), (CX *)B::z(L), (CX *)B::u(L)});
+      }
+      solve_forward_group<CX>(m.data(), (int)m.size(), s);
+      solve_backward_group<CX>(m.data(), (int)m.size(), s);
+    } else {
+      std::vector<SolveMember<R>> m;
+      for (auto &o : ops) {
+        LevelData &L = lev(o, l);
+        m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, B::w(L), B::z(L), B::u(L)});
+      }
+      solve_forward_group<R>(m.data(), (int)m.size(), s);
+      solve_backward_group<R>(m.data(), (int)m.size(), s);
+    }
+  }
+
+  void smooth_S(int l) {
+    for (auto &o : ops) {
+      LevelData &L = lev(o, l);
+      o.residual(l, B::x(L), B::b(L), B::w(L), RES_OUT_SLABRHS, nullptr);
+    }
+    slab_solves(l);
+    for (auto &o : ops) {
+      LevelData &L = lev(o, l);
+      launch_slab_update<R>(o.ne(l), L.N, o.h->q, o.h->opt.omega, B::w(L), B::x(L), 0, s);
+    }
+  }
+
+  void nodal_A(int l) {
+    std::vector<SolveMember<R>> m;
+    for (auto &o : ops) {
+      if (o.nv(l) == 0) continue;
+      LevelData &L = lev(o, l);
+      MeshData &md = o.mesh(l);
+      o.residual(l, B::x(L), B::b(L), B::w(L), RES_OUT_R, nullptr);
+      launch_gradT<R>(o.nv(l), o.W(l), md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, B::w(L), B::g(L), s);
+      m.push_back({&B::fac(md.nodal), &md.nodal.plan, o.W(l), B::g(L), B::zn(L), B::un(L)});
+    }
+    solve_forward_group<R>(m.data(), (int)m.size(), s);
+    solve_backward_group<R>(m.data(), (int)m.size(), s);
+    for (auto &o : ops) {
+      if (o.nv(l) == 0) continue;
+      LevelData &L = lev(o, l);
+      MeshData &md = o.mesh(l);
+      launch_time_scan<R>(o.nv(l), L.N, o.h->q, B::g(L), s);
+      launch_grad_add<R>(o.ne(l), o.W(l), md.d_head, md.d_tail, B::g(L), B::x(L), s);
+    }
+  }
+
+  void hybrid(int l, bool pre) {
+    const char *seq = smoother_sequence(ops[0].h->opt.smoother);
+    const int n = (int)strlen(seq);
+    for (int i = 0; i < n; ++i) {
+      if (seq[pre ? n - 1 - i : i] == 'S')
+        smooth_S(l);
+      else
+        nodal_A(l);
+    }
+  }
+
+  void vcycle(int l) {
+    if (lev(ops[0], l).N == 1) {
+      for (auto &o : ops) o.exact(l, B::x(lev(o, l)), B::b(lev(o, l)));
+      return;
+    }
+    hybrid(l, true);
+    for (auto &o : ops) {
+      LevelData &L = lev(o, l), &C = lev(o, l + 1);
+      o.residual(l, B::x(L), B::b(L), B::w(L), RES_OUT_R, nullptr);
+      o.restrict_to(l, B::w(L), B::b(C));
+      launch_fill<R>(B::x(C), (int64_t)o.ne(l + 1) * o.W(l + 1), 0.0, s);
+    }
+    vcycle(l + 1);
+    for (auto &o : ops) o.prolong_add(l, B::x(lev(o, l + 1)), B::x(lev(o, l)));
+    hybrid(l, false);
+  }
+};
+
+// Handles that may share a batched iteration: the same N_t, DG degree,
+// precision form and smoother sequence (so the same steps in the same order).
+bool same_cycle_shape(const stmg_handle *a, const stmg_handle *b) {
+  return a->Nt == b->Nt && a->pt == b->pt && a->opt.precision == b->opt.precision &&
+         a->opt.smoother == b->opt.smoother && a->levels.size() == b->levels.size();
+}
+
+// One iteration of every member on stream s; ||b - L x||^2 into each
+// member's d_scalar[slot].
+void group_iteration(const std::vector<stmg_handle *> &hs, hipStream_t s, int slot) {
+  if (hs[0]->opt.precision == STMG_FP32_REFINED) {
+    GroupOps<float> g;
+    g.s = s;
+    for (auto *h : hs) {
+      LevelData &L = h->levels[0];
+      OpsT<float> o{h, s};
+      const int64_t n = (int64_t)o.ne(0) * o.W(0);
+      launch_to_float(n, L.w, L.b32, s);
+      launch_fill<float>(L.x32, n, 0.0, s);
+      g.ops.push_back(o);
+    }
+    g.vcycle(0);
+    for (auto *h : hs) {
+      LevelData &L = h->levels[0];
+      Ops o64{h, s};
+      launch_add_float((int64_t)o64.ne(0) * o64.W(0), L.x32, L.x, s);
+      o64.residual_norm2(0, L.x, L.b, L.w, h->d_scalar + slot);
+    }
+  } else {
+    GroupOps<double> g;
+    g.s = s;
+    for (auto *h : hs) g.ops.push_back(Ops{h, s});
+    g.vcycle(0);
+    for (auto *h : hs) {
+      LevelData &L = h->levels[0];
+      Ops{h, s}.residual_norm2(0, L.x, L.b, L.w, h->d_scalar + slot);
+    }
+  }
+}
+
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
 void set_profiler(stmg_handle *h, bool on) {
@@ -1447,6 +1587,11 @@ void iteration(stmg_handle *h, double *dst_norm2) {
   solver_iteration(h, dst_norm2);
   check_launch();
 }
+bool batchable(const stmg_handle *a, const stmg_handle *b) { return same_cycle_shape(a, b); }
+void batched_iteration(const std::vector<stmg_handle *> &hs, hipStream_t s) {
+  group_iteration(hs, s, 0);
+  check_launch();
+}
 void destroy(stmg_handle *h) { destroy_handle(h); }
 const char *last_error() { return g_err.c_str(); }
 }  // namespace internal
@@ -1604,6 +1749,40 @@ int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host) {
       }
     }
     h->cycles += n_cycles;
+  });
+}
+
+int stmg_cycles_batched(stmg_handle *const *hs, int32_t n, int32_t n_cycles, double *res_host) {
+  return guard([&] {
+    STMG_REQUIRE(hs && n >= 1 && n <= SOLVE_GROUP_MAX, STMG_EINVAL, "need 1 to 8 handles");
+    STMG_REQUIRE(n_cycles >= 0 && n_cycles <= 8192, STMG_EINVAL, "n_cycles out of range");
+    std::vector<stmg_handle *> v(hs, hs + n);
+    for (int32_t i = 0; i < n; ++i) {
+      require_device(v[i]);
+      STMG_REQUIRE(same_cycle_shape(v[0], v[i]), STMG_EINVAL,
+                   "batched handles need the same N_t, p_t, precision form and smoother");
+      for (int32_t j = 0; j < i; ++j) STMG_REQUIRE(v[j] != v[i], STMG_EINVAL, "a handle appears twice");
+    }
+    // the members' own streams first finish what they hold
+    for (auto *h : v) hip_check(hipStreamSynchronize(h->stream), "sync");
+    hipStream_t s = v[0]->stream;
+    for (int32_t c = 0; c < n_cycles; ++c) group_iteration(v, s, c);
+    check_launch();
+    if (n_cycles > 0) {
+      std::vector<double> r2((size_t)n * n_cycles);
+      for (int32_t i = 0; i < n; ++i)
+        hip_check(hipMemcpyAsync(r2.data() + (size_t)i * n_cycles, v[i]->d_scalar, n_cycles * sizeof(double),
+                                 hipMemcpyDeviceToHost, s),
+                  "copy");
+      hip_check(hipStreamSynchronize(s), "sync");
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t c = 0; c < n_cycles; ++c) {
+          const double rel = std::sqrt(r2[(size_t)i * n_cycles + c]) / (v[i]->bnorm > 0 ? v[i]->bnorm : 1.0);
+          v[i]->history.push_back(rel);
+          if (res_host) res_host[(size_t)i * n_cycles + c] = rel;
+        }
+    }
+    for (auto *h : v) h->cycles += n_cycles;
   });
 }
 

@@ -129,6 +129,7 @@ def lib():
         L.stmg_profile.argtypes = [vp, ip]
         L.stmg_set_stream_tuning.argtypes = [vp, ip, ip]
         L.stmg_vcycle.argtypes = [vp, vp, vp]
+        L.stmg_cycles_batched.argtypes = [C.POINTER(vp), ip, ip, dp]
         L.stmg_debug_fail_alloc.argtypes = [C.c_int64]
         L.stmg_debug_fail_alloc.restype = C.c_int64
         L.stmg_power_rate.argtypes = [vp, vp, ip, C.c_double, dp, dp, C.POINTER(C.c_int32)]
@@ -136,7 +137,7 @@ def lib():
         L.stmg_profile_get.argtypes = [vp, ip, C.c_char_p, ip, C.POINTER(C.c_int64), dp, dp, dp]
         for name in ("stmg_setup", "stmg_info", "stmg_level_info", "stmg_edges", "stmg_solve",
                      "stmg_load", "stmg_cycles", "stmg_store", "stmg_power_rate", "stmg_residual",
-                     "stmg_residual_noalloc", "stmg_vcycle",
+                     "stmg_residual_noalloc", "stmg_vcycle", "stmg_cycles_batched",
                      "stmg_level_apply", "stmg_export_matrix", "stmg_export_factor", "stmg_profile",
                      "stmg_profile_count", "stmg_profile_get", "stmg_set_stream_tuning", "stmg_server_create",
                      "stmg_submit", "stmg_poll", "stmg_server_wait", "stmg_server_stats"):
@@ -149,6 +150,15 @@ def debug_fail_alloc(k):
     """Arm the k-th library allocation to fail (k <= 0 disarms); returns the
     allocations counted since the previous call."""
     return int(lib().stmg_debug_fail_alloc(int(k)))
+
+
+def cycles_batched(solvers, n):
+    """n iterations of several loaded solvers at once with merged solves;
+    returns the [len(solvers)][n] relative residuals."""
+    hs = (C.c_void_p * len(solvers))(*[s_._h.value for s_ in solvers])
+    res = np.zeros((len(solvers), max(1, n)))
+    _check(lib().stmg_cycles_batched(hs, len(solvers), n, res.ctypes.data_as(C.POINTER(C.c_double))))
+    return res[:, :n]
 
 
 def default_options(**kw) -> Options:

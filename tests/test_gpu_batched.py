@@ -1,0 +1,113 @@
+"""Batched iterations over several handles (stmg_cycles_batched): the slab
+and nodal solves of each level step run merged over the handles, one launch
+per tree height and tile shape.
+
+* Every member's iterates and residual histories are bitwise those of the
+  same handle iterated alone (stmg_cycles), for a mix of mesh sizes,
+  materials, a jittered mesh and a Neumann problem, both DG degrees and both
+  precision forms.
+* A batched solve reaches the oracle's residual target (the space-time
+  system of eq. (1), FP64 oracle) for each member.
+* Handles of different shapes, duplicates and more than 8 handles are
+  refused with STMG_EINVAL.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_09548_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _mix(Nt, pt):
+    probs = [inputs.config_block_random(n=4, Nt=Nt, pt=pt, seed=81, block_hexes=2),
+             inputs.config_block_random(n=8, Nt=Nt, pt=pt, seed=82, block_hexes=4),
+             inputs.config_core_box(n=6, Nt=Nt, pt=pt, seed=83, jitter=0.2),
+             inputs.config_request(8, Nt, pt, seed=84)]
+    nb = inputs.config_block_random(n=6, Nt=Nt, pt=pt, seed=85, block_hexes=3)
+    nb.bc = "neumann"
+    probs.append(nb)
+    return probs
+
+
+@pytest.mark.parametrize("pt,precision", [(1, 0), (0, 0), (1, 1)])
+def test_batched_equals_separate_bitwise(pt, precision):
+    import torch
+    from paper_1911_09548_amd import stmg
+    Nt, k = 16, 4
+    probs = _mix(Nt, pt)
+    print(f"\n[case] batched p_t={pt} precision={precision}: {len(probs)} members", flush=True)
+    solvers = [stmg.Solver(p, precision=precision, device_factor=1 if i == 1 else -1)
+               for i, p in enumerate(probs)]
+    try:
+        rhs = [_dev(np.random.default_rng(90 + i).standard_normal((Nt, pt + 1, s.n_edges)))
+               for i, s in enumerate(solvers)]
+        alone, hist_alone = [], []
+        for s, b in zip(solvers, rhs):
+            s.load(b)
+            hist_alone.append(s.cycles(k))
+            alone.append(s.store().clone())
+        for s, b in zip(solvers, rhs):
+            s.load(b)
+        hist = stmg.cycles_batched(solvers, k)
+        for i, s in enumerate(solvers):
+            x = s.store()
+            torch.cuda.synchronize()
+            assert torch.equal(x, alone[i]), (i, probs[i].meta["name"])
+            assert np.array_equal(hist[i], hist_alone[i]), (i, hist[i], hist_alone[i])
+        print(f"[batched] members bitwise equal; final residuals {[f'{h[-1]:.1e}' for h in hist]}")
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_batched_solve_reaches_oracle_residual():
+    from paper_1911_09548_amd import stmg
+    from oracle.vcycle import SpaceTimeMultigrid
+    Nt = 8
+    probs = [inputs.config_block_random(n=4, Nt=Nt, pt=1, seed=86, block_hexes=2),
+             inputs.config_unit_manufactured(4, Nt, 1)]
+    probs[1].bc = "neumann"
+    solvers = [stmg.Solver(p) for p in probs]
+    try:
+        bs = [np.random.default_rng(95 + i).standard_normal((Nt, 2, s.n_edges)) for i, s in enumerate(solvers)]
+        for s, b in zip(solvers, bs):
+            s.load(_dev(b))
+        hist = stmg.cycles_batched(solvers, 14)
+        for i, (s, p, b) in enumerate(zip(solvers, probs, bs)):
+            ora = SpaceTimeMultigrid(p)
+            x = ora.to_interior(s.store().cpu().numpy())
+            bi = ora.to_interior(b)
+            rr = np.linalg.norm(ora.levels[0].residual(x, bi)) / np.linalg.norm(bi)
+            print(f"[batched] member {i}: GPU history end {hist[i][-1]:.1e}, oracle residual {rr:.1e}")
+            assert rr <= 1e-10, (i, rr)
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_batched_refuses_mismatched_handles():
+    from paper_1911_09548_amd import stmg
+    a = stmg.Solver(inputs.config_block_random(n=4, Nt=8, pt=1, seed=87, block_hexes=2))
+    b = stmg.Solver(inputs.config_block_random(n=4, Nt=16, pt=1, seed=88, block_hexes=2))
+    c = stmg.Solver(inputs.config_block_random(n=4, Nt=8, pt=0, seed=89, block_hexes=2))
+    d = stmg.Solver(inputs.config_block_random(n=4, Nt=8, pt=1, seed=90, block_hexes=2), precision=stmg.FP32_REFINED)
+    try:
+        for other in (b, c, d):
+            with pytest.raises(stmg.StmgError) as e:
+                stmg.cycles_batched([a, other], 1)
+            assert e.value.code == stmg.STMG_EINVAL
+        with pytest.raises(stmg.StmgError) as e:
+            stmg.cycles_batched([a, a], 1)
+        assert e.value.code == stmg.STMG_EINVAL
+        with pytest.raises(stmg.StmgError) as e:
+            stmg.cycles_batched([a] * 9, 1)
+        assert e.value.code == stmg.STMG_EINVAL
+    finally:
+        for s in (a, b, c, d):
+            s.close()
