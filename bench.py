@@ -135,6 +135,7 @@ def serving_bench(args):
     stream = inputs.request_stream(n_requests=args.serve_requests, rate=1.0, seed=5, sizes=sizes,
                                    horizons=horizons, degrees=(0, 1))
     problems = []
+    log(f"[bench] serving: building {len(stream)} requests")
     for r in stream:
         prob = inputs.config_request(r["n"], r["Nt"], r["pt"], r["seed"])
         E = inputs.count_edges(prob.levels[0].tets, prob.levels[0].coords.shape[0])
@@ -170,15 +171,40 @@ def serving_bench(args):
             time.sleep(delay)
         tickets.append(srv.submit(prob, rhs, **opts32))
     worst, ok = 0.0, True
-    for (prob, rhs), tk in zip(problems, tickets):
+    for i, ((prob, rhs), tk) in enumerate(zip(problems, tickets)):
         assert srv.wait(tk, 900)
         rc, _, rep = srv.poll(tk, rhs.shape)
         ok &= rc == stmg.STMG_OK
         worst = max(worst, rep["rel_res"])
+        if (i + 1) % 8 == 0:
+            log(f"[bench] serving: {i + 1} of {len(problems)} requests done")
     st = srv.stats()
     srv.close()
     log(f"[bench] serving: p50 {st['p50_s']:.3f} s, p99 {st['p99_s']:.3f} s, "
-        f"{st['throughput_req_s']:.2f} requests/s, {st['throughput_dofs']:.3e} DOF-updates/s")
+        f"{st['throughput_req_s']:.2f} requests/s, {st['throughput_dofs']:.3e} DOF-updates/s, "
+        f"{st['batched_iterations']} batched iterations ({st['batched_members']} request iterations)")
+
+    def closed_loop(batch):
+        # saturated: every request submitted at once
+        srv = stmg.Server(max_active=args.serve_active, setup_threads=args.serve_threads, batch=batch)
+        tks = [srv.submit(prob, rhs, **opts32) for prob, rhs in problems]
+        good = True
+        for i, ((prob, rhs), tk) in enumerate(zip(problems, tks)):
+            assert srv.wait(tk, 900)
+            rc, _, _ = srv.poll(tk, rhs.shape)
+            good &= rc == stmg.STMG_OK
+            if (i + 1) % 8 == 0:
+                log(f"[bench] serving (closed loop, batch={batch}): {i + 1} of {len(problems)} requests done")
+        cst = srv.stats()
+        srv.close()
+        return {"throughput_req_s": cst["throughput_req_s"], "throughput_dof_updates_s": cst["throughput_dofs"],
+                "p50_s": cst["p50_s"], "p99_s": cst["p99_s"], "batched_iterations": cst["batched_iterations"],
+                "batched_request_iterations": cst["batched_members"], "all_converged": bool(good)}
+
+    closed = {"batched": closed_loop(True), "unbatched": closed_loop(False),
+              "single_stream_req_s": 1.0 / single32}
+    log(f"[bench] serving, all submitted at once: {closed['batched']['throughput_req_s']:.2f} requests/s batched, "
+        f"{closed['unbatched']['throughput_req_s']:.2f} unbatched, {closed['single_stream_req_s']:.2f} single-stream")
     return {"form": "continuous batching, fp32 smoother + fp64 refinement to 1e-8",
             "requests": len(problems),
             "mix": (f"n in {sizes} (x6 Kuhn tets), N_t in {horizons}, p_t in (0, 1), "
@@ -188,7 +214,8 @@ def serving_bench(args):
             "throughput_req_s": st["throughput_req_s"], "throughput_dof_updates_s": st["throughput_dofs"],
             "single_stream_s_per_request": {"fp32_refined": single32, "fp64": single64, "requests": k},
             "max_active": args.serve_active, "hbm_peak_bytes": st["hbm_peak"],
-            "all_converged": bool(ok), "max_final_rel_res": worst}
+            "batched_iterations": st["batched_iterations"], "batched_request_iterations": st["batched_members"],
+            "all_converged": bool(ok), "max_final_rel_res": worst, "closed_loop": closed}
 
 
 def _source_sha():
@@ -432,6 +459,7 @@ def main():
     ap.add_argument("--serve-probe", type=int, default=4, help="requests timed one at a time")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-threads", type=int, default=4)
+    ap.add_argument("--serve-only", action="store_true", help="only the serving-form measurement")
     ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
                     help="first run one plain device copy of this many MiB (read + write), so that "
                          "hardware byte counters can be scaled by a kernel of known traffic")
@@ -468,6 +496,11 @@ def main():
 
     if args.rate_sweep:
         rate_sweep(args)
+        return
+    if args.serve_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving_form": serving_bench(args)}), flush=True)
         return
     if args.two_lambda:
         print(json.dumps({"two_lambda": two_lambda(args)}), flush=True)

@@ -334,15 +334,21 @@ int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_sch
  * concurrently (one non-blocking HIP stream per active request, one
  * iteration in flight each, convergence polled without blocking); results
  * return to host memory and the request's device memory is released on its
- * stream. Each request runs exactly the kernels it would run alone, in the
- * same order with deterministic reductions, so its result does not depend
- * on the mix. Thread-safe; the calling thread never blocks on the GPU except
- * in stmg_server_wait. */
+ * stream. Requests of the same cycle shape whose iterations are due together
+ * run them batched (their slabs' solves of each level merged into one launch
+ * per tree height; see stmg_server_options.batch). Each request computes its
+ * values with the same instructions in the same order as it would alone,
+ * with deterministic reductions, so its result does not depend on the mix.
+ * Thread-safe; the calling thread never blocks on the GPU except in
+ * stmg_server_wait. */
 typedef struct stmg_server stmg_server;
 typedef struct {
   int64_t hbm_budget;            /* device bytes the server may hold; <= 0: 90% of free memory */
   int32_t max_active;            /* requests on the GPU at once (default 16) */
   int32_t setup_threads;         /* host setup workers (default 4) */
+  int32_t batch;                 /* 1 (default): due iterations of requests with the same N_t, p_t,
+                                    precision form and smoother run batched (stmg_cycles_batched's
+                                    merged solves, up to 8 requests, on a shared stream); 0: never */
 } stmg_server_options;
 typedef struct {
   int64_t submitted, completed, failed, active, pending;
@@ -350,6 +356,8 @@ typedef struct {
   double throughput_req_s;       /* completed / (last completion - first submission) */
   double throughput_dofs;        /* sum over completed of n_e N_t (p_t+1) x cycles, same span */
   int64_t hbm_reserved, hbm_peak, hbm_budget;
+  int64_t batched_iterations;    /* batched iterations run (each over 2 to 8 requests) */
+  int64_t batched_members;       /* request iterations inside them */
 } stmg_server_stats_t;
 
 void stmg_server_default_options(stmg_server_options *opt);

@@ -14,8 +14,13 @@
 // copied to pinned host memory -> device memory released on its stream.
 // Device setup never runs on the scheduler thread, so a large request's
 // factorisation does not stall the iterations of the requests in flight.
-// Every request runs exactly the kernels it would run alone, in the same
-// order, so its result does not depend on the mix.
+// Requests whose next iterations are due at the same time and whose V-cycles
+// take the same steps (same N_t, DG degree, precision form and smoother) run
+// those iterations batched, on one of the server's shared streams: the slab
+// and nodal solves of each level step of all of them in one launch per tree
+// height (up to 8 requests). Every request computes its values with the same
+// instructions in the same order as alone, batched or not, so its result
+// does not depend on the mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,6 +103,7 @@ struct Request {
   double *pin_norm = nullptr, *pin_x = nullptr;
   hipEvent_t ev = nullptr;
   bool in_flight = false;
+  bool want_iteration = false;  // the previous iteration is done and another is due
   int64_t est_bytes = 0;
   int64_t dofs = 0;  // n_e * N_t * q of the finest level
   double bnorm = 0.0;
@@ -124,6 +130,9 @@ struct stmg_server {
   std::vector<std::thread> workers;
   std::thread scheduler;
   int device = 0;
+  std::vector<hipStream_t> batch_streams;  // shared streams of batched iterations
+  size_t next_batch_stream = 0;
+  int64_t batched_iterations = 0, batched_members = 0;
 
   void worker_loop();
   void host_setup(const std::shared_ptr<Request> &r);
@@ -131,6 +140,8 @@ struct stmg_server {
   void scheduler_loop();
   bool admit_one();
   bool progress(Request &r);
+  void launch_iterations();
+  void start_iteration(Request &q);
   void finish(Request &r, int code, const char *msg);
   void release(Request &r);
 };
@@ -306,14 +317,8 @@ bool stmg_server::progress(Request &q) {
         return true;
       }
     }
-    try {
-      internal::iteration(q.h, q.h->d_scalar);
-      hipc(hipMemcpyAsync(q.pin_norm, q.h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, q.stream), "copy");
-      hipc(hipEventRecord(q.ev, q.stream), "hipEventRecord");
-      q.in_flight = true;
-    } catch (const StmgError &e) {
-      finish(q, e.code, e.what());
-    }
+    if (q.want_iteration) return false;
+    q.want_iteration = true;
     return true;
   }
   if (q.state == FINISHING) {
@@ -382,6 +387,61 @@ void stmg_server::release(Request &q) {
   std::vector<double>().swap(q.u0);
 }
 
+// One iteration of a request alone, on its own stream.
+void stmg_server::start_iteration(Request &q) {
+  try {
+    internal::iteration(q.h, q.h->d_scalar);
+    hipc(hipMemcpyAsync(q.pin_norm, q.h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, q.stream), "copy");
+    hipc(hipEventRecord(q.ev, q.stream), "hipEventRecord");
+    q.in_flight = true;
+  } catch (const StmgError &e) {
+    finish(q, e.code, e.what());
+  }
+}
+
+// Start the iterations that are due: requests of the same cycle shape in
+// batches of up to 8 on a shared stream, the others alone. A request is due
+// only when its previous iteration has completed, so it has no work in
+// flight on any stream when a batch takes it.
+void stmg_server::launch_iterations() {
+  std::vector<Request *> due;
+  for (auto &r : active)
+    if (r->state == RUNNING && r->want_iteration) due.push_back(r.get());
+  std::vector<bool> taken(due.size(), false);
+  for (size_t a = 0; a < due.size(); ++a) {
+    if (taken[a]) continue;
+    taken[a] = true;
+    std::vector<Request *> group{due[a]};
+    if (opt.batch)
+      for (size_t b = a + 1; b < due.size() && group.size() < (size_t)SOLVE_GROUP_MAX; ++b)
+        if (!taken[b] && internal::batchable(due[a]->h, due[b]->h)) {
+          taken[b] = true;
+          group.push_back(due[b]);
+        }
+    for (Request *q : group) q->want_iteration = false;
+    if (group.size() == 1) {
+      start_iteration(*group[0]);
+      continue;
+    }
+    hipStream_t s = batch_streams[next_batch_stream++ % batch_streams.size()];
+    std::vector<stmg_handle *> hs;
+    for (Request *q : group) hs.push_back(q->h);
+    try {
+      internal::batched_iteration(hs, s);
+      for (Request *q : group) {
+        hipc(hipMemcpyAsync(q->pin_norm, q->h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+        hipc(hipEventRecord(q->ev, s), "hipEventRecord");
+        q->in_flight = true;
+      }
+      batched_iterations++;
+      batched_members += (int64_t)group.size();
+    } catch (const StmgError &e) {
+      for (Request *q : group)
+        if (!q->in_flight) finish(*q, e.code, e.what());
+    }
+  }
+}
+
 void stmg_server::scheduler_loop() {
   hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
@@ -389,6 +449,7 @@ void stmg_server::scheduler_loop() {
     bool moved = false;
     while (admit_one()) moved = true;
     for (auto &r : active) moved |= progress(*r);
+    launch_iterations();
     active.erase(std::remove_if(active.begin(), active.end(),
                                 [](const std::shared_ptr<Request> &r) { return r->state == DONE || r->state == FAILED; }),
                  active.end());
@@ -412,6 +473,7 @@ void stmg_server_default_options(stmg_server_options *o) {
   o->hbm_budget = 0;
   o->max_active = 16;
   o->setup_threads = 4;
+  o->batch = 1;
 }
 
 int stmg_server_create(const stmg_server_options *opt, stmg_server **out) {
@@ -436,6 +498,15 @@ int stmg_server_create(const stmg_server_options *opt, stmg_server **out) {
   }
   if (s->opt.max_active <= 0) s->opt.max_active = 16;
   if (s->opt.setup_threads <= 0) s->opt.setup_threads = 4;
+  for (int i = 0; i < 4; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : s->batch_streams) (void)hipStreamDestroy(x);
+      delete s;
+      return STMG_EHIP;
+    }
+    s->batch_streams.push_back(st);
+  }
   for (int i = 0; i < s->opt.setup_threads; ++i) s->workers.emplace_back([s] { s->worker_loop(); });
   s->scheduler = std::thread([s] { s->scheduler_loop(); });
   *out = s;
@@ -543,6 +614,8 @@ int stmg_server_stats(stmg_server *s, stmg_server_stats_t *st) {
   st->hbm_reserved = s->reserved;
   st->hbm_peak = s->peak;
   st->hbm_budget = s->opt.hbm_budget;
+  st->batched_iterations = s->batched_iterations;
+  st->batched_members = s->batched_members;
   return STMG_OK;
 }
 
@@ -556,10 +629,12 @@ void stmg_server_destroy(stmg_server *s) {
   for (auto &t : s->workers) t.join();
   if (s->scheduler.joinable()) s->scheduler.join();
   // drain and free whatever is still on the device or set up on the host
+  for (auto x : s->batch_streams) (void)hipStreamSynchronize(x);
   for (auto &r : s->active) {
     if (r->stream) (void)hipStreamSynchronize(r->stream);
     s->release(*r);
   }
+  for (auto x : s->batch_streams) (void)hipStreamDestroy(x);
   for (auto &r : s->ready)
     if (r->h) internal::destroy(r->h);
   for (auto &r : s->admitted)

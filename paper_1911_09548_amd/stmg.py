@@ -73,14 +73,16 @@ class LevelInfo(C.Structure):
 
 
 class ServerOptions(C.Structure):
-    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("setup_threads", C.c_int32)]
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("setup_threads", C.c_int32),
+                ("batch", C.c_int32)]
 
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("active", C.c_int64), ("pending", C.c_int64), ("p50_s", C.c_double), ("p99_s", C.c_double),
                 ("mean_s", C.c_double), ("throughput_req_s", C.c_double), ("throughput_dofs", C.c_double),
-                ("hbm_reserved", C.c_int64), ("hbm_peak", C.c_int64), ("hbm_budget", C.c_int64)]
+                ("hbm_reserved", C.c_int64), ("hbm_peak", C.c_int64), ("hbm_budget", C.c_int64),
+                ("batched_iterations", C.c_int64), ("batched_members", C.c_int64)]
 
 
 _lib = None
@@ -216,8 +218,8 @@ def _marshal_problem(problem, keep):
 class Server:
     """Continuous-batching request server (see stmg_server_* in include/stmg.h)."""
 
-    def __init__(self, hbm_budget=0, max_active=16, setup_threads=4):
-        o = ServerOptions(int(hbm_budget), int(max_active), int(setup_threads))
+    def __init__(self, hbm_budget=0, max_active=16, setup_threads=4, batch=True):
+        o = ServerOptions(int(hbm_budget), int(max_active), int(setup_threads), 1 if batch else 0)
         h = C.c_void_p()
         _check(lib().stmg_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -159,3 +159,33 @@ def test_device_factorisation_in_the_mix():
         assert rep_s["cycles"] == rep["cycles"]
         assert np.array_equal(xs.cpu().numpy(), x)
     srv.close()
+
+
+def test_batched_requests_equal_unbatched():
+    """Requests of one cycle shape (N_t = 16, p_t = 1, precision form) on the
+    GPU together run batched iterations (merged slab and nodal solves); their
+    results are bitwise those of a server that never batches."""
+    from paper_1911_09548_amd import stmg
+    shape = [(4, 16, 1, 201), (6, 16, 1, 202), (8, 16, 1, 203), (4, 16, 1, 204),
+             (8, 16, 1, 205), (6, 16, 1, 206), (12, 16, 1, 207), (8, 16, 1, 208)]
+    reqs = [_request(*m) for m in shape]
+    opts = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
+    out = {}
+    for batch in (True, False):
+        srv = stmg.Server(max_active=8, setup_threads=4, batch=batch)
+        tickets = [srv.submit(p, r, **opts) for p, r in reqs]
+        res = []
+        for (p, r), t in zip(reqs, tickets):
+            assert srv.wait(t, 300)
+            res.append(srv.poll(t, r.shape))
+        out[batch] = (res, srv.stats())
+        srv.close()
+    (res_b, st_b), (res_u, st_u) = out[True], out[False]
+    print(f"\n[serving] batched: {st_b['batched_iterations']} batched iterations, "
+          f"{st_b['batched_members']} request iterations in them; unbatched: {st_u['batched_iterations']}")
+    assert st_b["batched_iterations"] > 0 and st_u["batched_iterations"] == 0
+    assert st_b["completed"] == len(shape) and st_u["completed"] == len(shape)
+    for (rc_b, x_b, rep_b), (rc_u, x_u, rep_u) in zip(res_b, res_u):
+        assert rc_b == rc_u == stmg.STMG_OK
+        assert rep_b["cycles"] == rep_u["cycles"]
+        assert np.array_equal(x_b, x_u)
