@@ -19,6 +19,15 @@ Vectors are arrays of shape (N, q, n_e): slab, DG component, interior edge.
   after the coarse-grid correction with the same steps in reversed order:
   the pre-smoother applies the name's letters from the last to the first,
   the post-smoother from the first to the last.
+* Inexact nodal solves (section 5 solves the spatial problems approximately,
+  with a few preconditioned iterations): with nodal_cheb = k > 0 the K_n^{-1}
+  of the nodal correction is replaced by k steps of the Chebyshev iteration
+  with Jacobi preconditioning from a zero start (Saad, "Iterative Methods for
+  Sparse Linear Systems", 2nd ed., Algorithm 12.1), on the interval
+  [lmax / 30, lmax] with lmax the Gershgorin bound max_i sum_j |K_ij| / K_ii
+  of D^{-1} K_n (the interval of Adams, Brezina, Hu and Tuminaro, 2003, for
+  polynomial smoothers). It is a fixed polynomial in D^{-1} K_n, so the
+  V-cycle stays a fixed linear iteration with the same fixed point.
 * Power iteration for the convergence rate (section 5.1): zero right-hand side,
   random start in [0, 1], up to 200 cycles, maximum l2 reduction factor, stop
   once the total reduction is below 1e-100.
@@ -69,8 +78,42 @@ class SlabSolverComplex:
         return out
 
 
+def chebyshev_bounds(A):
+    """(lmin, lmax) = (lmax / 30, max_i sum_j |A_ij| / A_ii): the Gershgorin
+    bound of the spectrum of D^{-1} A and the lower end used for the
+    Chebyshev iteration."""
+    A = sp.csr_matrix(A)
+    lmax = float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() / A.diagonal()))
+    return lmax / 30.0, lmax
+
+
+def chebyshev_solve(A, g, k, bounds=None):
+    """k steps of the Jacobi-preconditioned Chebyshev iteration for A y = g
+    from y = 0 (Saad, Algorithm 12.1): theta, delta = centre and half-width of
+    the interval, sigma = theta / delta; d_0 = D^{-1} g / theta, y_1 = d_0;
+    then rho_i = 1 / (2 sigma - rho_{i-1}) (rho_0 = 1 / sigma),
+    d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) D^{-1} (g - A y_i),
+    y_{i+1} = y_i + d_i. The error after k steps is T_k((theta - D^{-1}A) /
+    delta) / T_k(sigma) times the initial one. g may hold several right-hand
+    sides as columns."""
+    lmin, lmax = bounds if bounds is not None else chebyshev_bounds(A)
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    sigma = theta / delta
+    dinv = 1.0 / sp.csr_matrix(A).diagonal()
+    dinv = dinv.reshape((-1,) + (1,) * (g.ndim - 1))
+    rho = 1.0 / sigma
+    d = dinv * g / theta
+    y = d.copy()
+    for _ in range(k - 1):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * dinv * (g - A @ y)
+        y = y + d
+        rho = rho_new
+    return y
+
+
 class Level:
-    def __init__(self, spec, space, pt, slab_solver="real"):
+    def __init__(self, spec, space, pt, slab_solver="real", nodal_cheb=0):
         self.spec, self.space, self.pt = spec, space, pt
         self.q = pt + 1
         self.N, self.tau = spec.N, spec.tau
@@ -80,7 +123,11 @@ class Level:
             self.slab = SlabSolverComplex(M, K, self.tau)
         else:
             self.slab = SlabSolverReal(M, K, self.Kt, self.Mt)
-        self.Kn_lu = spla.splu(sp.csc_matrix(space.Kn))
+        self.nodal_cheb = nodal_cheb
+        if nodal_cheb > 0:
+            self.Kn_bounds = chebyshev_bounds(space.Kn) if space.n_v > 0 else None
+        else:
+            self.Kn_lu = spla.splu(sp.csc_matrix(space.Kn))
 
     @classmethod
     def operator_only(cls, space, pt, N, tau):
@@ -123,7 +170,11 @@ class Level:
         G = self.space.G
         g = np.stack([(G.T @ r[:, k].T).T for k in range(self.q)], axis=1)   # (N,q,nv)
         N, q, nv = g.shape
-        y = self.Kn_lu.solve(np.ascontiguousarray(g.reshape(N * q, nv).T)).T.reshape(N, q, nv)
+        if self.nodal_cheb > 0:
+            y = chebyshev_solve(self.space.Kn, np.ascontiguousarray(g.reshape(N * q, nv).T), self.nodal_cheb,
+                                self.Kn_bounds).T.reshape(N, q, nv)
+        else:
+            y = self.Kn_lu.solve(np.ascontiguousarray(g.reshape(N * q, nv).T)).T.reshape(N, q, nv)
         # forward substitution with L_t: K_t y_n = y_n + N_t y_{n-1}
         z = np.empty_like(y)
         prev = np.zeros((q, nv))
@@ -162,7 +213,7 @@ class SpaceTimeMultigrid:
     """The oracle solver for one problem (see module docstring)."""
 
     def __init__(self, problem, lambda_crit=0.1, omega=0.5, slab_solver="real",
-                 allow_space=True, use_nodal=True, space_levels=None, smoother=None):
+                 allow_space=True, use_nodal=True, space_levels=None, smoother=None, nodal_cheb=0):
         self.problem = problem
         self.pt, self.q = problem.pt, problem.pt + 1
         self.omega, self.use_nodal = omega, use_nodal
@@ -171,7 +222,7 @@ class SpaceTimeMultigrid:
         self.smoother = smoother
         self.space = space_levels if space_levels is not None else build_space_levels(problem)
         self.specs = build_level_specs(self.space, problem.T, problem.Nt, lambda_crit, allow_space)
-        self.levels = [Level(s, self.space[s.space], problem.pt, slab_solver) for s in self.specs]
+        self.levels = [Level(s, self.space[s.space], problem.pt, slab_solver, nodal_cheb) for s in self.specs]
         self.Pt = time_prolongation(problem.pt)
         self.fine = self.space[0]
 

@@ -257,3 +257,61 @@ def test_smoother_names_read_right_to_left():
     assert s_sa.levels[1].N == 1
     assert np.array_equal(s_sa.vcycle(0, x, b), two_level(s_sa, A, S))
     assert np.array_equal(s_as.vcycle(0, x, b), two_level(s_as, S, A))
+
+
+def test_chebyshev_error_is_the_scaled_chebyshev_polynomial():
+    """k steps from zero leave the error p(D^{-1} A) e_0 with
+    p(lam) = T_k((theta - lam) / delta) / T_k(theta / delta): checked
+    eigencomponent by eigencomponent on a random SPD matrix whose spectrum
+    lies inside the interval given."""
+    from numpy.polynomial import chebyshev as npc
+    from oracle.vcycle import chebyshev_solve
+    rng = np.random.default_rng(12)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.2, 3.0, n)
+    Dh = np.diag(rng.uniform(0.5, 2.0, n))            # D^{1/2}
+    A = Dh @ Q @ np.diag(lam) @ Q.T @ Dh              # D^{-1/2} A D^{-1/2} = Q lam Q^T
+    A = 0.5 * (A + A.T)
+    D = np.diag(A)
+    # the diagonal of A must be D for the Jacobi preconditioner: rescale
+    s = np.sqrt(np.diag(Dh) ** 2 / D)
+    A = np.diag(s) @ A @ np.diag(s)
+    Dm = np.diag(np.sqrt(np.diag(A)))
+    lamD, V = np.linalg.eigh(np.linalg.inv(Dm) @ A @ np.linalg.inv(Dm))
+    lmin, lmax = 0.9 * lamD.min(), 1.1 * lamD.max()
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    g = rng.standard_normal(n)
+    x = np.linalg.solve(A, g)
+    import scipy.sparse as sps
+    for k in (1, 2, 5, 9):
+        y = chebyshev_solve(sps.csr_matrix(A), g, k, (lmin, lmax))
+        c = np.zeros(k + 1)
+        c[-1] = 1.0
+        p = npc.chebval((theta - lamD) / delta, c) / npc.chebval(theta / delta, c)
+        e0 = V.T @ (Dm @ x)                  # error components in the D^{1/2} eigenbasis
+        ek = V.T @ (Dm @ (x - y))
+        assert np.allclose(ek, p * e0, atol=1e-12 * np.abs(e0).max()), k
+
+
+def test_chebyshev_bounds_contain_the_spectrum_and_converge():
+    from oracle.vcycle import chebyshev_bounds, chebyshev_solve
+    s = _solver(4, 2, 1)
+    Kn = s.fine.Kn
+    lmin, lmax = chebyshev_bounds(Kn)
+    Dm = np.diag(1.0 / np.sqrt(Kn.diagonal()))
+    ev = np.linalg.eigvalsh(Dm @ Kn.toarray() @ Dm)
+    assert ev.max() <= lmax * (1 + 1e-12) and abs(lmin - lmax / 30) <= 1e-15 * lmax
+    g = np.random.default_rng(3).standard_normal((Kn.shape[0], 3))
+    y = chebyshev_solve(Kn, g, 400, (0.99 * ev.min(), lmax))
+    assert np.linalg.norm(y - np.linalg.solve(Kn.toarray(), g)) <= 1e-10 * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_inexact_nodal_vcycle_converges_to_direct_solution(pt):
+    s = _solver(4, 8, pt, nodal_cheb=3)
+    b = np.random.default_rng(5).standard_normal((8, pt + 1, s.fine.n_e))
+    x, hist = s.solve(b, rtol=1e-12, max_cycles=80)
+    xd = direct_solve(s, b)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
