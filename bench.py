@@ -141,6 +141,8 @@ def serving_bench(args):
         E = inputs.count_edges(prob.levels[0].tets, prob.levels[0].coords.shape[0])
         rhs = np.random.default_rng(r["seed"]).standard_normal((r["Nt"], r["pt"] + 1, E))
         problems.append((prob, rhs))
+        if len(problems) % 8 == 0:
+            log(f"[bench] serving: {len(problems)} requests built")
     opts32 = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
     opts64 = dict(precision=stmg.FP64, rtol=1e-8, max_cycles=60)
 
@@ -159,9 +161,36 @@ def serving_bench(args):
     k = min(args.serve_probe, len(problems))
     single32 = one_at_a_time(opts32, k)
     single64 = one_at_a_time(opts64, k)
-    rate = 0.8 / single32
-    log(f"[bench] serving: single-stream {single32:.3f} s/request (FP32 refined), {single64:.3f} (FP64); "
-        f"arrivals at {rate:.2f} requests/s")
+    log(f"[bench] serving: single-stream {single32:.3f} s/request (FP32 refined), {single64:.3f} (FP64), "
+        f"first {k} requests one at a time")
+
+    def closed_loop(batch):
+        # saturated: every request submitted at once
+        srv = stmg.Server(max_active=args.serve_active, setup_threads=args.serve_threads, batch=batch)
+        tks = [srv.submit(prob, rhs, **opts32) for prob, rhs in problems]
+        good = True
+        for i, ((prob, rhs), tk) in enumerate(zip(problems, tks)):
+            assert srv.wait(tk, 900)
+            rc, _, _ = srv.poll(tk, rhs.shape)
+            good &= rc == stmg.STMG_OK
+            if (i + 1) % 8 == 0:
+                log(f"[bench] serving (closed loop, batch={batch}): {i + 1} of {len(problems)} requests done")
+        cst = srv.stats()
+        srv.close()
+        return {"throughput_req_s": cst["throughput_req_s"], "throughput_dof_updates_s": cst["throughput_dofs"],
+                "p50_s": cst["p50_s"], "p99_s": cst["p99_s"], "batched_iterations": cst["batched_iterations"],
+                "batched_request_iterations": cst["batched_members"], "all_converged": bool(good)}
+
+    # the server's capacity on this mix: all requests submitted at once
+    closed = {"batched": closed_loop(True)}
+    if args.serve_closed:
+        closed["unbatched"] = closed_loop(False)
+    capacity = closed["batched"]["throughput_req_s"]
+    log(f"[bench] serving, all submitted at once: {capacity:.2f} requests/s batched" +
+        (f", {closed['unbatched']['throughput_req_s']:.2f} unbatched" if "unbatched" in closed else "") +
+        f"; {1.0 / single32:.2f} requests/s single-stream (first {k} requests)")
+    # Poisson arrivals at 0.8x that capacity: latency under load
+    rate = 0.8 * capacity
     srv = stmg.Server(max_active=args.serve_active, setup_threads=args.serve_threads)
     t0 = time.perf_counter()
     tickets = []
@@ -183,33 +212,11 @@ def serving_bench(args):
     log(f"[bench] serving: p50 {st['p50_s']:.3f} s, p99 {st['p99_s']:.3f} s, "
         f"{st['throughput_req_s']:.2f} requests/s, {st['throughput_dofs']:.3e} DOF-updates/s, "
         f"{st['batched_iterations']} batched iterations ({st['batched_members']} request iterations)")
-
-    def closed_loop(batch):
-        # saturated: every request submitted at once
-        srv = stmg.Server(max_active=args.serve_active, setup_threads=args.serve_threads, batch=batch)
-        tks = [srv.submit(prob, rhs, **opts32) for prob, rhs in problems]
-        good = True
-        for i, ((prob, rhs), tk) in enumerate(zip(problems, tks)):
-            assert srv.wait(tk, 900)
-            rc, _, _ = srv.poll(tk, rhs.shape)
-            good &= rc == stmg.STMG_OK
-            if (i + 1) % 8 == 0:
-                log(f"[bench] serving (closed loop, batch={batch}): {i + 1} of {len(problems)} requests done")
-        cst = srv.stats()
-        srv.close()
-        return {"throughput_req_s": cst["throughput_req_s"], "throughput_dof_updates_s": cst["throughput_dofs"],
-                "p50_s": cst["p50_s"], "p99_s": cst["p99_s"], "batched_iterations": cst["batched_iterations"],
-                "batched_request_iterations": cst["batched_members"], "all_converged": bool(good)}
-
-    closed = {"batched": closed_loop(True), "unbatched": closed_loop(False),
-              "single_stream_req_s": 1.0 / single32}
-    log(f"[bench] serving, all submitted at once: {closed['batched']['throughput_req_s']:.2f} requests/s batched, "
-        f"{closed['unbatched']['throughput_req_s']:.2f} unbatched, {closed['single_stream_req_s']:.2f} single-stream")
     return {"form": "continuous batching, fp32 smoother + fp64 refinement to 1e-8",
             "requests": len(problems),
             "mix": (f"n in {sizes} (x6 Kuhn tets), N_t in {horizons}, p_t in (0, 1), "
                     "block-random sigma in [1e-2,1e4], nu in [1e-3,100], Gaussian rhs (seeded)"),
-            "arrivals": f"Poisson, {rate:.3f} requests/s = 0.8x single-stream capacity",
+            "arrivals": f"Poisson, {rate:.3f} requests/s = 0.8x the saturated throughput of the same mix",
             "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_s": st["mean_s"],
             "throughput_req_s": st["throughput_req_s"], "throughput_dof_updates_s": st["throughput_dofs"],
             "single_stream_s_per_request": {"fp32_refined": single32, "fp64": single64, "requests": k},
@@ -414,18 +421,29 @@ def core_box(args):
     for form, prec in (("fp64", stmg.FP64), ("fp32_refined", stmg.FP32_REFINED)):
         log(f"[core box] setup {form} n={n} Nt={Nt}")
         t0 = time.perf_counter()
-        s = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec, factor_transpose=args.core_box_transpose)
+        try:
+            s = stmg.Solver(prob, rtol=1e-8, max_cycles=100, precision=prec,
+                            factor_transpose=args.core_box_transpose)
+        except stmg.StmgError as e:
+            # refused by the device-memory estimate (or out of memory)
+            out["forms"][form] = {"refused": str(e), "code": e.code, "after_s": time.perf_counter() - t0}
+            log(f"[core box] {form}: {e}")
+            continue
         setup_s = time.perf_counter() - t0
         if "levels" not in out:
             out["levels"] = [{"mesh": li.mesh, "N": li.N, "lambda": li.lambda_, "n_e": li.n_e}
                              for li in (s.level_info(l) for l in range(s.n_levels))]
             rhs = torch.from_numpy(inputs.gaussian_rhs(s.n_edges, Nt, pt, seed=2)).cuda()
+        info = stmg.Info()
+        stmg.lib().stmg_info(s._h, stmg.C.byref(info))
+        out["forms"].setdefault(form, {})
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, rep = s.solve(rhs, allow_notconv=True)
         torch.cuda.synchronize()
         solve_s = time.perf_counter() - t0
-        out["forms"][form] = {"setup_s": setup_s, "cycles": rep["cycles"], "time_to_1e-8_s": solve_s,
+        out["forms"][form] = {"setup_s": setup_s, "device_bytes": info.device_bytes,
+                              "factor_bytes": info.factor_bytes, "cycles": rep["cycles"], "time_to_1e-8_s": solve_s,
                               "ms_per_cycle": 1e3 * solve_s / max(1, rep["cycles"]),
                               "final_rel_res": rep["rel_res"], "converged": rep["status"] == stmg.STMG_OK,
                               "history": rep["history"]}
@@ -460,6 +478,8 @@ def main():
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-threads", type=int, default=4)
     ap.add_argument("--serve-only", action="store_true", help="only the serving-form measurement")
+    ap.add_argument("--serve-closed", type=int, default=1,
+                    help="also measure the saturated (closed-loop) throughput, batched and unbatched")
     ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
                     help="first run one plain device copy of this many MiB (read + write), so that "
                          "hardware byte counters can be scaled by a kernel of known traffic")
@@ -473,6 +493,8 @@ def main():
     ap.add_argument("--two-lambda", action="store_true",
                     help="only the full Two-lambda table (section 5.2): 7 values of nu2 x 8 of lambda")
     ap.add_argument("--two-lambda-cycles", type=int, default=100)
+    ap.add_argument("--nodal-steps", type=int, default=3,
+                    help="also measure the form with inexact nodal solves (k Chebyshev steps; 0 skips)")
     ap.add_argument("--no-two-lambda", action="store_true",
                     help="skip the Two-lambda subset of the default run")
     ap.add_argument("--core-box", type=int, default=0, metavar="N",
@@ -653,6 +675,34 @@ def main():
             f"({tts32:.2f}s)")
         s32.close()
 
+    inexact = None
+    if args.nodal_steps > 0:
+        # inexact nodal solves (section 5): k Chebyshev steps instead of the
+        # exact K_n solve, same workload and FP64 form; no nodal factor
+        torch.cuda.empty_cache()
+        log(f"[bench] setup with inexact nodal solves ({args.nodal_steps} Chebyshev steps)")
+        t0 = time.perf_counter()
+        sc = stmg.Solver(prob, rtol=1e-8, max_cycles=100, nodal=args.nodal_steps, device_factor=dev_factor)
+        setup_c = time.perf_counter() - t0
+        sc.load(rhs)
+        sc.cycles(args.warmup)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sc.cycles(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_c = e0.elapsed_time(e1) / args.steps
+        t = time.perf_counter()
+        _, rep_c = sc.solve(rhs)
+        torch.cuda.synchronize()
+        tts_c = time.perf_counter() - t
+        inexact = {"nodal": f"{args.nodal_steps} Jacobi-preconditioned Chebyshev steps", "value": dofs / (ms_c * 1e-3),
+                   "ms_per_step": ms_c, "time_to_1e-8_s": tts_c, "cycles_to_1e-8": rep_c["cycles"],
+                   "final_rel_res": rep_c["rel_res"], "setup_s": setup_c}
+        log(f"[bench] inexact nodal: {ms_c:.2f} ms per V-cycle, 1e-8 in {rep_c['cycles']} cycles ({tts_c:.2f}s), "
+            f"setup {setup_c:.1f}s")
+        sc.close()
+
     out = {
         "metric": "space-time DOF-updates/s per V-cycle",
         "value": dofs / (ms * 1e-3),
@@ -670,6 +720,8 @@ def main():
     }
     if prec:
         out["precision_form"] = prec
+    if inexact:
+        out["inexact_nodal_form"] = inexact
     if not args.no_serving:
         torch.cuda.empty_cache()
         out["serving_form"] = serving_bench(args)

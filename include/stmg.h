@@ -69,9 +69,14 @@ enum {
 
 enum { STMG_FP64 = 0, STMG_FP32_REFINED = 1 };
 enum { STMG_BC_DIRICHLET = 0, STMG_BC_NEUMANN = 1 };
-/* Nodal solve of the auxiliary correction (eq. (8)): K_n^{-1} applied
- * exactly with its Cholesky factor, as the analysis of section 4.1 assumes. */
-enum { STMG_NODAL_EXACT = 0 };
+/* Nodal solve of the auxiliary correction (eq. (8)). STMG_NODAL_EXACT:
+ * K_n^{-1} applied exactly with its Cholesky factor, as the analysis of
+ * section 4.1 assumes. k in 1..STMG_NODAL_CHEBYSHEV_MAX: no nodal factor;
+ * K_n^{-1} replaced by k steps of the Jacobi-preconditioned Chebyshev
+ * iteration from zero on [lmax / 30, lmax], lmax the Gershgorin bound of
+ * D^{-1} K_n (the inexact spatial solves of section 5). The V-cycle stays a
+ * fixed linear iteration with the same fixed point; its rate changes. */
+enum { STMG_NODAL_EXACT = 0, STMG_NODAL_CHEBYSHEV_MAX = 16 };
 /* Smoother sequences (section 4) of the steps S (damped block Jacobi,
  * eq. (2)) and A (nodal auxiliary correction, eq. (8)). A name reads like a
  * product of matrices, right to left: before the coarse-grid correction SA
@@ -140,7 +145,7 @@ typedef struct {
   int32_t gemm_splitk;           /* solve K split: 0 auto, -1 never, k >= 2 forced k-way (testing) */
   int32_t device_factor;         /* numeric factorisation: -1 (default) on the GPU when the finest slab
                                     factor has >= 1e6 entries, else on the host; 1 GPU; 0 host */
-  int32_t nodal;                 /* STMG_NODAL_EXACT (the only value accepted) */
+  int32_t nodal;                 /* STMG_NODAL_EXACT, or k Chebyshev steps (1..16) for K_n^{-1} */
 } stmg_options;
 
 typedef struct {

@@ -782,6 +782,72 @@ void launch_gradT(int32_t n_v, int32_t W, const int64_t *ptr, const int32_t *edg
     hipLaunchKernelGGL((k_gradT<R, 1>), grid, dim3(BLOCK), 0, s, n_v, W, ptr, edge, sign, r, g);
 }
 
+// One step of the Jacobi-preconditioned Chebyshev iteration for K y = g on
+// all W columns of every row (K symmetric in CSR over the rows' numbering,
+// dinv = 1 / diag K); a thread per row and packet of P values, as k_gradT:
+//   first step (y null): d = b dinv g, y_out = d;
+//   later steps:         d = a d + b dinv (g - K y), y_out = y + d.
+template <typename R, int P>
+__global__ __launch_bounds__(BLOCK) void k_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *col,
+                                                     const R *val, const R *dinv, const R *g, const R *y, R *d,
+                                                     R *y_out, R a, R b) {
+  using PK = Pack<R, P>;
+  using V = typename PK::type;
+  const int32_t WP = W / P;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= (int64_t)n * WP) return;
+  const int32_t v = (int32_t)(i / WP), c = (int32_t)(i % WP) * P;
+  const int64_t off = (int64_t)v * W + c;
+  const V gv = *reinterpret_cast<const V *>(g + off);
+  const R di = dinv[v];
+  V dv, yo;
+  if (!y) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const R dd = b * di * PK::get(gv, t);
+      PK::set(dv, t, dd);
+      PK::set(yo, t, dd);
+    }
+  } else {
+    R acc[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) acc[t] = 0;
+    const int64_t k1 = ptr[v + 1];
+#pragma unroll 4
+    for (int64_t k = ptr[v]; k < k1; ++k) {
+      const V xv = *reinterpret_cast<const V *>(y + (int64_t)col[k] * W + c);
+      const R kv = val[k];
+#pragma unroll
+      for (int t = 0; t < P; ++t) acc[t] += kv * PK::get(xv, t);
+    }
+    const V d0 = *reinterpret_cast<const V *>(d + off);
+    const V y0 = *reinterpret_cast<const V *>(y + off);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const R dd = a * PK::get(d0, t) + b * di * (PK::get(gv, t) - acc[t]);
+      PK::set(dv, t, dd);
+      PK::set(yo, t, PK::get(y0, t) + dd);
+    }
+  }
+  *reinterpret_cast<V *>(d + off) = dv;
+  *reinterpret_cast<V *>(y_out + off) = yo;
+}
+
+template <typename R>
+void launch_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *col, const R *val, const R *dinv,
+                      const R *g, const R *y, R *d, R *y_out, double a, double b, hipStream_t s) {
+  const int P = W % 2 == 0 ? 2 : 1;
+  const int64_t nt = (int64_t)n * (W / P);
+  if (nt == 0) return;
+  const dim3 grid((unsigned)((nt + BLOCK - 1) / BLOCK));
+  if (P == 2)
+    hipLaunchKernelGGL((k_cheb_step<R, 2>), grid, dim3(BLOCK), 0, s, n, W, ptr, col, val, dinv, g, y, d, y_out,
+                       (R)a, (R)b);
+  else
+    hipLaunchKernelGGL((k_cheb_step<R, 1>), grid, dim3(BLOCK), 0, s, n, W, ptr, col, val, dinv, g, y, d, y_out,
+                       (R)a, (R)b);
+}
+
 // Inverse of the time operator on the gradient subspace (K_t on the diagonal,
 // -N_t below), per vertex row, in place:
 //   q = 1: y_n = sum_{m <= n} g_m (the running sum of eq. (8));
@@ -1125,7 +1191,9 @@ void launch_add_float(int64_t n, const float *x, double *y, hipStream_t s) {
                                    const double *, const R *, R *, hipStream_t);                          \
   template void launch_prolong_add<R>(int32_t, int32_t, int32_t, const int64_t *, const int32_t *,         \
                                       const double *, const R *, R *, hipStream_t);                       \
-  template void launch_fill<R>(R *, int64_t, double, hipStream_t);
+  template void launch_fill<R>(R *, int64_t, double, hipStream_t);                                         \
+  template void launch_cheb_step<R>(int32_t, int32_t, const int64_t *, const int32_t *, const R *, const R *,  \
+                                    const R *, const R *, R *, R *, double, double, hipStream_t);
 VEC_INST(double)
 VEC_INST(float)
 #undef VEC_INST

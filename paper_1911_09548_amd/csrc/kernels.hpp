@@ -103,6 +103,14 @@ template <typename R>
 void launch_grad_add(int32_t n_e, int32_t W, const int32_t *head, const int32_t *tail, const R *y, R *x,
                      hipStream_t s);
 
+// One step of the Jacobi-preconditioned Chebyshev iteration for K y = g over
+// all W columns of each row (K symmetric in CSR, dinv = 1 / diag K): with y
+// null, d = b dinv g and y_out = d; otherwise d = a d + b dinv (g - K y) and
+// y_out = y + d (y_out distinct from y).
+template <typename R>
+void launch_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *col, const R *val, const R *dinv,
+                      const R *g, const R *y, R *d, R *y_out, double a, double b, hipStream_t s);
+
 // Space-time transfers. P_s given as CSR (rows: coarse for restrict = P^T,
 // fine for prolong = P); the identity when ptr == nullptr (same mesh).
 template <typename R>

@@ -534,7 +534,21 @@ void setup_mesh_host(stmg_handle *h, MeshData &md) {
   const bool has_nodal = T.n_int_verts() > 0;
   if (has_nodal) {
     md.sym_v = symbolic_from_tree(md.nd, vertex_nodes(T, md.nd), S.Kn);
-    if (dev_factor(h)) {
+    if (h->opt.nodal > 0) {
+      // no factor: K_n itself, for the Chebyshev iteration
+      md.Knp = csr_permute_sym(S.Kn, md.sym_v.perm);
+      double lmax = 0.0;
+      for (int32_t r = 0; r < md.Knp.n_rows; ++r) {
+        double sum = 0.0, diag = 0.0;
+        for (int64_t k = md.Knp.ptr[r]; k < md.Knp.ptr[r + 1]; ++k) {
+          sum += std::fabs(md.Knp.val[k]);
+          if (md.Knp.col[k] == r) diag = md.Knp.val[k];
+        }
+        STMG_REQUIRE(diag > 0.0, STMG_ENUMERIC, "nodal matrix with a non-positive diagonal entry");
+        lmax = std::max(lmax, sum / diag);
+      }
+      md.kn_lmax = lmax;
+    } else if (dev_factor(h)) {
       build_front_plan(md.sym_v, S.Kn, md.fp_v);
     } else {
       md.nodal_host = std::make_unique<HostFactor<double>>();
@@ -621,7 +635,22 @@ void setup_mesh_device(stmg_handle *h, MeshData &md) {
     for (int32_t r = 0; r < ne; ++r) abi[r] = T.int_edges[md.sym_e.perm[r]];
     md.d_map_abi = dev_upload(h, abi);
   }
-  if (has_nodal) {
+  if (has_nodal && h->opt.nodal > 0) {
+    const Csr &A = md.Knp;
+    std::vector<double> dinv(A.n_rows, 0.0);
+    for (int32_t r = 0; r < A.n_rows; ++r)
+      for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
+        if (A.col[k] == r) dinv[r] = 1.0 / A.val[k];
+    md.d_kn_ptr = dev_upload(h, A.ptr);
+    md.d_kn_col = dev_upload(h, A.col);
+    md.d_kn_val = dev_upload(h, A.val);
+    md.d_kn_dinv = dev_upload(h, dinv);
+    if (h->opt.precision == STMG_FP32_REFINED) {
+      std::vector<float> v32(A.val.begin(), A.val.end()), d32(dinv.begin(), dinv.end());
+      md.d_kn_val32 = dev_upload(h, v32);
+      md.d_kn_dinv32 = dev_upload(h, d32);
+    }
+  } else if (has_nodal) {
     build_plan(h, md.sym_v, md.nodal);
     if (dev_factor(h)) {
       factor_into<double, float>(h, md.sym_v, md.fp_v, S.Kn.val, md.nodal, true, true,
@@ -755,10 +784,12 @@ void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
     L.z = dev_alloc<double>(h, ne * W);
     L.u = dev_alloc<double>(h, std::max<int64_t>(1, L.slab.u_rows * W));
   }
+  const bool cheb = h->opt.nodal > 0;
   if (!prec && nv > 0) {
     L.g = dev_alloc<double>(h, nv * W);
     L.zn = dev_alloc<double>(h, nv * W);
-    L.un = dev_alloc<double>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
+    L.un = dev_alloc<double>(h, std::max<int64_t>(1, (cheb ? nv : md.nodal.u_rows) * W));
+    if (cheb) L.yn = dev_alloc<double>(h, nv * W);
   }
   if (prec && first && last) {
     L.xe = dev_alloc<double>(h, ne * W);
@@ -773,7 +804,8 @@ void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
     if (nv > 0) {
       L.g32 = dev_alloc<float>(h, nv * W);
       L.zn32 = dev_alloc<float>(h, nv * W);
-      L.un32 = dev_alloc<float>(h, std::max<int64_t>(1, md.nodal.u_rows * W));
+      L.un32 = dev_alloc<float>(h, std::max<int64_t>(1, (cheb ? nv : md.nodal.u_rows) * W));
+      if (cheb) L.yn32 = dev_alloc<float>(h, nv * W);
     }
   }
 }
@@ -794,6 +826,9 @@ struct Bufs<double> {
   static double *g(LevelData &L) { return L.g; }
   static double *zn(LevelData &L) { return L.zn; }
   static double *un(LevelData &L) { return L.un; }
+  static double *yn(LevelData &L) { return L.yn; }
+  static const double *knval(MeshData &m) { return m.d_kn_val; }
+  static const double *kndinv(MeshData &m) { return m.d_kn_dinv; }
   static const double *mval(MeshData &m) { return m.d_mval; }
   static const double *kval(MeshData &m) { return m.d_kval; }
   static const double *gval(MeshData &m) { return m.d_gval; }
@@ -810,6 +845,9 @@ struct Bufs<float> {
   static float *g(LevelData &L) { return L.g32; }
   static float *zn(LevelData &L) { return L.zn32; }
   static float *un(LevelData &L) { return L.un32; }
+  static float *yn(LevelData &L) { return L.yn32; }
+  static const float *knval(MeshData &m) { return m.d_kn_val32; }
+  static const float *kndinv(MeshData &m) { return m.d_kn_dinv32; }
   static const float *mval(MeshData &m) { return m.d_mval32; }
   static const float *kval(MeshData &m) { return m.d_kval32; }
   static const float *gval(MeshData &m) { return m.d_gval32; }
@@ -929,12 +967,46 @@ struct OpsT {
     const double sz = sizeof(R);
     timed("k_gradT", sz * w * ((double)ne(l) + nv(l)),
           [&] { launch_gradT<R>(nv(l), w, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, B::w(L), B::g(L), s); });
-    const FactorDev &F = B::fac(md.nodal);
-    solve_forward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), B::un(L), s);
-    solve_backward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), s);
-    timed("k_time_scan", 2.0 * sz * w * nv(l), [&] { launch_time_scan<R>(nv(l), L.N, h->q, B::g(L), s); });
+    R *y = nodal_solve(l);
+    timed("k_time_scan", 2.0 * sz * w * nv(l), [&] { launch_time_scan<R>(nv(l), L.N, h->q, y, s); });
     timed("k_grad_add", sz * w * ((double)nv(l) + 2.0 * ne(l)),
-          [&] { launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, B::g(L), x, s); });
+          [&] { launch_grad_add<R>(ne(l), w, md.d_head, md.d_tail, y, x, s); });
+  }
+
+  // y = K_n^{-1} g for every column of g (level l's g buffer): exactly with
+  // the factor, in place; or (option nodal = k > 0) k steps of the
+  // Jacobi-preconditioned Chebyshev iteration on [lmax / 30, lmax], lmax the
+  // Gershgorin bound of D^{-1} K_n (section 5's inexact spatial solves).
+  // Returns the buffer that holds y.
+  R *nodal_solve(int l) {
+    LevelData &L = h->levels[l];
+    MeshData &md = mesh(l);
+    const int32_t w = W(l);
+    if (h->opt.nodal <= 0) {
+      const FactorDev &F = B::fac(md.nodal);
+      solve_forward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), B::un(L), s);
+      solve_backward<R>(F, md.nodal.plan, w, B::g(L), B::zn(L), s);
+      return B::g(L);
+    }
+    const double lmax = md.kn_lmax, lmin = lmax / 30.0;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    R *ya = B::un(L), *yb = B::yn(L), *d = B::zn(L);
+    const double bytes = sizeof(R) * (double)w * nv(l);
+    timed("k_cheb_step", 3.0 * bytes, [&] {
+      launch_cheb_step<R>(nv(l), w, md.d_kn_ptr, md.d_kn_col, B::knval(md), B::kndinv(md), B::g(L), nullptr, d,
+                          ya, 0.0, 1.0 / theta, s);
+    });
+    for (int i = 1; i < h->opt.nodal; ++i) {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      timed("k_cheb_step", 5.0 * bytes, [&] {
+        launch_cheb_step<R>(nv(l), w, md.d_kn_ptr, md.d_kn_col, B::knval(md), B::kndinv(md), B::g(L), ya, d, yb,
+                            rho_new * rho, 2.0 * rho_new / delta, s);
+      });
+      std::swap(ya, yb);
+      rho = rho_new;
+    }
+    return ya;
   }
 
   // The handle's smoother of S and A steps (section 4). Its name reads like
@@ -1105,6 +1177,10 @@ struct GroupOps {
   }
 
   void nodal_A(int l) {
+    if (ops[0].h->opt.nodal > 0) {  // inexact nodal solves: per member
+      for (auto &o : ops) o.nodal_A(l, B::x(lev(o, l)), B::b(lev(o, l)));
+      return;
+    }
     std::vector<SolveMember<R>> m;
     for (auto &o : ops) {
       if (o.nv(l) == 0) continue;
@@ -1158,7 +1234,8 @@ struct GroupOps {
 // precision form and smoother sequence (so the same steps in the same order).
 bool same_cycle_shape(const stmg_handle *a, const stmg_handle *b) {
   return a->Nt == b->Nt && a->pt == b->pt && a->opt.precision == b->opt.precision &&
-         a->opt.smoother == b->opt.smoother && a->levels.size() == b->levels.size();
+         a->opt.smoother == b->opt.smoother && a->opt.nodal == b->opt.nodal &&
+         a->levels.size() == b->levels.size();
 }
 
 // One iteration of every member on stream s; ||b - L x||^2 into each
@@ -1407,8 +1484,8 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   STMG_REQUIRE(smoother_sequence(h->opt.smoother) != nullptr, STMG_EINVAL, "unknown smoother sequence");
   STMG_REQUIRE(h->opt.precision == STMG_FP64 || h->opt.precision == STMG_FP32_REFINED, STMG_EINVAL,
                "unknown precision form");
-  STMG_REQUIRE(h->opt.nodal == STMG_NODAL_EXACT, STMG_EINVAL,
-               "nodal must be STMG_NODAL_EXACT (the nodal matrix is factored exactly)");
+  STMG_REQUIRE(h->opt.nodal >= 0 && h->opt.nodal <= STMG_NODAL_CHEBYSHEV_MAX, STMG_EINVAL,
+               "nodal must be STMG_NODAL_EXACT (0) or a number of Chebyshev steps 1..16");
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
   STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                "gemm_rows must be 0, 32 or 64");
@@ -1481,8 +1558,12 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
     const int64_t nent = (int64_t)md.gent.size() / 2;
     bytes += nent * (8 + RES_GROUP * 2 * (8 + (prec ? 4 : 0))) + 4 * (int64_t)md.gptr.size();
     bytes += 4 * (int64_t)(md.tile_ptr.size() + md.tile_cols.size()) + 2 * (int64_t)md.lcol.size();
-    const int64_t pn = md.sym_v.panel_entries;
-    bytes += pn * 8 * 2 + (prec ? pn * 4 * 2 : 0);
+    if (h->opt.nodal > 0) {
+      bytes += md.Knp.nnz() * (4 + 8 + (prec ? 4 : 0)) + (8 + 8 + (prec ? 4 : 0)) * (nv + 1);
+    } else {
+      const int64_t pn = md.sym_v.panel_entries;
+      bytes += pn * 8 * 2 + (prec ? pn * 4 * 2 : 0);
+    }
   }
   for (size_t l = 0; l < h->levels.size(); ++l) {
     const LevelData &L = h->levels[l];
@@ -1494,9 +1575,10 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
     if (need32(h, L)) bytes += pe * scal / 2;
     const int64_t urow = md.sym_e.rptr[md.sym_e.ns];
     const bool last = l + 1 == h->levels.size();
-    if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + md.sym_v.rptr[md.sym_v.ns]);
+    const int64_t nodal_extra = h->opt.nodal > 0 ? 2 * nv : md.sym_v.rptr[md.sym_v.ns];
+    if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + nodal_extra);
     if (prec) {
-      bytes += 4 * W * (4 * ne + urow + 2 * nv + md.sym_v.rptr[md.sym_v.ns]);
+      bytes += 4 * W * (4 * ne + urow + 2 * nv + nodal_extra);
       if (l == 0 || last) bytes += 8 * W * 3 * ne;
       if (last) bytes += 8 * W * (ne + urow);
       if (l == 0 && last) bytes += 8 * W * 2 * ne;
@@ -1517,7 +1599,8 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
       temp = std::max(temp, t);
     };
     for (const auto &md : h->meshes)
-      if (md.S->topo.n_int_verts() > 0) factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false);
+      if (md.S->topo.n_int_verts() > 0 && h->opt.nodal <= 0)
+        factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false);
     for (const auto &L : h->levels) {
       const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
       factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L));
@@ -1646,6 +1729,17 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
       int ndev = 0;
       hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
       STMG_REQUIRE(ndev > 0, STMG_EHIP, "no HIP device");
+      // refuse before allocating when the device cannot hold the handle
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      const int64_t need = estimate_device_bytes(h);
+      if (need > (int64_t)free_b) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "the handle needs about %.1f GB of device memory, %.1f GB are free",
+                 need / 1e9, free_b / 1e9);
+        fail(STMG_ENOMEM, msg);
+      }
+      if (verbose()) fprintf(stderr, "[stmg] estimated device bytes %.2f GB (free %.2f GB)\n", need / 1e9, free_b / 1e9);
       setup_device_phase(h, static_cast<hipStream_t>(stream));
     }
   });

@@ -75,6 +75,14 @@ struct MeshData {
   double *d_p_val = nullptr;
   std::unique_ptr<HostFactor<double>> nodal_host;
   DevFactor nodal;
+  // inexact nodal solves (option nodal > 0): K_n in the internal vertex
+  // numbering, its inverse diagonal and the Gershgorin bound of D^{-1} K_n
+  Csr Knp;
+  double kn_lmax = 0.0;
+  int64_t *d_kn_ptr = nullptr;
+  int32_t *d_kn_col = nullptr;
+  double *d_kn_val = nullptr, *d_kn_dinv = nullptr;
+  float *d_kn_val32 = nullptr, *d_kn_dinv32 = nullptr;
 };
 
 struct LevelData {
@@ -89,6 +97,8 @@ struct LevelData {
   double *g = nullptr, *zn = nullptr, *un = nullptr;
   float *x32 = nullptr, *b32 = nullptr, *w32 = nullptr, *z32 = nullptr, *u32 = nullptr;
   float *g32 = nullptr, *zn32 = nullptr, *un32 = nullptr;
+  double *yn = nullptr;          // second iterate buffer of the inexact nodal solve
+  float *yn32 = nullptr;
   // precision form with one level (N_t = 1): the FP64 coarsest solve's own
   // iterate and right-hand side, apart from the outer x and b of level 0
   double *xe = nullptr, *be = nullptr;

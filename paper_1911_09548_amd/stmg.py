@@ -19,6 +19,7 @@ STMG_OK, STMG_EINVAL, STMG_ENOMEM, STMG_ENOTCONV, STMG_ENUMERIC, STMG_EHIP, STMG
 FP64, FP32_REFINED = 0, 1
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 NODAL_EXACT = 0
+NODAL_CHEBYSHEV_MAX = 16
 BCS = {"dirichlet": BC_DIRICHLET, "neumann": BC_NEUMANN}
 SMOOTH_SAS, SMOOTH_S_ONLY, SMOOTH_SA, SMOOTH_AS, SMOOTH_SSA, SMOOTH_ASS, SMOOTH_SSAS, SMOOTH_SSASS = range(8)
 SMOOTHERS = {"SAS": SMOOTH_SAS, "SS": SMOOTH_S_ONLY, "SA": SMOOTH_SA, "AS": SMOOTH_AS, "SSA": SMOOTH_SSA,

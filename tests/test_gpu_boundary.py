@@ -78,3 +78,23 @@ def test_injected_device_allocation_failures_release_memory():
         assert rep["rel_res"] <= 1e-8
     finally:
         gpu.close()
+
+
+def test_setup_refuses_before_allocating_beyond_free_memory():
+    """A handle whose estimated device bytes exceed the free device memory
+    (12^3 mesh, 2^19 slabs: hundreds of GB of vectors) is refused with
+    STMG_ENOMEM by the estimate, before any device allocation."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=12, Nt=2 ** 19, pt=1, seed=23, block_hexes=4)
+    print("\n[case] 12^3 x 2^19 slabs: refused by the estimate", flush=True)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    stmg.debug_fail_alloc(0)
+    with pytest.raises(stmg.StmgError) as e:
+        stmg.Solver(prob, device_factor=0)
+    n_alloc = stmg.debug_fail_alloc(0)
+    assert e.value.code == stmg.STMG_ENOMEM and "free" in str(e.value), e.value
+    torch.cuda.synchronize()
+    assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
+    print(f"[enomem] {e.value}; host-phase allocation points {n_alloc}")

@@ -233,7 +233,15 @@ def test_boundary_condition_and_nodal_values(stmg):
     bad_bc.bc = "neumann"
     assert _setup_rc(stmg, bad_bc) == stmg.STMG_OK
     assert _setup_rc(stmg, good, nodal=stmg.NODAL_EXACT) == stmg.STMG_OK
-    assert _setup_rc(stmg, good, nodal=1) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, nodal=1) == stmg.STMG_OK
+    assert _setup_rc(stmg, good, nodal=stmg.NODAL_CHEBYSHEV_MAX) == stmg.STMG_OK
+    assert _setup_rc(stmg, good, nodal=stmg.NODAL_CHEBYSHEV_MAX + 1) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, nodal=-1) == stmg.STMG_EINVAL
+    # inexact nodal solves keep no nodal factor
+    h = stmg.Solver(inputs.config_unit_manufactured(2, 4, 1), host_only=1, nodal=3)
+    with pytest.raises(stmg.StmgError):
+        h.export_factor(0, 1)
+    h.close()
     # an out-of-range bc value through the raw struct
     keep = []
     p = stmg._marshal_problem(good, keep)
