@@ -146,6 +146,9 @@ typedef struct {
   int32_t device_factor;         /* numeric factorisation: -1 (default) on the GPU when the finest slab
                                     factor has >= 1e6 entries, else on the host; 1 GPU; 0 host */
   int32_t nodal;                 /* STMG_NODAL_EXACT, or k Chebyshev steps (1..16) for K_n^{-1} */
+  int32_t graph;                 /* 1 (default): stmg_cycles and stmg_solve capture one iteration as a HIP
+                                    graph at first use and replay it (bitwise the same iterates); 0: launch
+                                    every kernel each cycle. Launches are eager while profiling. */
 } stmg_options;
 
 typedef struct {

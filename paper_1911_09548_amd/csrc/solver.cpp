@@ -20,6 +20,8 @@ void alloc_point(const char *what);
 
 namespace {
 
+constexpr int GRAPH_NORM_SLOT = 8192;  // d_scalar[0..8191]: norms of stmg_cycles; [8192]: the graph's
+
 thread_local std::string g_err;
 
 // Failure injection (stmg_debug_fail_alloc): allocation points counted
@@ -1273,6 +1275,56 @@ void group_iteration(const std::vector<stmg_handle *> &hs, hipStream_t s, int sl
 
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
+// ------------------------------------------------------- graph replay
+// The launches of one iteration are the same in every cycle (same buffers,
+// shapes and arguments), so they are captured once on a private stream into
+// a HIP graph and replayed on the handle's stream: the launch sequence goes
+// to the device in one call, and the iterate is bitwise that of the eager
+// launches. The iteration holds no memory set or copy nodes; its norm goes
+// to d_scalar[GRAPH_NORM_SLOT].
+void drop_graph(stmg_handle *h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
+}
+
+bool use_graph(const stmg_handle *h) { return h->opt.graph != 0 && !h->prof_state.on; }
+
+void capture_iteration(stmg_handle *h) {
+  if (h->graph_exec) return;
+  if (!h->graph_stream) hip_check(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking), "hipStreamCreate");
+  hipStream_t user = h->stream;
+  h->stream = h->graph_stream;
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(h->graph_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    solver_iteration(h, h->d_scalar + GRAPH_NORM_SLOT);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->graph_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    h->stream = user;
+    throw;
+  }
+  h->stream = user;
+  hip_check(hipStreamEndCapture(h->graph_stream, &g), "hipStreamEndCapture");
+  const hipError_t e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, "hipGraphInstantiate");
+}
+
+// One iteration on the handle's stream, replayed from the graph or launched
+// eagerly; the squared residual norm ends in dst (device).
+void run_iteration(stmg_handle *h, double *dst) {
+  if (!use_graph(h)) {
+    solver_iteration(h, dst);
+    return;
+  }
+  capture_iteration(h);
+  hip_check(hipGraphLaunch(h->graph_exec, h->stream), "hipGraphLaunch");
+  if (dst != h->d_scalar + GRAPH_NORM_SLOT)
+    hip_check(hipMemcpyAsync(dst, h->d_scalar + GRAPH_NORM_SLOT, sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+              "copy");
+}
+
 void set_profiler(stmg_handle *h, bool on) {
   Profiler *p = on ? &h->prof : nullptr;
   for (auto &L : h->levels) L.slab.plan.prof = p;
@@ -1350,6 +1402,11 @@ void apply_op(stmg_handle *h, int level, int op_code, R *t0, R *t1, R *t2) {
 
 void destroy_handle(stmg_handle *h) {
   if (!h) return;
+  if (h->graph_exec || h->graph_stream) {
+    (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
+  }
   if (!h->prof_state.recs.empty() || !h->prof_state.pool.empty()) (void)hipStreamSynchronize(h->stream);
   for (auto &r : h->prof_state.recs) {
     (void)hipEventDestroy(r.a);
@@ -1656,7 +1713,7 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
   h->n_partial = residual_blocks(h->space[0].topo.n_int_edges(), L0.N * h->q, h->q, 1) + 4096;  // any chunk
   h->d_partial = dev_alloc<double>(h, h->n_partial);
   h->d_halo = dev_alloc<double>(h, 2 * (size_t)h->space[0].topo.n_int_edges() + 64);
-  h->d_scalar = dev_alloc<double>(h, 8192);
+  h->d_scalar = dev_alloc<double>(h, GRAPH_NORM_SLOT + 1);
   hip_check(hipStreamSynchronize(stream), "setup");
   h->setup_s += wall_time() - t0;
 }
@@ -1717,6 +1774,7 @@ void stmg_default_options(stmg_options *o) {
   o->gemm_splitk = 0;
   o->device_factor = -1;
   o->nodal = STMG_NODAL_EXACT;
+  o->graph = 1;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -1829,7 +1887,7 @@ int stmg_cycles(stmg_handle *h, int32_t n_cycles, double *res_host) {
   return guard([&] {
     require_device(h);
     STMG_REQUIRE(n_cycles >= 0 && n_cycles <= 8192, STMG_EINVAL, "n_cycles out of range");
-    for (int32_t i = 0; i < n_cycles; ++i) solver_iteration(h, h->d_scalar + i);
+    for (int32_t i = 0; i < n_cycles; ++i) run_iteration(h, h->d_scalar + i);
     check_launch();
     if (res_host && n_cycles > 0) {
       std::vector<double> r2(n_cycles);
@@ -2005,7 +2063,7 @@ int stmg_solve(stmg_handle *h, const double *rhs_dev, const double *u0_dev, cons
     if (bn > 0.0) {
       status = STMG_ENOTCONV;
       for (int32_t c = 0; c < h->opt.max_cycles; ++c) {
-        solver_iteration(h, h->d_scalar);
+        run_iteration(h, h->d_scalar);
         check_launch();
         double r2 = 0.0;
         hip_check(hipMemcpyAsync(&r2, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
@@ -2177,6 +2235,10 @@ int stmg_set_stream_tuning(stmg_handle *h, int32_t stream_chunk, int32_t row_sch
                  "row_schedule needs the space-filling curve chosen at setup");
     h->opt.stream_chunk = stream_chunk;
     h->opt.row_schedule = row_schedule;
+    if (h->graph_exec) {  // the captured launches used the old shape
+      hip_check(hipStreamSynchronize(h->stream), "sync");
+      drop_graph(h);
+    }
   });
 }
 

@@ -153,6 +153,11 @@ struct stmg_handle {
   stmg::Profiler prof;
   int32_t cycles = 0;
   double rel_res = 0.0;
+  // one iteration captured as a HIP graph (option graph), replayed by
+  // stmg_cycles and stmg_solve; its squared residual norm lands in
+  // d_scalar[GRAPH_NORM_SLOT]
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t graph_stream = nullptr;   // the capture stream
   int device = -1;                      // HIP device current at setup
   double *noalloc_scratch = nullptr;    // that device's copy of the no-allocation scratch array
 };

@@ -52,7 +52,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("host_only", C.c_int32), ("stream_chunk", C.c_int32), ("row_schedule", C.c_int32),
                 ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32), ("factor_transpose", C.c_int32),
-                ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32), ("nodal", C.c_int32)]
+                ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32), ("nodal", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class Report(C.Structure):

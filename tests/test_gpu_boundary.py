@@ -98,3 +98,40 @@ def test_setup_refuses_before_allocating_beyond_free_memory():
     torch.cuda.synchronize()
     assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
     print(f"[enomem] {e.value}; host-phase allocation points {n_alloc}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_equals_eager_launches(precision):
+    """Iterations replayed from the captured HIP graph give bitwise the
+    iterates and residual norms of eager launches, over several replays with
+    eager work (a residual, a layout conversion) and synchronisations between
+    them, and in stmg_solve."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=8, Nt=32, pt=1, seed=24, block_hexes=4)
+    print(f"\n[case] graph replay, 8^3 x 32, precision {precision}", flush=True)
+    rng = np.random.default_rng(6)
+    solvers = {g: stmg.Solver(prob, precision=precision, graph=g) for g in (1, 0)}
+    try:
+        b = _dev(rng.standard_normal((prob.Nt, 2, solvers[0].n_edges)))
+        got = {}
+        for g, s in solvers.items():
+            s.load(b)
+            seq = []
+            for k in (1, 3, 2):
+                h = s.cycles(k)
+                x = s.store().clone()
+                r = s.residual(x, b)          # eager work between replays
+                torch.cuda.synchronize()
+                seq.append((h, x, r))
+            x_solve, rep = s.solve(b)
+            torch.cuda.synchronize()
+            got[g] = (seq, x_solve.clone(), rep["history"])
+        for (hg, xg, rg), (he, xe, re_) in zip(got[1][0], got[0][0]):
+            assert np.array_equal(hg, he)
+            assert torch.equal(xg, xe) and torch.equal(rg, re_)
+        assert torch.equal(got[1][1], got[0][1]) and got[1][2] == got[0][2]
+        print(f"[graph] {len(got[1][2])} solve cycles, replays bitwise equal to eager launches")
+    finally:
+        for s in solvers.values():
+            s.close()
