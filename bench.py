@@ -234,7 +234,8 @@ def _source_sha():
 def _kernel_key(name):
     """rocprofv3 kernel name -> the profiler's instantiation name."""
     import re
-    n = name.split("(")[0].replace("void ", "").replace("stmg::", "").replace(" ", "")
+    n = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("stmg::", "")
+    n = n.replace(" ", "")
     m = re.match(r"k_sn_gemm<(\w+),(\d+),(\d+),(\d)>", n)
     if m:
         return f"k_sn_gemm<{m.group(1)},{m.group(2)},{m.group(3)},{['fwd', 'bwd', 'bwdT'][int(m.group(4))]}>"
@@ -285,6 +286,68 @@ def pmc_summary(fetch_csv, write_csv):
     for k, (n, tot) in rows[:20]:
         wn, wt = w.get(k, [1, 0.0])
         print(f"traffic {k} {tot / n * sf * 1024:.0f} {wt / max(wn, 1) * sw * 1024:.0f} {sha}")
+
+
+def stats_summary(stats_csv, top=24):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv):
+    calls, total and average duration per kernel, with the library
+    profiler's names beside rocprofv3's."""
+    import csv
+    rows = []
+    for r in csv.DictReader(open(stats_csv)):
+        rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+                     float(r.get("Percentage", 0.0))))
+    rows.sort(key=lambda t: -t[2])
+    cycle = ("k_sn_gemm", "k_sn_reduce", "k_residual", "k_fwd_asm", "k_slab_", "k_grad", "k_time_scan",
+             "k_restrict", "k_prolong", "k_sum", "k_to_", "k_add_float", "k_fill", "k_cheb")
+    for title, sel in (("Kernels of the V-cycle", lambda k: k.startswith(cycle)),
+                       ("Other kernels (setup: numeric factorisation, uploads, layout changes)",
+                        lambda k: not k.startswith(cycle))):
+        print(f"### {title}\n")
+        print("| kernel (rocprofv3) | profiler name | calls | total ms | avg us | % of GPU time |")
+        print("|---|---|---|---|---|---|")
+        for name, calls, tot, avg, pct in [r for r in rows if sel(_kernel_key(r[0]))][:top]:
+            short = name if len(name) < 70 else name[:67] + "..."
+            key = _kernel_key(name)
+            key = key if len(key) < 48 else key[:45] + "..."
+            print(f"| `{short}` | `{key}` | {calls} | {tot:.2f} | {avg:.2f} | {pct:.2f} |")
+        print()
+
+
+def sq_summary(sq_csv, cache_csv, top=14):
+    """Shader and cache counters per kernel from two rocprofv3 --pmc runs:
+    MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 1024
+    SIMDs); waves per SIMD = 4 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 x 1024);
+    issue wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; L2 hit = TCC_HIT /
+    (TCC_HIT + TCC_MISS). Sums over each kernel's dispatches."""
+    import collections
+    import csv
+
+    def load(path):
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        disp = collections.defaultdict(set)
+        for r in csv.DictReader(open(path)):
+            k = _kernel_key(r["Kernel_Name"])
+            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+        return agg, disp
+
+    sq, disp = load(sq_csv)
+    cache, _ = load(cache_csv)
+    rows = sorted(sq.items(), key=lambda kv: -kv[1].get("GRBM_GUI_ACTIVE", 0.0))
+    print("| kernel | dispatches | MFMA busy % | waves per SIMD | issue wait % | L2 hit % | LDS bank conflicts |")
+    print("|---|---|---|---|---|---|---|")
+    for k, c in rows[:top]:
+        active = c.get("GRBM_GUI_ACTIVE", 0.0) / 8.0 * 1024.0
+        if active <= 0:
+            continue
+        mfma = 100.0 * c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / active
+        waves = 4.0 * c.get("SQ_WAVE_CYCLES", 0.0) / active
+        wait = 100.0 * c.get("SQ_WAIT_INST_ANY", 0.0) / max(c.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        h = cache.get(k, {})
+        hit = 100.0 * h.get("TCC_HIT_sum", 0.0) / max(h.get("TCC_HIT_sum", 0.0) + h.get("TCC_MISS_sum", 0.0), 1.0)
+        print(f"| `{k}` | {len(disp[k])} | {mfma:.1f} | {waves:.1f} | {wait:.1f} | {hit:.1f} | "
+              f"{c.get('SQ_LDS_BANK_CONFLICT', 0.0):.0f} |")
 
 
 def recorded_traffic(kernel):
@@ -483,6 +546,10 @@ def main():
     ap.add_argument("--hbm-calibrate", type=int, default=0, metavar="MiB",
                     help="first run one plain device copy of this many MiB (read + write), so that "
                          "hardware byte counters can be scaled by a kernel of known traffic")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("SQ_CSV", "CACHE_CSV"),
+                    help="summarise the shader and cache counter runs (no GPU work)")
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
+                    help="summarise a rocprofv3 --stats kernel table (no GPU work)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 counter runs (no GPU work)")
     ap.add_argument("--rate-sweep", action="store_true",
@@ -509,6 +576,12 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.stats_summary:
+        stats_summary(args.stats_summary)
+        return
+    if args.sq_summary:
+        sq_summary(*args.sq_summary)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
