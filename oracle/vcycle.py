@@ -19,6 +19,7 @@ Vectors are arrays of shape (N, q, n_e): slab, DG component, interior edge.
   after the coarse-grid correction with the same steps in reversed order:
   the pre-smoother applies the name's letters from the last to the first,
   the post-smoother from the first to the last.
+* Inexact slab solves (slab_solver="twogrid:k"): see SlabSolverTwoGrid.
 * Inexact nodal solves (section 5 solves the spatial problems approximately,
   with a few preconditioned iterations): with nodal_cheb = k > 0 the K_n^{-1}
   of the nodal correction is replaced by k steps of the Chebyshev iteration
@@ -112,14 +113,78 @@ def chebyshev_solve(A, g, k, bounds=None):
     return y
 
 
+class SlabSolverTwoGrid:
+    """Inexact slab solve (section 5 solves the spatial problems with a few
+    preconditioned iterations): k steps of preconditioned Richardson
+    iteration from zero, z <- z + B (w - A z), for the spatial operator of
+    the slab (A = mu M + tau K with mu = 2 + i sqrt(2) for degree 1, after the
+    diagonalisation of the slab's time block; A = M + tau K for degree 0).
+    B is one two-grid cycle on the nested meshes: `sweeps` sweeps of a hybrid
+    smoother (a damped edge Jacobi step with diag(A), then a Jacobi step on
+    the gradients of the nodal space, whose Galerkin operator is
+    G^T A G = mu K_n because K G = 0), the correction with the exact solve of
+    the Galerkin coarse operator P^T A P = mu M_c + tau K_c, and the same
+    sweeps with their steps in reversed order.
+    """
+
+    def __init__(self, space, coarse, pt, tau, k, omega_e=0.5, sweeps=2):
+        self.pt, self.k, self.omega, self.sweeps = pt, k, omega_e, sweeps
+        self.mu = (2.0 + 1j * np.sqrt(2.0)) if pt == 1 else 1.0
+        dt = np.complex128 if pt == 1 else np.float64
+        self.A = sp.csr_matrix(self.mu * space.M + tau * space.K, dtype=dt)
+        self.dinv = 1.0 / self.A.diagonal()
+        self.G = sp.csr_matrix(space.G)
+        self.dn = self.mu * space.Kn.diagonal()
+        self.P = sp.csr_matrix(coarse.Pe)
+        Ac = sp.csc_matrix(self.mu * coarse.M + tau * coarse.K, dtype=dt)
+        self.lu_c = spla.splu(Ac)
+
+    def _nodal(self, r, z):
+        y = (self.G.T @ (r - self.A @ z)) / self.dn[:, None]
+        return z + self.G @ y
+
+    def _edge(self, r, z):
+        return z + self.omega * self.dinv[:, None] * (r - self.A @ z)
+
+    def precondition(self, r):
+        """One two-grid cycle B r (columns of r are right-hand sides)."""
+        z = np.zeros_like(r)
+        for _ in range(self.sweeps):
+            z = self._nodal(r, self._edge(r, z))
+        z = z + self.P @ self.lu_c.solve(np.ascontiguousarray(self.P.T @ (r - self.A @ z)))
+        for _ in range(self.sweeps):
+            z = self._edge(r, self._nodal(r, z))
+        return z
+
+    def solve_spatial(self, w):
+        z = np.zeros_like(w)
+        for _ in range(self.k):
+            z = z + self.precondition(w - self.A @ z)
+        return z
+
+    def solve(self, r):  # r: (N, q, n) real slab residuals
+        s2 = np.sqrt(2.0)
+        if self.pt == 1:
+            w = (0.5 + 1j * s2 / 4) * r[:, 0] - (3j * s2 / 4) * r[:, 1]      # (N, n)
+            z = self.solve_spatial(np.ascontiguousarray(w.T)).T
+            out = np.empty_like(r)
+            out[:, 0] = 2.0 * z.real
+            out[:, 1] = 2.0 * (z.real - s2 * z.imag)
+            return out
+        z = self.solve_spatial(np.ascontiguousarray(r[:, 0].T)).T
+        return z[:, None, :].copy()
+
+
 class Level:
-    def __init__(self, spec, space, pt, slab_solver="real", nodal_cheb=0):
+    def __init__(self, spec, space, pt, slab_solver="real", nodal_cheb=0, coarse_space=None):
         self.spec, self.space, self.pt = spec, space, pt
         self.q = pt + 1
         self.N, self.tau = spec.N, spec.tau
         self.Kt, self.Mt, self.Nt = time_matrices(pt, self.tau)
         M, K = space.M, space.K
-        if slab_solver == "complex" and pt == 1:
+        if slab_solver.startswith("twogrid:") and coarse_space is not None:
+            self.slab = SlabSolverTwoGrid(space, coarse_space, pt, self.tau, int(slab_solver.split(":")[1]))
+        elif slab_solver == "complex" and pt == 1:
             self.slab = SlabSolverComplex(M, K, self.tau)
         else:
             self.slab = SlabSolverReal(M, K, self.Kt, self.Mt)
@@ -222,7 +287,14 @@ class SpaceTimeMultigrid:
         self.smoother = smoother
         self.space = space_levels if space_levels is not None else build_space_levels(problem)
         self.specs = build_level_specs(self.space, problem.T, problem.Nt, lambda_crit, allow_space)
-        self.levels = [Level(s, self.space[s.space], problem.pt, slab_solver, nodal_cheb) for s in self.specs]
+        # inexact slab solves ("twogrid:k") use the next coarser mesh; a level
+        # on the coarsest mesh, and the one-slab coarsest level, solve exactly
+        def coarse_of(spec):
+            if spec.N == 1 or spec.space + 1 >= len(self.space):
+                return None
+            return self.space[spec.space + 1]
+        self.levels = [Level(s, self.space[s.space], problem.pt, slab_solver, nodal_cheb, coarse_of(s))
+                       for s in self.specs]
         self.Pt = time_prolongation(problem.pt)
         self.fine = self.space[0]
 

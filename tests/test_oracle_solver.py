@@ -315,3 +315,55 @@ def test_inexact_nodal_vcycle_converges_to_direct_solution(pt):
     xd = direct_solve(s, b)
     assert hist[-1] <= 1e-12
     assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def _twogrid(pt, k=3, box=False):
+    from oracle.vcycle import SlabSolverTwoGrid
+    prob = (inputs.config_core_box(n=8, Nt=2, pt=pt, seed=3, jitter=0.2) if box else
+            inputs.config_block_random(n=8, Nt=2, pt=pt, seed=11, block_hexes=4))
+    s = SpaceTimeMultigrid(prob)
+    return s, SlabSolverTwoGrid(s.space[0], s.space[1], pt, s.levels[0].tau, k)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_twogrid_slab_solve_converges_to_the_slab_solve(pt):
+    """Preconditioned Richardson with the two-grid cycle converges to the
+    exact spatial solve (SuperLU of mu M + tau K); 3 steps reduce the error
+    below 0.2, also on the high-contrast jittered case."""
+    import scipy.sparse.linalg as spla
+    for box in (False, True):
+        s, tg = _twogrid(pt, box=box)
+        rng = np.random.default_rng(7)
+        n = s.fine.n_e
+        w = rng.standard_normal((n, 3)) + (1j * rng.standard_normal((n, 3)) if pt else 0)
+        exact = spla.splu(tg.A.tocsc()).solve(w)
+        tg.k = 150
+        assert np.linalg.norm(tg.solve_spatial(w) - exact) <= 1e-10 * np.linalg.norm(exact)
+        tg.k = 3
+        assert np.linalg.norm(tg.solve_spatial(w) - exact) <= 0.2 * np.linalg.norm(exact)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_twogrid_cycle_is_symmetric(pt):
+    """The two-grid cycle B (smoother, coarse correction, smoother in reversed
+    order) is symmetric in the bilinear form u^T B v, as A = mu M + tau K is:
+    a step out of order or a transposed transfer breaks it."""
+    s, tg = _twogrid(pt)
+    rng = np.random.default_rng(8)
+    n = s.fine.n_e
+    u = rng.standard_normal((n, 1)) + (1j * rng.standard_normal((n, 1)) if pt else 0)
+    v = rng.standard_normal((n, 1)) + (1j * rng.standard_normal((n, 1)) if pt else 0)
+    a, b = (u.T @ tg.precondition(v)).item(), (v.T @ tg.precondition(u)).item()
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1e-300)
+
+
+@pytest.mark.parametrize("pt", [0, 1])
+def test_twogrid_vcycle_converges_to_direct_solution(pt):
+    prob = inputs.config_block_random(n=4, Nt=8, pt=pt, seed=11, block_hexes=2)
+    s = SpaceTimeMultigrid(prob, slab_solver="twogrid:3")
+    assert any(type(lev.slab).__name__ == "SlabSolverTwoGrid" for lev in s.levels)
+    b = np.random.default_rng(9).standard_normal((8, pt + 1, s.fine.n_e))
+    x, hist = s.solve(b, rtol=1e-12, max_cycles=200)
+    assert hist[-1] <= 1e-12
+    xd = direct_solve(s, b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
