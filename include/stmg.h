@@ -355,7 +355,8 @@ typedef struct {
   int32_t max_active;            /* requests on the GPU at once (default 16) */
   int32_t setup_threads;         /* host setup workers (default 4) */
   int32_t batch;                 /* 1 (default): due iterations of requests with the same N_t, p_t,
-                                    precision form and smoother run batched (stmg_cycles_batched's
+                                    precision form, smoother and nodal solve, and finest interior edge
+                                    counts within a factor of 2, run batched (stmg_cycles_batched's
                                     merged solves, up to 8 requests, on a shared stream); 0: never */
 } stmg_server_options;
 typedef struct {

@@ -1727,7 +1727,15 @@ void iteration(stmg_handle *h, double *dst_norm2) {
   solver_iteration(h, dst_norm2);
   check_launch();
 }
-bool batchable(const stmg_handle *a, const stmg_handle *b) { return same_cycle_shape(a, b); }
+// The server batches only requests of similar work per iteration (finest
+// interior edge counts within a factor of 2): a batch ends when its largest
+// member does, so a small request batched with a much larger one would wait
+// for it every iteration.
+bool batchable(const stmg_handle *a, const stmg_handle *b) {
+  if (!same_cycle_shape(a, b)) return false;
+  const int64_t ea = a->space[0].topo.n_int_edges(), eb = b->space[0].topo.n_int_edges();
+  return ea <= 2 * eb && eb <= 2 * ea;
+}
 void batched_iteration(const std::vector<stmg_handle *> &hs, hipStream_t s) {
   group_iteration(hs, s, 0);
   check_launch();

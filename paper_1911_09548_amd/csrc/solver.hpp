@@ -170,8 +170,9 @@ stmg_handle *setup_host(const stmg_problem *prob, const stmg_options *opt);  // 
 int64_t estimate_bytes(const stmg_handle *h);                                // device bytes the next phase needs
 void setup_device(stmg_handle *h, hipStream_t stream);                       // uploads on `stream`
 void iteration(stmg_handle *h, double *dst_norm2);                          // enqueue one iteration on h->stream
-// Handles whose iterations can run batched, and one batched iteration on
-// stream s (each member's squared residual norm into its d_scalar[0]).
+// Handles the server batches (the same cycle shape and similar work per
+// iteration), and one batched iteration on stream s (each member's squared
+// residual norm into its d_scalar[0]).
 bool batchable(const stmg_handle *a, const stmg_handle *b);
 void batched_iteration(const std::vector<stmg_handle *> &hs, hipStream_t s);
 void destroy(stmg_handle *h);
