@@ -77,6 +77,19 @@ enum { STMG_BC_DIRICHLET = 0, STMG_BC_NEUMANN = 1 };
  * D^{-1} K_n (the inexact spatial solves of section 5). The V-cycle stays a
  * fixed linear iteration with the same fixed point; its rate changes. */
 enum { STMG_NODAL_EXACT = 0, STMG_NODAL_CHEBYSHEV_MAX = 16 };
+/* Slab solves of the smoother (eq. (2)). STMG_SLAB_EXACT: A^{-1} applied
+ * exactly with the slab factor of the level's mesh. k in
+ * 1..STMG_SLAB_TWOGRID_MAX: on levels with N > 1 whose mesh has a coarser
+ * one, A z = w (A = mu M + tau K after the diagonalisation of the slab's time
+ * block: mu = 2 + i sqrt(2) for p_t = 1, 1 for p_t = 0) is solved inexactly
+ * (section 5) by k steps of Richardson iteration from zero, z <- z + B (w -
+ * A z), B one two-grid cycle: two sweeps of [a damped edge Jacobi step,
+ * omega 1/2, with diag(A); a Jacobi step on the gradients G y with
+ * diag(mu K_n), the Galerkin operator G^T A G = mu K_n], the exact solve of
+ * the Galerkin coarse operator P^T A P = mu M_c + tau K_c with the coarser
+ * mesh's factor, and the two sweeps with their steps reversed. The V-cycle
+ * stays a fixed linear iteration with the same fixed point. */
+enum { STMG_SLAB_EXACT = 0, STMG_SLAB_TWOGRID_MAX = 16 };
 /* Smoother sequences (section 4) of the steps S (damped block Jacobi,
  * eq. (2)) and A (nodal auxiliary correction, eq. (8)). A name reads like a
  * product of matrices, right to left: before the coarse-grid correction SA
@@ -149,6 +162,12 @@ typedef struct {
   int32_t graph;                 /* 1 (default): stmg_cycles and stmg_solve capture one iteration as a HIP
                                     graph at first use and replay it (bitwise the same iterates); 0: launch
                                     every kernel each cycle. Launches are eager while profiling. */
+  int32_t slab;                  /* STMG_SLAB_EXACT (default), or k (1..16): the slab solves of every level
+                                    with N > 1 whose mesh has a coarser one (problem.meshes[mesh + 1]) are
+                                    replaced by k steps of Richardson iteration from zero, each preconditioned
+                                    by one two-grid cycle on the two meshes (section 5 solves the spatial
+                                    problems inexactly); such a level keeps the slab factor of the coarser
+                                    mesh only. Plain FP64 form only (STMG_EINVAL with STMG_FP32_REFINED). */
 } stmg_options;
 
 typedef struct {
@@ -182,6 +201,10 @@ typedef struct {
   int64_t factor_nnz_slab_struct;  /* structural nonzeros of the slab factor L (column counts of the
                                       elimination tree; the zeros of dense supernode blocks excluded) */
   int64_t factor_nnz_nodal_struct; /* the same for the nodal factor */
+  int32_t slab_factor_mesh;      /* mesh of the slab factor the level keeps: `mesh` (exact slab solves) or
+                                    mesh + 1 (inexact ones, option slab); the slab factor fields above
+                                    describe that factor */
+  int32_t slab_steps;            /* 0: exact slab solves; k: k two-grid Richardson steps */
 } stmg_level_info_t;
 
 typedef struct stmg_handle stmg_handle;

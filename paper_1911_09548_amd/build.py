@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libstmg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["space.cpp", "ordering.cpp", "factor.cpp"]
-HIP_SOURCES = ["kernels.hip", "factor_dev.hip", "solver.cpp", "server.cpp"]  # .cpp here: host code using the HIP runtime
+HIP_SOURCES = ["kernels.hip", "twogrid.hip", "factor_dev.hip", "solver.cpp", "server.cpp"]  # .cpp here: host code using the HIP runtime
 
 
 def _hipcc() -> str:

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <type_traits>
 #include <cstring>
 
 using namespace stmg;
@@ -704,7 +705,7 @@ bool slab_transpose(const stmg_handle *h, const LevelData &L) {
   if (h->opt.factor_transpose == 1) return true;
   int64_t total = 0;
   for (const auto &l : h->levels) {
-    const MeshData &md = h->meshes[h->mesh_slot[l.mesh]];
+    const MeshData &md = h->meshes[h->mesh_slot[l.fmesh]];
     total += md.sym_e.panel_entries * (h->pt == 1 ? 16 : 8);
   }
   return total <= (int64_t)40 << 30 || L.N <= 16;
@@ -721,7 +722,7 @@ bool need32(const stmg_handle *h, const LevelData &L) {
 }
 
 void setup_level_factor_host(stmg_handle *h, LevelData &L) {
-  MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+  MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
   const SpaceLevel &S = *md.S;
   const int64_t nnz = S.M.nnz();
   if (h->pt == 1) {
@@ -739,7 +740,7 @@ void setup_level_factor_host(stmg_handle *h, LevelData &L) {
 }
 
 void setup_level_factor_device(stmg_handle *h, LevelData &L) {
-  MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+  MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
   build_plan(h, md.sym_e, L.slab);
   if (dev_factor(h)) {
     const SpaceLevel &S = *md.S;
@@ -769,6 +770,47 @@ void setup_level_factor_device(stmg_handle *h, LevelData &L) {
   }
 }
 
+// Diagonals of the two-grid smoother in the internal numberings: 1 / A_ii,
+// A = mu M + tau K, per edge, and 1 / (mu (K_n)_vv) per vertex (complex
+// pairs for DG degree 1, mu = 2 + i sqrt(2); real for degree 0, mu = 1).
+void upload_twogrid_diagonals(stmg_handle *h, LevelData &L, const MeshData &md) {
+  const int32_t ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
+  const bool cpx = h->pt == 1;
+  const double mre = cpx ? 2.0 : 1.0, mim = cpx ? std::sqrt(2.0) : 0.0;
+  auto inv = [&](double re, double im, double *out) {
+    if (!cpx) {
+      out[0] = 1.0 / re;
+      return;
+    }
+    const double d = re * re + im * im;
+    out[0] = re / d;
+    out[1] = -im / d;
+  };
+  const int q = cpx ? 2 : 1;
+  std::vector<double> de((size_t)ne * q), dn((size_t)std::max(nv, 1) * q, 0.0);
+  for (int32_t r = 0; r < ne; ++r) {
+    double m = 0.0, k = 0.0;
+    for (int64_t j = md.Mp.ptr[r]; j < md.Mp.ptr[r + 1]; ++j)
+      if (md.Mp.col[j] == r) {
+        m = md.Mp.val[j];
+        k = md.Kp.val[j];
+      }
+    STMG_REQUIRE(m > 0.0, STMG_ENUMERIC, "mass matrix with a non-positive diagonal entry");
+    inv(mre * m + L.tau * k, mim * m, &de[(size_t)r * q]);
+  }
+  const Csr &Kn = md.S->Kn;
+  for (int32_t r = 0; r < nv; ++r) {
+    const int32_t a = md.sym_v.perm[r];  // internal vertex r -> ascending interior index
+    double kd = 0.0;
+    for (int64_t j = Kn.ptr[a]; j < Kn.ptr[a + 1]; ++j)
+      if (Kn.col[j] == a) kd = Kn.val[j];
+    STMG_REQUIRE(kd > 0.0, STMG_ENUMERIC, "nodal matrix with a non-positive diagonal entry");
+    inv(mre * kd, mim * kd, &dn[(size_t)r * q]);
+  }
+  L.tg_dinv = dev_upload(h, de);
+  L.tg_dn = dev_upload(h, dn);
+}
+
 void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
   MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
   const int64_t ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
@@ -792,6 +834,15 @@ void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
     L.zn = dev_alloc<double>(h, nv * W);
     L.un = dev_alloc<double>(h, std::max<int64_t>(1, (cheb ? nv : md.nodal.u_rows) * W));
     if (cheb) L.yn = dev_alloc<double>(h, nv * W);
+  }
+  if (L.twogrid) {
+    const MeshData &mf = h->meshes[h->mesh_slot[L.fmesh]];
+    if (h->opt.slab > 1) L.tg_r = dev_alloc<double>(h, ne * W);
+    L.tg_a = dev_alloc<double>(h, ne * W);
+    L.tg_b = dev_alloc<double>(h, ne * W);
+    L.tg_t = dev_alloc<double>(h, ne * W);
+    L.tg_c = dev_alloc<double>(h, (int64_t)mf.S->topo.n_int_edges() * W);
+    upload_twogrid_diagonals(h, L, md);
   }
   if (prec && first && last) {
     L.xe = dev_alloc<double>(h, ne * W);
@@ -938,9 +989,20 @@ struct OpsT {
     h->prof.end(s, name, 0.0, bytes);
   }
 
-  // w <- A_l^{-1} w in place (slab right-hand-side layout)
+  // w <- A_l^{-1} w in place (slab right-hand-side layout); inexactly on
+  // levels with two-grid slab solves
   void slab_solve(int l, R *w) {
     LevelData &L = h->levels[l];
+    if (L.twogrid) {
+      if constexpr (std::is_same<R, double>::value) {
+        if (L.slab.is_complex)
+          slab_solve_twogrid<cd>(l, w);
+        else
+          slab_solve_twogrid<double>(l, w);
+        return;
+      }
+      fail(STMG_ENOSYS, "inexact slab solves in the FP32 smoother");
+    }
     const int32_t nc = L.N;
     const FactorDev &F = B::fac(L.slab);
     if (L.slab.is_complex) {
@@ -949,6 +1011,89 @@ struct OpsT {
     } else {
       solve_forward<R>(F, L.slab.plan, nc, w, B::z(L), B::u(L), s);
       solve_backward<R>(F, L.slab.plan, nc, w, B::z(L), s);
+    }
+  }
+
+  // Two-grid slab solve (option slab = k): w <- k steps of Richardson
+  // iteration from zero for A z = w, z <- z + B (w - A z), A = mu M + tau K
+  // on the level's mesh (T = cd: mu = 2 + i sqrt(2); T = double: mu = 1),
+  // one scalar per slab and row. B is one two-grid cycle (section 5's
+  // inexact spatial solves): two sweeps of [damped edge Jacobi, omega 1/2;
+  // Jacobi on the gradients with diag(mu K_n)], the exact solve of
+  // mu M_c + tau K_c on the next coarser mesh between the transfers P^T and
+  // P, then the two sweeps with their steps reversed.
+  template <typename T>
+  void slab_solve_twogrid(int l, double *w_) {
+    LevelData &L = h->levels[l];
+    MeshData &md = mesh(l);
+    MeshData &mc = h->meshes[h->mesh_slot[L.fmesh]];
+    const int32_t n = ne(l), nvl = nv(l), N = L.N, ncl = mc.S->topo.n_int_edges(), wl = W(l);
+    const double tau = L.tau, om = 0.5, sz = sizeof(double);
+    T mu;
+    if constexpr (std::is_same<T, cd>::value)
+      mu = cd{2.0, std::sqrt(2.0)};
+    else
+      mu = 1.0;
+    const T *dinv = (const T *)L.tg_dinv, *dn = (const T *)L.tg_dn;
+    T *w = (T *)w_, *t = (T *)L.tg_t, *c = (T *)L.tg_c;
+    const double vec = sz * wl * n, pat = (double)md.Mp.nnz() * (4 + 8 + 8) + 8.0 * n;
+    // out = r - A z (mode 0); out = z + om dinv (r - A z) (mode 1, out != z,
+    // out may be r); out = om dinv r (mode 2)
+    auto apply = [&](const T *r, const T *z, T *out, int mode) {
+      timed("k_tg_apply", mode == 2 ? 2.0 * vec : 3.0 * vec + pat + (mode == 1 ? sz * wl * n / N : 0.0), [&] {
+        launch_tg_apply<T>(n, N, md.d_ptr, md.d_col, md.d_mval, md.d_kval, mu, tau, dinv, om, r, z, out, mode, s);
+      });
+    };
+    auto nodal = [&](const T *r, T *z) {
+      if (nvl == 0) return;
+      apply(r, z, t, 0);
+      timed("k_gradT", sz * wl * ((double)n + nvl), [&] {
+        launch_gradT<double>(nvl, wl, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, (const double *)t, L.g, s);
+      });
+      timed("k_scale_slabs", 2.0 * sz * wl * nvl, [&] { launch_scale_slabs<T>(nvl, N, dn, (T *)L.g, s); });
+      timed("k_grad_add", sz * wl * ((double)nvl + 2.0 * n),
+            [&] { launch_grad_add<double>(n, wl, md.d_head, md.d_tail, L.g, (double *)z, s); });
+    };
+    auto coarse = [&](const T *r, T *z) {
+      apply(r, z, t, 0);
+      timed("k_csr_slabs", sz * wl * ((double)n + ncl),
+            [&] { launch_csr_slabs<T>(ncl, N, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, t, c, 0, s); });
+      // t is free again: the coarse solve's workspace
+      const FactorDev &F = L.slab.f;
+      solve_forward<T>(F, L.slab.plan, N, c, t, (T *)L.u, s);
+      solve_backward<T>(F, L.slab.plan, N, c, t, s);
+      timed("k_csr_slabs", sz * wl * ((double)ncl + 2.0 * n),
+            [&] { launch_csr_slabs<T>(n, N, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, c, z, 1, s); });
+    };
+    // out <- B r with iterates in a and b; out != a (out may be b or r)
+    auto precondition = [&](const T *r, T *a, T *b, T *out) {
+      apply(r, nullptr, a, 2);
+      nodal(r, a);
+      apply(r, a, b, 1);
+      nodal(r, b);
+      coarse(r, b);
+      nodal(r, b);
+      apply(r, b, a, 1);
+      nodal(r, a);
+      apply(r, a, out, 1);
+    };
+    T *a = (T *)L.tg_a, *b = (T *)L.tg_b, *z = (T *)B::z(L), *rho = (T *)L.tg_r;
+    const int k = h->opt.slab;
+    const int64_t nd = (int64_t)n * wl;
+    if (k == 1) {
+      precondition(w, a, b, w);
+      return;
+    }
+    precondition(w, a, b, z);
+    for (int j = 2; j <= k; ++j) {
+      apply(w, z, rho, 0);
+      if (j < k) {
+        precondition(rho, a, b, b);
+        timed("k_axpy", 3.0 * sz * nd, [&] { launch_axpy(nd, 1.0, (const double *)b, (double *)z, s); });
+      } else {  // the last step writes z + B rho over w
+        precondition(rho, a, b, w);
+        timed("k_axpy", 3.0 * sz * nd, [&] { launch_axpy(nd, 1.0, (const double *)z, (double *)w, s); });
+      }
     }
   }
 
@@ -1146,23 +1291,31 @@ struct GroupOps {
 
   static LevelData &lev(OpsT<R> &o, int l) { return o.h->levels[l]; }
 
+  // exact slab solves merged over the members; two-grid ones member by member
   void slab_solves(int l) {
+    for (auto &o : ops)
+      if (lev(o, l).twogrid) o.slab_solve(l, B::w(lev(o, l)));
     if (lev(ops[0], l).slab.is_complex) {
       std::vector<SolveMember<CX>> m;
       for (auto &o : ops) {
         LevelData &L = lev(o, l);
-        m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, (CX *)B::w(L), (CX *)B::z(L), (CX *)B::u(L)});
+        if (!L.twogrid)
+          m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, (CX *)B::w(L), (CX *)B::z(L), (CX *)B::u(L)});
       }
-      solve_forward_group<CX>(m.data(), (int)m.size(), s);
-      solve_backward_group<CX>(m.data(), (int)m.size(), s);
+      if (!m.empty()) {
+        solve_forward_group<CX>(m.data(), (int)m.size(), s);
+        solve_backward_group<CX>(m.data(), (int)m.size(), s);
+      }
     } else {
       std::vector<SolveMember<R>> m;
       for (auto &o : ops) {
         LevelData &L = lev(o, l);
-        m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, B::w(L), B::z(L), B::u(L)});
+        if (!L.twogrid) m.push_back({&B::fac(L.slab), &L.slab.plan, L.N, B::w(L), B::z(L), B::u(L)});
       }
-      solve_forward_group<R>(m.data(), (int)m.size(), s);
-      solve_backward_group<R>(m.data(), (int)m.size(), s);
+      if (!m.empty()) {
+        solve_forward_group<R>(m.data(), (int)m.size(), s);
+        solve_backward_group<R>(m.data(), (int)m.size(), s);
+      }
     }
   }
 
@@ -1236,7 +1389,7 @@ struct GroupOps {
 // precision form and smoother sequence (so the same steps in the same order).
 bool same_cycle_shape(const stmg_handle *a, const stmg_handle *b) {
   return a->Nt == b->Nt && a->pt == b->pt && a->opt.precision == b->opt.precision &&
-         a->opt.smoother == b->opt.smoother && a->opt.nodal == b->opt.nodal &&
+         a->opt.smoother == b->opt.smoother && a->opt.nodal == b->opt.nodal && a->opt.slab == b->opt.slab &&
          a->levels.size() == b->levels.size();
 }
 
@@ -1543,6 +1696,10 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
                "unknown precision form");
   STMG_REQUIRE(h->opt.nodal >= 0 && h->opt.nodal <= STMG_NODAL_CHEBYSHEV_MAX, STMG_EINVAL,
                "nodal must be STMG_NODAL_EXACT (0) or a number of Chebyshev steps 1..16");
+  STMG_REQUIRE(h->opt.slab >= 0 && h->opt.slab <= STMG_SLAB_TWOGRID_MAX, STMG_EINVAL,
+               "slab must be STMG_SLAB_EXACT (0) or a number of two-grid Richardson steps 1..16");
+  STMG_REQUIRE(h->opt.slab == 0 || h->opt.precision == STMG_FP64, STMG_EINVAL,
+               "inexact slab solves (slab > 0) are built for the plain FP64 form only");
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
   STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                "gemm_rows must be 0, 32 or 64");
@@ -1577,7 +1734,14 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
     h->levels.push_back(std::move(n));
   }
   h->levels.back().lambda = h->space[h->levels.back().mesh].anisotropy(h->levels.back().tau);
-  const int32_t used = h->levels.back().mesh + 1;
+  // meshes 0..used-1 are set up: every level's mesh, and the coarser mesh of
+  // the levels with inexact slab solves
+  int32_t used = h->levels.back().mesh + 1;
+  for (auto &L : h->levels) {
+    L.twogrid = h->opt.slab > 0 && L.N > 1 && L.mesh + 1 < (int32_t)h->space.size();
+    L.fmesh = L.twogrid ? L.mesh + 1 : L.mesh;
+    used = std::max(used, L.fmesh + 1);
+  }
   h->mesh_slot.assign(h->space.size(), -1);
   h->meshes.resize(used);
   if (verbose()) fprintf(stderr, "[stmg] assembly and hierarchy %.2fs\n", wall_time() - t0);
@@ -1625,12 +1789,15 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
   for (size_t l = 0; l < h->levels.size(); ++l) {
     const LevelData &L = h->levels[l];
     const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    const MeshData &mf = h->meshes[h->mesh_slot[L.fmesh]];
     const int64_t W = (int64_t)L.N * h->q, ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
     const int64_t scal = h->pt == 1 ? 16 : 8;
-    const int64_t pe = md.sym_e.panel_entries * (slab_transpose(h, L) ? 2 : 1);
+    const int64_t pe = mf.sym_e.panel_entries * (slab_transpose(h, L) ? 2 : 1);
     if (need64(h, L)) bytes += pe * scal;
     if (need32(h, L)) bytes += pe * scal / 2;
-    const int64_t urow = md.sym_e.rptr[md.sym_e.ns];
+    const int64_t urow = mf.sym_e.rptr[mf.sym_e.ns];
+    if (L.twogrid)  // Richardson residual, smoother iterates, temporary, coarse vector, diagonals
+      bytes += 8 * W * (4 * ne + mf.S->topo.n_int_edges()) + 16 * (ne + nv);
     const bool last = l + 1 == h->levels.size();
     const int64_t nodal_extra = h->opt.nodal > 0 ? 2 * nv : md.sym_v.rptr[md.sym_v.ns];
     if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + nodal_extra);
@@ -1659,7 +1826,7 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
       if (md.S->topo.n_int_verts() > 0 && h->opt.nodal <= 0)
         factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false);
     for (const auto &L : h->levels) {
-      const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+      const MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
       factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L));
     }
     bytes += temp + ((int64_t)128 << 20);
@@ -1783,6 +1950,7 @@ void stmg_default_options(stmg_options *o) {
   o->device_factor = -1;
   o->nodal = STMG_NODAL_EXACT;
   o->graph = 1;
+  o->slab = STMG_SLAB_EXACT;
 }
 
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_handle **out) {
@@ -1836,18 +2004,21 @@ int stmg_level_info(const stmg_handle *h, int32_t level, stmg_level_info_t *info
     STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
     const LevelData &L = h->levels[level];
     const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    const MeshData &mf = h->meshes[h->mesh_slot[L.fmesh]];
     info->mesh = L.mesh;
     info->N = L.N;
     info->tau = L.tau;
     info->n_e = md.S->topo.n_int_edges();
     info->n_v = md.S->topo.n_int_verts();
     info->nnz_pattern = md.S->M.nnz();
-    info->factor_nnz_slab = md.sym_e.nnz_L;
+    info->factor_nnz_slab = mf.sym_e.nnz_L;
     info->factor_nnz_nodal = md.sym_v.nnz_L;
-    info->n_supernodes_slab = md.sym_e.ns;
+    info->n_supernodes_slab = mf.sym_e.ns;
     info->lambda = L.lambda;
-    info->factor_nnz_slab_struct = md.sym_e.nnz_L_struct;
+    info->factor_nnz_slab_struct = mf.sym_e.nnz_L_struct;
     info->factor_nnz_nodal_struct = md.sym_v.nnz_L_struct;
+    info->slab_factor_mesh = L.fmesh;
+    info->slab_steps = L.twogrid ? h->opt.slab : 0;
   });
 }
 
@@ -2295,6 +2466,7 @@ int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32
     STMG_REQUIRE(level >= 0 && level < (int32_t)h->levels.size(), STMG_EINVAL, "level out of range");
     const LevelData &L = h->levels[level];
     const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
+    const MeshData &mf = h->meshes[h->mesh_slot[L.fmesh]];  // of the slab factor the level keeps
     const Symbolic *S = nullptr;
     const std::vector<int64_t> *off = nullptr;
     const double *vals = nullptr;
@@ -2304,7 +2476,7 @@ int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32
     if (!h->opt.host_only) {
       STMG_REQUIRE(which == 0 || which == 1, STMG_EINVAL, "which must be 0 or 1");
       const DevFactor &D = which == 0 ? L.slab : md.nodal;
-      S = which == 0 ? &md.sym_e : &md.sym_v;
+      S = which == 0 ? &mf.sym_e : &md.sym_v;
       STMG_REQUIRE(D.f.panel != nullptr && !D.h_panel_off.empty(), STMG_ENOSYS,
                    "no FP64 factor of this level on the device");
       cpx = which == 0 && D.is_complex ? 1 : 0;
@@ -2319,7 +2491,7 @@ int stmg_export_factor(const stmg_handle *h, int32_t level, int32_t which, int32
         vals = copy.data();
       }
     } else if (which == 0) {
-      S = &md.sym_e;
+      S = &mf.sym_e;
       if (L.slab_host_c) {
         off = &L.slab_host_c->panel_off;
         vals = reinterpret_cast<const double *>(L.slab_host_c->panel.data());

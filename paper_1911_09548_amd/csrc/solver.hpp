@@ -89,6 +89,11 @@ struct LevelData {
   int32_t mesh = 0, N = 0;
   double tau = 0.0;
   double lambda = 0.0;
+  // inexact slab solves (option slab = k > 0, levels with N > 1 whose mesh
+  // has a coarser one): the slab factor below is then the one of the coarser
+  // mesh fmesh = mesh + 1 with this level's tau
+  bool twogrid = false;
+  int32_t fmesh = 0;
   std::unique_ptr<HostFactor<double>> slab_host_r;
   std::unique_ptr<HostFactor<cplx>> slab_host_c;
   DevFactor slab;
@@ -99,6 +104,12 @@ struct LevelData {
   float *g32 = nullptr, *zn32 = nullptr, *un32 = nullptr;
   double *yn = nullptr;          // second iterate buffer of the inexact nodal solve
   float *yn32 = nullptr;
+  // two-grid slab solves: diag(A)^{-1} per internal edge and diag(mu K_n)^{-1}
+  // per internal vertex (complex for DG degree 1), the Richardson residual,
+  // two smoother iterates, a residual temporary (n_e x W values each) and the
+  // coarse vector (coarse n_e x W)
+  double *tg_dinv = nullptr, *tg_dn = nullptr;
+  double *tg_r = nullptr, *tg_a = nullptr, *tg_b = nullptr, *tg_t = nullptr, *tg_c = nullptr;
   // precision form with one level (N_t = 1): the FP64 coarsest solve's own
   // iterate and right-hand side, apart from the outer x and b of level 0
   double *xe = nullptr, *be = nullptr;

@@ -20,6 +20,8 @@ FP64, FP32_REFINED = 0, 1
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 NODAL_EXACT = 0
 NODAL_CHEBYSHEV_MAX = 16
+SLAB_EXACT = 0
+SLAB_TWOGRID_MAX = 16
 BCS = {"dirichlet": BC_DIRICHLET, "neumann": BC_NEUMANN}
 SMOOTH_SAS, SMOOTH_S_ONLY, SMOOTH_SA, SMOOTH_AS, SMOOTH_SSA, SMOOTH_ASS, SMOOTH_SSAS, SMOOTH_SSASS = range(8)
 SMOOTHERS = {"SAS": SMOOTH_SAS, "SS": SMOOTH_S_ONLY, "SA": SMOOTH_SA, "AS": SMOOTH_AS, "SSA": SMOOTH_SSA,
@@ -53,7 +55,7 @@ class Options(C.Structure):
                 ("host_only", C.c_int32), ("stream_chunk", C.c_int32), ("row_schedule", C.c_int32),
                 ("leaf_size", C.c_int32), ("gemm_rows", C.c_int32), ("factor_transpose", C.c_int32),
                 ("gemm_splitk", C.c_int32), ("device_factor", C.c_int32), ("nodal", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("slab", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -71,7 +73,8 @@ class LevelInfo(C.Structure):
                 ("n_v", C.c_int32), ("nnz_pattern", C.c_int64), ("factor_nnz_slab", C.c_int64),
                 ("factor_nnz_nodal", C.c_int64), ("n_supernodes_slab", C.c_int32),
                 ("lambda_", C.c_double), ("factor_nnz_slab_struct", C.c_int64),
-                ("factor_nnz_nodal_struct", C.c_int64)]
+                ("factor_nnz_nodal_struct", C.c_int64), ("slab_factor_mesh", C.c_int32),
+                ("slab_steps", C.c_int32)]
 
 
 class ServerOptions(C.Structure):

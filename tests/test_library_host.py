@@ -340,3 +340,45 @@ def test_structural_factor_counts(stmg, bc):
         assert li.factor_nnz_nodal_struct <= li.factor_nnz_nodal
     finally:
         lib.close()
+
+
+@pytest.mark.parametrize("pt", [1, 0])
+def test_twogrid_levels_keep_the_coarser_factor(stmg, pt):
+    """Option slab = k (inexact slab solves, section 5): exactly the levels
+    with N > 1 whose mesh has a coarser one report k two-grid steps and keep
+    the slab factor of mesh + 1 with their own tau (it solves the Galerkin
+    coarse operator mu M_c + tau K_c of the oracle's coarser mesh); the other
+    levels keep their exact factor."""
+    from oracle.vcycle import SpaceTimeMultigrid
+    prob = inputs.config_block_random(n=4, Nt=8, pt=pt, seed=31, block_hexes=2)
+    ora = SpaceTimeMultigrid(prob)
+    lib = stmg.Solver(prob, host_only=1, slab=2)
+    rng = np.random.default_rng(12)
+    try:
+        n_tg = 0
+        for l, spec in enumerate(ora.specs):
+            li = lib.level_info(l)
+            tg = spec.N > 1 and spec.space + 1 < len(ora.space)
+            n_tg += tg
+            assert (li.slab_steps, li.slab_factor_mesh) == ((2, spec.space + 1) if tg else (0, spec.space))
+            sd = ora.space[li.slab_factor_mesh]
+            mu = (2 + 1j * np.sqrt(2)) if pt == 1 else 1.0
+            A = mu * sd.M + spec.tau * sd.K
+            F = lib.export_factor(l, 0)
+            assert F["perm"].size == sd.n_e
+            b = rng.standard_normal((sd.n_e, 2)) + (1j * rng.standard_normal((sd.n_e, 2)) if pt else 0)
+            x = _apply_factor(F, b)
+            assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b) * 1e2, (l, li.slab_factor_mesh)
+        assert n_tg >= 2
+    finally:
+        lib.close()
+
+
+def test_slab_option_values(stmg):
+    good = inputs.config_unit_manufactured(2, 4, 1)
+    assert _setup_rc(stmg, good, slab=stmg.SLAB_EXACT) == stmg.STMG_OK
+    assert _setup_rc(stmg, good, slab=stmg.SLAB_TWOGRID_MAX) == stmg.STMG_OK
+    assert _setup_rc(stmg, good, slab=stmg.SLAB_TWOGRID_MAX + 1) == stmg.STMG_EINVAL
+    assert _setup_rc(stmg, good, slab=-1) == stmg.STMG_EINVAL
+    # the FP32 smoother has no inexact slab solve
+    assert _setup_rc(stmg, good, slab=2, precision=stmg.FP32_REFINED) == stmg.STMG_EINVAL
