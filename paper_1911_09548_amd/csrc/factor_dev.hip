@@ -46,6 +46,37 @@ void build_front_plan(const Symbolic &S, const Csr &A, FrontPlan &fp) {
     for (int32_t s = 0; s < ns; ++s)
       if (S.parent[s] >= 0) fp.kids[nx[S.parent[s]]++] = s;
   }
+  // The update matrices live on a stack: in post-order the children of a
+  // supernode are the top entries when it is assembled, so they are popped
+  // and its own update is pushed in their place (the extend-adds read them
+  // before the update is written, in stream order). uoff[ns] becomes the
+  // stack's peak. A tree whose subtrees are not contiguous keeps one slot per
+  // update.
+  {
+    std::vector<int64_t> off(ns, 0);
+    int64_t top = 0, peak = 0;
+    bool stack = true;
+    for (int32_t s = 0; s < ns && stack; ++s) {
+      int64_t base = top, kids_sz = 0;
+      for (int32_t q = fp.kid_ptr[s]; q < fp.kid_ptr[s + 1]; ++q) {
+        const int32_t ch = fp.kids[q];
+        const int64_t rc = S.nrows(ch);
+        if (rc == 0) continue;
+        base = std::min(base, off[ch]);
+        kids_sz += rc * rc;
+      }
+      stack = top - base == kids_sz;
+      top = base;
+      off[s] = top;
+      const int64_t r = S.nrows(s);
+      if (S.parent[s] >= 0 && r > 0) top += r * r;
+      peak = std::max(peak, top);
+    }
+    if (stack) {
+      for (int32_t s = 0; s < ns; ++s) fp.uoff[s] = off[s];
+      fp.uoff[ns] = peak;
+    }
+  }
   // update row of s -> row of the parent's front
   fp.relpos.assign(S.rows.size(), 0);
   for (int32_t s = 0; s < ns; ++s) {

@@ -34,7 +34,8 @@ struct FrontPlan {
   std::vector<int64_t> a_pos;    // entry of A -> position in its front (row + col * m)
   std::vector<int64_t> a_k;      // entry of A -> index of its value on A's pattern
   std::vector<int32_t> relpos;   // [rptr[ns]] update row of s -> row of its parent's front
-  std::vector<int64_t> uoff;     // [ns+1] offsets of the r x r update matrices (0 for roots)
+  std::vector<int64_t> uoff;     // [ns+1] offsets of the r x r update matrices on the update stack
+                                 // (post-order reuse); uoff[ns] = the stack's peak in entries
   std::vector<int32_t> kid_ptr;  // [ns+1] children of each supernode
   std::vector<int32_t> kids;
   int64_t max_m2 = 0;            // largest front, entries

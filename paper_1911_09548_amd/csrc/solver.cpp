@@ -1766,9 +1766,21 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
   return h.release();
 }
 
-// Device bytes the device phase will allocate (vectors, factors, patterns),
-// from host data; used by the server's admission control. Plans and small
-// index arrays are covered by a 5% margin.
+// Order of the slab factorisations of the device phase: largest factor
+// first (ties in level order).
+std::vector<size_t> factor_order(const stmg_handle *h) {
+  std::vector<size_t> order(h->levels.size());
+  std::iota(order.begin(), order.end(), size_t(0));
+  auto entries = [&](size_t l) { return h->meshes[h->mesh_slot[h->levels[l].fmesh]].sym_e.panel_entries; };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return entries(a) > entries(b); });
+  return order;
+}
+
+// Peak device bytes of the device phase (vectors, factors, patterns, and the
+// factorisation temporaries alive while the slab factors are computed, in
+// factor_order before any level vector), from host data; used by the setup's
+// refusal and the server's admission control. Plans and small index arrays
+// are covered by a 5% margin.
 int64_t estimate_device_bytes(const stmg_handle *h) {
   const bool prec = h->opt.precision == STMG_FP32_REFINED;
   int64_t bytes = 0;
@@ -1786,6 +1798,8 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
       bytes += pn * 8 * 2 + (prec ? pn * 4 * 2 : 0);
     }
   }
+  const int64_t mesh_bytes = bytes;
+  std::vector<int64_t> level_factor(h->levels.size(), 0);
   for (size_t l = 0; l < h->levels.size(); ++l) {
     const LevelData &L = h->levels[l];
     const MeshData &md = h->meshes[h->mesh_slot[L.mesh]];
@@ -1793,8 +1807,9 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
     const int64_t W = (int64_t)L.N * h->q, ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
     const int64_t scal = h->pt == 1 ? 16 : 8;
     const int64_t pe = mf.sym_e.panel_entries * (slab_transpose(h, L) ? 2 : 1);
-    if (need64(h, L)) bytes += pe * scal;
-    if (need32(h, L)) bytes += pe * scal / 2;
+    if (need64(h, L)) level_factor[l] += pe * scal;
+    if (need32(h, L)) level_factor[l] += pe * scal / 2;
+    bytes += level_factor[l];
     const int64_t urow = mf.sym_e.rptr[mf.sym_e.ns];
     if (L.twogrid)  // Richardson residual, smoother iterates, temporary, coarse vector, diagonals
       bytes += 8 * W * (4 * ne + mf.S->topo.n_int_edges()) + 16 * (ne + nv);
@@ -1812,24 +1827,27 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
   const int64_t v0 = (int64_t)h->meshes[0].S->topo.n_int_edges() * L0.N * h->q * 8;
   bytes += std::min<int64_t>((int64_t)256 << 20, 4 * v0);  // split-K workspace
   if (dev_factor(h)) {
-    // the largest set of factorisation temporaries alive at once (one
-    // factor at a time): front, update-matrix arena, plan arrays, values and
-    // the FP64 panels of a level that keeps only FP32 ones; plus rocBLAS's
-    // own workspace
-    int64_t temp = 0;
+    // factorisation temporaries (one factor at a time): front, update
+    // stack, plan arrays, values and the FP64 panels of a level that keeps
+    // only FP32 ones; plus rocBLAS's own workspace. The nodal factors are
+    // computed with the mesh data, the slab factors after it in factor_order
+    // before any level vector.
     auto factor_temp = [&](const FrontPlan &fp, const Symbolic &S, int64_t nnz, int64_t scal, bool fp64_temp) {
-      const int64_t t = (fp.max_m2 + fp.uoff[S.ns]) * scal + 16 * (int64_t)fp.a_pos.size() +
-                        4 * (int64_t)fp.relpos.size() + nnz * scal + (fp64_temp ? S.panel_entries * scal : 0);
-      temp = std::max(temp, t);
+      return (fp.max_m2 + fp.uoff[S.ns]) * scal + 16 * (int64_t)fp.a_pos.size() + 4 * (int64_t)fp.relpos.size() +
+             nnz * scal + (fp64_temp ? S.panel_entries * scal : 0) + ((int64_t)128 << 20);
     };
+    int64_t peak = 0;
     for (const auto &md : h->meshes)
       if (md.S->topo.n_int_verts() > 0 && h->opt.nodal <= 0)
-        factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false);
-    for (const auto &L : h->levels) {
+        peak = std::max(peak, mesh_bytes + factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false));
+    int64_t done = mesh_bytes;
+    for (size_t l : factor_order(h)) {
+      const LevelData &L = h->levels[l];
       const MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
-      factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L));
+      peak = std::max(peak, done + factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L)));
+      done += level_factor[l];
     }
-    bytes += temp + ((int64_t)128 << 20);
+    bytes = std::max(bytes, peak);
   }
   return bytes + bytes / 20 + (1 << 20);
 }
@@ -1857,13 +1875,16 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
     setup_mesh_device(h, h->meshes[j]);
     if (j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
   }
-  for (size_t l = 0; l < h->levels.size(); ++l) {
+  // every slab factor first, the largest first (its factorisation
+  // temporaries then share the device with the mesh data only), then the
+  // level vectors
+  for (size_t l : factor_order(h)) {
     setup_level_factor_device(h, h->levels[l]);
-    alloc_level_vectors(h, h->levels[l], l == 0);
     if (verbose())
-      fprintf(stderr, "[stmg] level %zu device setup (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
+      fprintf(stderr, "[stmg] level %zu slab factor (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
               wall_time() - t0);
   }
+  for (size_t l = 0; l < h->levels.size(); ++l) alloc_level_vectors(h, h->levels[l], l == 0);
   // split-K partial sums of the backward solves, shared by all factors
   const LevelData &L0 = h->levels[0];
   const int64_t v0 = (int64_t)h->space[0].topo.n_int_edges() * L0.N * h->q * 8;
