@@ -574,6 +574,8 @@ def main():
     ap.add_argument("--two-lambda-cycles", type=int, default=100)
     ap.add_argument("--nodal-steps", type=int, default=3,
                     help="also measure the form with inexact nodal solves (k Chebyshev steps; 0 skips)")
+    ap.add_argument("--slab-steps", type=int, default=2,
+                    help="also measure the form with inexact slab solves (k two-grid Richardson steps; 0 skips)")
     ap.add_argument("--no-two-lambda", action="store_true",
                     help="skip the Two-lambda subset of the default run")
     ap.add_argument("--core-box", type=int, default=0, metavar="N",
@@ -763,14 +765,12 @@ def main():
             f"({tts32:.2f}s)")
         s32.close()
 
-    inexact = None
-    if args.nodal_steps > 0:
-        # inexact nodal solves (section 5): k Chebyshev steps instead of the
-        # exact K_n solve, same workload and FP64 form; no nodal factor
+    def inexact_form(label, key, what, **opts):
+        # the same workload and FP64 form with inexact spatial solves (section 5)
         torch.cuda.empty_cache()
-        log(f"[bench] setup with inexact nodal solves ({args.nodal_steps} Chebyshev steps)")
+        log(f"[bench] setup with inexact {label} solves ({what})")
         t0 = time.perf_counter()
-        sc = stmg.Solver(prob, rtol=1e-8, max_cycles=100, nodal=args.nodal_steps, device_factor=dev_factor)
+        sc = stmg.Solver(prob, rtol=1e-8, max_cycles=100, device_factor=dev_factor, **opts)
         setup_c = time.perf_counter() - t0
         sc.load(rhs)
         sc.cycles(args.warmup)
@@ -784,12 +784,26 @@ def main():
         _, rep_c = sc.solve(rhs)
         torch.cuda.synchronize()
         tts_c = time.perf_counter() - t
-        inexact = {"nodal": f"{args.nodal_steps} Jacobi-preconditioned Chebyshev steps", "value": dofs / (ms_c * 1e-3),
-                   "ms_per_step": ms_c, "time_to_1e-8_s": tts_c, "cycles_to_1e-8": rep_c["cycles"],
-                   "final_rel_res": rep_c["rel_res"], "setup_s": setup_c}
-        log(f"[bench] inexact nodal: {ms_c:.2f} ms per V-cycle, 1e-8 in {rep_c['cycles']} cycles ({tts_c:.2f}s), "
-            f"setup {setup_c:.1f}s")
+        info = stmg.Info()
+        stmg.lib().stmg_info(sc._h, stmg.C.byref(info))
+        res = {key: what, "value": dofs / (ms_c * 1e-3), "ms_per_step": ms_c, "time_to_1e-8_s": tts_c,
+               "cycles_to_1e-8": rep_c["cycles"], "final_rel_res": rep_c["rel_res"], "setup_s": setup_c,
+               "device_bytes": info.device_bytes, "factor_bytes": info.factor_bytes}
+        log(f"[bench] inexact {label}: {ms_c:.2f} ms per V-cycle, 1e-8 in {rep_c['cycles']} cycles ({tts_c:.2f}s), "
+            f"setup {setup_c:.1f}s, factors {info.factor_bytes / 1e9:.2f} GB")
         sc.close()
+        return res
+
+    inexact = inexact_slab = None
+    if args.nodal_steps > 0:
+        # k Chebyshev steps instead of the exact K_n solve; no nodal factor
+        inexact = inexact_form("nodal", "nodal", f"{args.nodal_steps} Jacobi-preconditioned Chebyshev steps",
+                               nodal=args.nodal_steps)
+    if args.slab_steps > 0:
+        # k two-grid Richardson steps instead of the exact slab solves on the
+        # levels whose mesh has a coarser one; those keep the coarser slab factor
+        inexact_slab = inexact_form("slab", "slab", f"{args.slab_steps} Richardson steps with a two-grid cycle",
+                                    slab=args.slab_steps)
 
     out = {
         "metric": "space-time DOF-updates/s per V-cycle",
@@ -810,6 +824,8 @@ def main():
         out["precision_form"] = prec
     if inexact:
         out["inexact_nodal_form"] = inexact
+    if inexact_slab:
+        out["inexact_slab_form"] = inexact_slab
     if not args.no_serving:
         torch.cuda.empty_cache()
         out["serving_form"] = serving_bench(args)

@@ -114,13 +114,15 @@ void launch_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *c
 // Inexact slab solves (two-grid cycle), on slab-solve vectors of N scalars
 // per row (T = cd for DG degree 1, double for degree 0):
 //   launch_tg_apply: mode 0: out = w - (mu M + tau K) z; mode 1: out = z +
-//     omega dinv (w - (mu M + tau K) z) (out distinct from z);
+//     omega dinv (w - (mu M + tau K) z) (out distinct from z, may be w);
+//     mode 2: out = omega dinv w (z unused); rows visited in the order sched
+//     (a permutation of 0..n-1);
 //   launch_csr_slabs: y (+)= P x for a CSR matrix P (add != 0 accumulates);
 //   launch_scale_slabs: y = diag(d) y.
 template <typename T>
-void launch_tg_apply(int32_t n, int32_t N, const int64_t *ptr, const int32_t *col, const double *mval,
-                     const double *kval, T mu, double tau, const T *dinv, double omega, const T *w, const T *z,
-                     T *out, int mode, hipStream_t s);
+void launch_tg_apply(int32_t n, int32_t N, const int32_t *sched, const int64_t *ptr, const int32_t *col,
+                     const double *mval, const double *kval, T mu, double tau, const T *dinv, double omega,
+                     const T *w, const T *z, T *out, int mode, hipStream_t s);
 template <typename T>
 void launch_csr_slabs(int32_t n, int32_t N, const int64_t *ptr, const int32_t *col, const double *val, const T *x,
                       T *y, int add, hipStream_t s);

@@ -1041,7 +1041,8 @@ struct OpsT {
     // out may be r); out = om dinv r (mode 2)
     auto apply = [&](const T *r, const T *z, T *out, int mode) {
       timed("k_tg_apply", mode == 2 ? 2.0 * vec : 3.0 * vec + pat + (mode == 1 ? sz * wl * n / N : 0.0), [&] {
-        launch_tg_apply<T>(n, N, md.d_ptr, md.d_col, md.d_mval, md.d_kval, mu, tau, dinv, om, r, z, out, mode, s);
+        launch_tg_apply<T>(n, N, md.d_sched, md.d_ptr, md.d_col, md.d_mval, md.d_kval, mu, tau, dinv, om, r, z, out,
+                           mode, s);
       });
     };
     auto nodal = [&](const T *r, T *z) {
