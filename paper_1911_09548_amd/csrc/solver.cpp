@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <type_traits>
 #include <cstring>
 
@@ -22,6 +23,7 @@ void alloc_point(const char *what);
 namespace {
 
 constexpr int GRAPH_NORM_SLOT = 8192;  // d_scalar[0..8191]: norms of stmg_cycles; [8192]: the graph's
+constexpr int FACTOR_WORKERS = 8;      // most threads of the parallel slab factorisations in stmg_setup
 
 thread_local std::string g_err;
 
@@ -53,6 +55,13 @@ void hip_check(hipError_t e, const char *what) {
   fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// The stream and rocBLAS handle of setup work in the calling thread: those
+// of a worker thread of the parallel slab factorisation, else the handle's.
+thread_local hipStream_t tl_setup_stream = nullptr;
+thread_local rocblas_handle tl_setup_rb = nullptr;
+hipStream_t setup_stream(const stmg_handle *h) { return tl_setup_stream ? tl_setup_stream : h->stream; }
+rocblas_handle setup_rb(const stmg_handle *h) { return tl_setup_rb ? tl_setup_rb : h->rb; }
+
 // Handles owned by the server allocate stream-ordered (hipMallocAsync on
 // their own stream) so that allocation and release never wait for other
 // requests' work; other handles use hipMalloc.
@@ -65,18 +74,20 @@ T *dev_alloc(stmg_handle *h, size_t count) {
     hip_check(hipMallocAsync(&p, count * sizeof(T), h->stream), "hipMallocAsync");
   else
     hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  std::lock_guard<std::mutex> lock(h->alloc_mu);
   h->bufs.push_back({p, count * sizeof(T)});
   h->device_bytes += (int64_t)(count * sizeof(T));
   return static_cast<T *>(p);
 }
 
-// Copies on the handle's stream and waits for that stream only.
+// Copies on the setup stream and waits for that stream only.
 template <typename T>
 T *dev_upload(stmg_handle *h, const T *src, size_t count) {
   T *p = dev_alloc<T>(h, count);
   if (count) {
-    hip_check(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, h->stream), "upload");
-    hip_check(hipStreamSynchronize(h->stream), "upload");
+    hipStream_t st = setup_stream(h);
+    hip_check(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipStreamSynchronize(st), "upload");
   }
   return p;
 }
@@ -87,12 +98,13 @@ T *dev_upload(stmg_handle *h, const std::vector<T> &v) {
 }
 
 // A device buffer that lives only during setup (released on the handle's
-// stream for stream-ordered handles, after a stream synchronisation
-// otherwise).
+// stream for stream-ordered handles, after a synchronisation of the setup
+// stream otherwise).
 struct DevTemp {
   stmg_handle *h;
+  hipStream_t st;
   void *p = nullptr;
-  DevTemp(stmg_handle *h_, size_t bytes) : h(h_) {
+  DevTemp(stmg_handle *h_, size_t bytes) : h(h_), st(setup_stream(h_)) {
     alloc_point("device setup temporary");
     if (bytes == 0) bytes = 16;
     if (h->stream_ordered)
@@ -103,8 +115,8 @@ struct DevTemp {
   template <typename T>
   DevTemp(stmg_handle *h_, const std::vector<T> &v) : DevTemp(h_, v.size() * sizeof(T)) {
     if (!v.empty()) {
-      hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream), "upload");
-      hip_check(hipStreamSynchronize(h->stream), "upload");
+      hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+      hip_check(hipStreamSynchronize(st), "upload");
     }
   }
   ~DevTemp() {
@@ -112,7 +124,7 @@ struct DevTemp {
     if (h->stream_ordered) {
       (void)hipFreeAsync(p, h->stream);
     } else {
-      (void)hipStreamSynchronize(h->stream);
+      (void)hipStreamSynchronize(st);
       (void)hipFree(p);
     }
   }
@@ -127,6 +139,12 @@ struct DevTemp {
 // Set by the host phase from the device_factor option: large factors are
 // factored on the GPU; small ones (launch-latency bound there) on the host.
 bool dev_factor(const stmg_handle *h) { return h->device_factor_on; }
+
+// Setup progress on stderr (environment STMG_VERBOSE set and not 0).
+bool verbose() {
+  static const bool v = getenv("STMG_VERBOSE") && getenv("STMG_VERBOSE")[0] != '0';
+  return v;
+}
 
 // ------------------------------------------------------------- solve plans
 void build_plan(stmg_handle *h, const Symbolic &S, DevFactor &D) {
@@ -312,6 +330,7 @@ void upload_factor(stmg_handle *h, const Symbolic &S, const HostFactor<TH> &F, D
   D.f32 = D.f;
   D.f32.panel = D.f32.panel_t = nullptr;
   if (need32) upload_panels<T32>(h, S, F, D.f32, transpose, D.factor_bytes);
+  std::lock_guard<std::mutex> lock(h->alloc_mu);
   h->factor_bytes += D.factor_bytes;
 }
 
@@ -334,16 +353,17 @@ void factor_into(stmg_handle *h, const Symbolic &S, const FrontPlan &fp, const s
   DevTemp t_flag(h, sizeof(int32_t));
   DevTemp t_p64(h, need64 ? 0 : (size_t)n * sizeof(T64));
   T64 *p64 = need64 ? dev_alloc<T64>(h, (size_t)n) : t_p64.as<T64>();
-  hip_check(hipMemsetAsync(t_flag.p, 0, sizeof(int32_t), h->stream), "memset");
+  hipStream_t st = setup_stream(h);
+  hip_check(hipMemsetAsync(t_flag.p, 0, sizeof(int32_t), st), "memset");
   FrontPlanDev fd;
   fd.a_pos = t_pos.as<int64_t>();
   fd.a_k = t_k.as<int64_t>();
   fd.relpos = t_rel.as<int32_t>();
   factor_device<T64>(S, fp, fd, off, t_vals.as<T64>(), p64, t_front.as<T64>(), t_arena.as<T64>(),
-                     t_flag.as<int32_t>(), h->rb, h->stream);
+                     t_flag.as<int32_t>(), setup_rb(h), st);
   int32_t bad = 0;
-  hip_check(hipMemcpyAsync(&bad, t_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "copy");
-  hip_check(hipStreamSynchronize(h->stream), "factorisation");
+  hip_check(hipMemcpyAsync(&bad, t_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipStreamSynchronize(st), "factorisation");
   STMG_REQUIRE(bad == 0, STMG_ENUMERIC, "zero or non-finite pivot in factorisation");
   D.factor_bytes = 0;
   D.f.panel = need64 ? p64 : nullptr;
@@ -352,7 +372,7 @@ void factor_into(stmg_handle *h, const Symbolic &S, const FrontPlan &fp, const s
     D.factor_bytes += n * (int64_t)sizeof(T64);
     if (transpose) {
       T64 *pt = dev_alloc<T64>(h, (size_t)n);
-      convert_panels<T64, T64>(p64, nullptr, pt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, h->stream);
+      convert_panels<T64, T64>(p64, nullptr, pt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, st);
       D.f.panel_t = pt;
       D.factor_bytes += n * (int64_t)sizeof(T64);
     }
@@ -361,13 +381,14 @@ void factor_into(stmg_handle *h, const Symbolic &S, const FrontPlan &fp, const s
   D.f32.panel = D.f32.panel_t = nullptr;
   if (need32) {
     T32 *q = dev_alloc<T32>(h, (size_t)n), *qt = transpose ? dev_alloc<T32>(h, (size_t)n) : nullptr;
-    convert_panels<T64, T32>(p64, q, qt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, h->stream);
+    convert_panels<T64, T32>(p64, q, qt, D.f.panel_off, t_width.as<int32_t>(), S.ns, n, st);
     D.f32.panel = q;
     D.f32.panel_t = qt;
     D.factor_bytes += n * (int64_t)sizeof(T32) * (transpose ? 2 : 1);
   }
   hip_check(hipGetLastError(), "kernel launch");
-  hip_check(hipStreamSynchronize(h->stream), "factor conversion");
+  hip_check(hipStreamSynchronize(st), "factor conversion");
+  std::lock_guard<std::mutex> lock(h->alloc_mu);
   h->factor_bytes += D.factor_bytes;
 }
 
@@ -741,7 +762,9 @@ void setup_level_factor_host(stmg_handle *h, LevelData &L) {
 
 void setup_level_factor_device(stmg_handle *h, LevelData &L) {
   MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
+  const double t0 = wall_time();
   build_plan(h, md.sym_e, L.slab);
+  if (verbose()) fprintf(stderr, "[stmg]   solve plan %.3fs\n", wall_time() - t0);
   if (dev_factor(h)) {
     const SpaceLevel &S = *md.S;
     const int64_t nnz = S.M.nnz();
@@ -1486,10 +1509,6 @@ void set_profiler(stmg_handle *h, bool on) {
 }
 
 // Setup progress on stderr when STMG_VERBOSE is set (long factorisations).
-bool verbose() {
-  static const bool v = getenv("STMG_VERBOSE") && getenv("STMG_VERBOSE")[0] != '0';
-  return v;
-}
 
 void require_device(const stmg_handle *h) {
   STMG_REQUIRE(h, STMG_EINVAL, "null handle");
@@ -1842,11 +1861,21 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
       if (md.S->topo.n_int_verts() > 0 && h->opt.nodal <= 0)
         peak = std::max(peak, mesh_bytes + factor_temp(md.fp_v, md.sym_v, md.S->Kn.nnz(), 8, false));
     int64_t done = mesh_bytes;
+    std::vector<int64_t> temps;
     for (size_t l : factor_order(h)) {
       const LevelData &L = h->levels[l];
       const MeshData &md = h->meshes[h->mesh_slot[L.fmesh]];
-      peak = std::max(peak, done + factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L)));
+      temps.push_back(factor_temp(md.fp_e, md.sym_e, md.S->M.nnz(), h->pt == 1 ? 16 : 8, !need64(h, L)));
+      peak = std::max(peak, done + temps.back());
       done += level_factor[l];
+    }
+    if (h->factor_workers > 1) {
+      // parallel factorisations: at worst every factor and the temporaries
+      // of the largest factorisations, one per worker, at once
+      std::sort(temps.begin(), temps.end(), std::greater<int64_t>());
+      int64_t t_sum = 0;
+      for (size_t i = 0; i < temps.size() && i < (size_t)h->factor_workers; ++i) t_sum += temps[i];
+      peak = std::max(peak, done + t_sum);
     }
     bytes = std::max(bytes, peak);
   }
@@ -1876,14 +1905,58 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
     setup_mesh_device(h, h->meshes[j]);
     if (j > 0) setup_transfer(h, h->meshes[j - 1], h->meshes[j]);
   }
+  if (verbose()) fprintf(stderr, "[stmg] mesh data and nodal factors %.2fs\n", wall_time() - t0);
   // every slab factor first, the largest first (its factorisation
-  // temporaries then share the device with the mesh data only), then the
-  // level vectors
-  for (size_t l : factor_order(h)) {
-    setup_level_factor_device(h, h->levels[l]);
-    if (verbose())
-      fprintf(stderr, "[stmg] level %zu slab factor (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
-              wall_time() - t0);
+  // temporaries then share the device with the mesh data and the other
+  // workers' temporaries only), then the level vectors
+  const std::vector<size_t> order = factor_order(h);
+  const int workers = std::min<int>(h->factor_workers, (int)order.size());
+  if (workers <= 1) {
+    for (size_t l : order) {
+      setup_level_factor_device(h, h->levels[l]);
+      if (verbose())
+        fprintf(stderr, "[stmg] level %zu slab factor (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
+                wall_time() - t0);
+    }
+  } else {
+    // the factorisations are sequences of small dependent launches whose
+    // issue dominates their time: workers with a stream and a rocBLAS handle
+    // each take the next level in `order` until none is left
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> errs(workers);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < workers; ++t)
+      pool.emplace_back([&, t] {
+        hipStream_t st = nullptr;
+        rocblas_handle rb = nullptr;
+        try {
+          hip_check(hipSetDevice(h->device), "hipSetDevice");
+          hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+          STMG_REQUIRE(rocblas_create_handle(&rb) == rocblas_status_success, STMG_EHIP, "rocblas_create_handle failed");
+          STMG_REQUIRE(rocblas_set_stream(rb, st) == rocblas_status_success, STMG_EHIP, "rocblas_set_stream failed");
+          tl_setup_stream = st;
+          tl_setup_rb = rb;
+          for (size_t i; (i = next.fetch_add(1)) < order.size();) {
+            setup_level_factor_device(h, h->levels[order[i]]);
+            if (verbose())
+              fprintf(stderr, "[stmg] level %zu slab factor (GPU factorisation, worker %d) %.2fs\n", order[i], t,
+                      wall_time() - t0);
+          }
+        } catch (...) {
+          errs[t] = std::current_exception();
+          next.store(order.size());
+        }
+        tl_setup_stream = nullptr;
+        tl_setup_rb = nullptr;
+        if (rb) (void)rocblas_destroy_handle(rb);
+        if (st) {
+          (void)hipStreamSynchronize(st);
+          (void)hipStreamDestroy(st);
+        }
+      });
+    for (auto &th : pool) th.join();
+    for (auto &e : errs)
+      if (e) std::rethrow_exception(e);
   }
   for (size_t l = 0; l < h->levels.size(); ++l) alloc_level_vectors(h, h->levels[l], l == 0);
   // split-K partial sums of the backward solves, shared by all factors
@@ -1988,6 +2061,11 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
       // refuse before allocating when the device cannot hold the handle
       size_t free_b = 0, total_b = 0;
       hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      // parallel GPU factorisations, as many as their temporaries fit
+      if (dev_factor(h) && !h->stream_ordered)
+        for (h->factor_workers = FACTOR_WORKERS;
+             h->factor_workers > 1 && estimate_device_bytes(h) > (int64_t)free_b; h->factor_workers /= 2) {
+        }
       const int64_t need = estimate_device_bytes(h);
       if (need > (int64_t)free_b) {
         char msg[160];

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -170,6 +171,8 @@ struct stmg_handle {
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;   // the capture stream
   int device = -1;                      // HIP device current at setup
+  int32_t factor_workers = 1;           // threads (each with its own stream) of the slab factorisations
+  std::mutex alloc_mu;                  // guards bufs, device_bytes and factor_bytes during setup
   double *noalloc_scratch = nullptr;    // that device's copy of the no-allocation scratch array
 };
 
