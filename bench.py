@@ -299,7 +299,8 @@ def stats_summary(stats_csv, top=24):
                      float(r.get("Percentage", 0.0))))
     rows.sort(key=lambda t: -t[2])
     cycle = ("k_sn_gemm", "k_sn_reduce", "k_residual", "k_fwd_asm", "k_slab_", "k_grad", "k_time_scan",
-             "k_restrict", "k_prolong", "k_sum", "k_to_", "k_add_float", "k_fill", "k_cheb")
+             "k_restrict", "k_prolong", "k_sum", "k_to_", "k_add_float", "k_fill", "k_cheb", "k_tg_",
+             "k_csr_slabs", "k_scale_slabs", "k_axpy")
     for title, sel in (("Kernels of the V-cycle", lambda k: k.startswith(cycle)),
                        ("Other kernels (setup: numeric factorisation, uploads, layout changes)",
                         lambda k: not k.startswith(cycle))):
