@@ -163,99 +163,80 @@ __global__ __launch_bounds__(FB) void k_extend_add(T *F, int64_t m, const T *U, 
   *f = f_add(*f, U[e]);
 }
 
+// Right-looking L L^T of the kb x kb lower triangle in LDS (leading
+// dimension ld), kb <= 64, by the FB threads of a block: lane i (of each of
+// the FB / 64 waves) owns row i; per column j every thread takes the pivot,
+// wave 0 scales the column, then wave v updates the trailing columns
+// c = j + 1 + v, j + 1 + v + FB / 64, ... of its lanes' rows. Every entry
+// receives its updates in column order, two barriers per column. A zero or
+// non-finite pivot sets *flag and is replaced by 1.
+template <typename T>
+__device__ void block_chol(T *Ls, int ld, int kb, int32_t *flag) {
+  const int i = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < kb; ++j) {
+    T p = Ls[j + j * ld];
+    const bool bad = f_bad_pivot(p);
+    if (bad) p = f_one(T{});
+    const T d = f_sqrt(p), dinv = f_recip(d);
+    if (wave == 0 && i > j && i < kb) Ls[i + j * ld] = f_mul(Ls[i + j * ld], dinv);
+    __syncthreads();  // the scaled column is written and the pivot read by all
+    if (wave == 0 && i == j) {
+      Ls[j + j * ld] = d;
+      if (bad) flag[0] = 1;
+    }
+    if (i > j && i < kb) {
+      const T lij = Ls[i + j * ld];
+      for (int c = j + 1 + wave; c <= i; c += FB / 64) Ls[i + c * ld] = f_fms(Ls[i + c * ld], lij, Ls[c + j * ld]);
+    }
+    __syncthreads();
+  }
+}
+
 // In-place L L^T of the kb x kb diagonal block at A (ld), kb <= NB, in LDS.
 template <typename T>
 __global__ __launch_bounds__(FB) void k_diag_chol(T *A, int64_t ld, int kb, int32_t *flag) {
   __shared__ T Ls[NB * NB];
-  __shared__ T dinv;
-  for (int e = threadIdx.x; e < kb * kb; e += FB) {
-    const int i = e % kb, c = e / kb;
-    Ls[e] = i >= c ? A[i + c * ld] : f_zero(T{});
-  }
+  const int i = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < kb; c += FB / 64)
+    if (i < kb) Ls[i + c * kb] = i >= c ? A[i + c * ld] : f_zero(T{});
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (threadIdx.x == 0) {
-      T p = Ls[j + j * kb];
-      if (f_bad_pivot(p)) {
-        flag[0] = 1;
-        p = f_one(T{});
-      }
-      const T d = f_sqrt(p);
-      Ls[j + j * kb] = d;
-      dinv = f_recip(d);
-    }
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < kb; i += FB) Ls[i + j * kb] = f_mul(Ls[i + j * kb], dinv);
-    __syncthreads();
-    const int n = kb - j - 1;
-    for (int e = threadIdx.x; e < n * n; e += FB) {
-      const int i = j + 1 + e % n, c = j + 1 + e / n;
-      if (i >= c) Ls[i + c * kb] = f_fms(Ls[i + c * kb], Ls[i + j * kb], Ls[c + j * kb]);
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < kb * kb; e += FB) {
-    const int i = e % kb, c = e / kb;
-    if (i >= c) A[i + c * ld] = Ls[e];
-  }
+  block_chol(Ls, kb, kb, flag);
+  for (int c = wave; c < kb; c += FB / 64)
+    if (i < kb && i >= c) A[i + c * ld] = Ls[i + c * kb];
 }
 
-// Fronts with w <= NB: one wave factors the w x w diagonal block in LDS
-// (lane i owns row i: right-looking L L^T, then the in-place inverse of the
-// lower triangle column by column from the last), and writes inv(L11) into
-// the panel's top block (zeros above the diagonal).
+// Fronts with w <= NB: the block factors the w x w diagonal block in LDS
+// (block_chol), then inverts the lower triangle in place column by column
+// from the last, Linv[i][j] = -(sum_{k=j+1..i} Linv[i][k] L[k][j]) / L[j][j],
+// the sum split over the waves (k = j + 1 + v mod FB / 64) and added in a
+// fixed order, and writes inv(L11) into the panel's top block (zeros above
+// the diagonal).
 template <typename T>
-__global__ __launch_bounds__(64) void k_chol_inv_small(const T *F, int64_t m, int w, T *P, int32_t *flag) {
+__global__ __launch_bounds__(FB) void k_chol_inv_small(const T *F, int64_t m, int w, T *P, int32_t *flag) {
+  constexpr int NW = FB / 64;
   __shared__ T Ls[NB * NB];
-  const int i = threadIdx.x;
-  for (int c = 0; c < w; ++c)
+  __shared__ T part[NW][64];
+  const int i = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < w; c += NW)
     if (i < w) Ls[i + c * NB] = i >= c ? F[i + c * m] : f_zero(T{});
   __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    T p = Ls[j + j * NB];
-    if (f_bad_pivot(p)) {
-      if (i == 0) flag[0] = 1;
-      p = f_one(T{});
-    }
-    const T d = f_sqrt(p), dinv = f_recip(d);
-    T lij = f_zero(T{});
-    __syncthreads();  // everyone has read the pivot
-    if (i == j) Ls[j + j * NB] = d;
-    if (i > j && i < w) {
-      lij = f_mul(Ls[i + j * NB], dinv);
-      Ls[i + j * NB] = lij;
-    }
-    __syncthreads();
-    // the update's iterations are independent: unrolled, so that their LDS
-    // reads overlap instead of each waiting for the previous write
-    if (i > j && i < w) {
-#pragma unroll 8
-      for (int c = j + 1; c <= i; ++c) Ls[i + c * NB] = f_fms(Ls[i + c * NB], lij, Ls[c + j * NB]);
-    }
-    __syncthreads();
-  }
-  // inverse: for j from the last column, Linv[i][j] = -(sum_{k=j+1..i} Linv[i][k] L[k][j]) / L[j][j]
+  block_chol(Ls, NB, w, flag);
   for (int j = w - 1; j >= 0; --j) {
-    const T djinv = f_recip(Ls[j + j * NB]);
-    // acc -= Linv[i,k] L[k,j] over k, in four interleaved partial sums (k mod 4)
-    // added in a fixed order, so that the FMA chain is not one long dependency
     T acc = f_zero(T{});
-    if (i > j && i < w) {
-      T a4[4] = {f_zero(T{}), f_zero(T{}), f_zero(T{}), f_zero(T{})};
-      int k = j + 1;
-      for (; k + 3 <= i; k += 4) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) a4[t] = f_fms(a4[t], Ls[i + (k + t) * NB], Ls[k + t + j * NB]);
-      }
-      for (; k <= i; ++k) a4[0] = f_fms(a4[0], Ls[i + k * NB], Ls[k + j * NB]);
-      acc = f_add(f_add(a4[0], a4[1]), f_add(a4[2], a4[3]));
+    if (i > j && i < w)
+      for (int k = j + 1 + wave; k <= i; k += NW) acc = f_fms(acc, Ls[i + k * NB], Ls[k + j * NB]);
+    part[wave][i] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      const T djinv = f_recip(Ls[j + j * NB]);
+      T sum = part[0][i];
+      for (int v = 1; v < NW; ++v) sum = f_add(sum, part[v][i]);
+      if (i > j && i < w) Ls[i + j * NB] = f_mul(sum, djinv);
+      if (i == j) Ls[j + j * NB] = djinv;
     }
     __syncthreads();
-    if (i == j) Ls[j + j * NB] = djinv;
-    if (i > j && i < w) Ls[i + j * NB] = f_mul(acc, djinv);
-    __syncthreads();
   }
-  for (int c = 0; c < w; ++c)
+  for (int c = wave; c < w; c += NW)
     if (i < w) P[i + c * m] = i >= c ? Ls[i + c * NB] : f_zero(T{});
 }
 
@@ -421,7 +402,7 @@ void factor_device(const Symbolic &S, const FrontPlan &fp, const FrontPlanDev &f
       // small diagonal block: inv(L11) in one kernel, then
       // L21 = F21 inv(L11)^T (into the panel), F22 -= L21 L21^T,
       // W21 = -L21 inv(L11) (into F21's place, then the panel)
-      hipLaunchKernelGGL(k_chol_inv_small<T>, dim3(1), dim3(64), 0, st, (const T *)F, (int64_t)m, w, P, flag);
+      hipLaunchKernelGGL(k_chol_inv_small<T>, dim3(1), dim3(FB), 0, st, (const T *)F, (int64_t)m, w, P, flag);
       if (r > 0) {
         rb_trmm_t(rb, r, w, P, m, F + w, m, P + w, m);
         rb_syrk_sub(rb, r, w, P + w, m, F + w + (int64_t)w * m, m);
