@@ -110,16 +110,25 @@ def oracle_sample(args):
         # beyond a bounded sample)
         big = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
         sp = finest_space(big)
-        lev = Level.operator_only(sp, big.pt, big.Nt, big.T / big.Nt)
+        t = time.perf_counter()
+        lev = Level.operator_only(sp, big.pt, big.Nt, big.T / big.Nt, nodal=True)
+        t_kn = time.perf_counter() - t
         xb = np.random.default_rng(3).standard_normal((big.Nt, big.pt + 1, sp.n_e))
         bb = np.random.default_rng(2).standard_normal(xb.shape)
         t = time.perf_counter()
         lev.residual(xb, bb)
         t_res = time.perf_counter() - t
+        t = time.perf_counter()
+        lev.nodal_A(xb, bb)
+        t_nod = time.perf_counter() - t
         dofs_big = sp.n_e * big.Nt * (big.pt + 1)
         out["same_inputs"] = {"workload": f"{args.n}^3 x 6 Kuhn tets, N_t={big.Nt}, p_t={big.pt} (the GPU line's)",
                               "residual_s": t_res, "residual_dof_per_s": dofs_big / t_res,
-                              "note": "one space-time residual b - L x (eq. (1)), 1 thread"}
+                              "nodal_correction_s": t_nod, "nodal_factor_s": t_kn,
+                              "note": ("one space-time residual b - L x (eq. (1)) and one nodal correction A "
+                                       "(eq. (8): its residual, G^T, the K_n solve of all N_t (p_t+1) columns "
+                                       "with the SuperLU factor, the time scan, G), 1 thread; the slab factors "
+                                       "of this size do not fit a bounded sample")}
     print(json.dumps(out))
 
 

@@ -188,22 +188,28 @@ class Level:
             self.slab = SlabSolverComplex(M, K, self.tau)
         else:
             self.slab = SlabSolverReal(M, K, self.Kt, self.Mt)
+        self._setup_nodal(nodal_cheb)
+
+    def _setup_nodal(self, nodal_cheb):
         self.nodal_cheb = nodal_cheb
         if nodal_cheb > 0:
-            self.Kn_bounds = chebyshev_bounds(space.Kn) if space.n_v > 0 else None
+            self.Kn_bounds = chebyshev_bounds(self.space.Kn) if self.space.n_v > 0 else None
         else:
-            self.Kn_lu = spla.splu(sp.csc_matrix(space.Kn))
+            self.Kn_lu = spla.splu(sp.csc_matrix(self.space.Kn))
 
     @classmethod
-    def operator_only(cls, space, pt, N, tau):
-        """A level that applies L and its residual but factorises nothing
-        (for checks at sizes where the exact slab and nodal factors are too
-        costly for the oracle)."""
+    def operator_only(cls, space, pt, N, tau, nodal=False):
+        """A level that applies L and its residual but factorises no slab
+        block (for checks at sizes where the exact slab factors are too
+        costly for the oracle); with nodal=True it also applies the nodal
+        correction A (the K_n factor is small)."""
         lev = cls.__new__(cls)
         lev.spec, lev.space, lev.pt = None, space, pt
         lev.q = pt + 1
         lev.N, lev.tau = N, tau
         lev.Kt, lev.Mt, lev.Nt = time_matrices(pt, tau)
+        if nodal:
+            lev._setup_nodal(0)
         return lev
 
     # -- operators -------------------------------------------------------

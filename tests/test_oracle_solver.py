@@ -195,11 +195,12 @@ def test_operator_only_level_matches_full_level():
     from oracle.vcycle import Level
     prob = inputs.config_block_random(n=4, Nt=8, pt=1, seed=11, block_hexes=2)
     s = SpaceTimeMultigrid(prob)
-    lev = Level.operator_only(finest_space(prob), 1, 8, prob.T / 8)
+    lev = Level.operator_only(finest_space(prob), 1, 8, prob.T / 8, nodal=True)
     rng = np.random.default_rng(9)
     x, b = rng.standard_normal((2, 8, 2, s.fine.n_e))
     assert np.array_equal(lev.residual(x, b), s.levels[0].residual(x, b))
     assert np.array_equal(lev.apply_slab(x), s.levels[0].apply_slab(x))
+    assert np.array_equal(lev.nodal_A(x, b), s.levels[0].nodal_A(x, b))
 
 
 def test_power_rate_of_a_single_slab_is_zero():
