@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <system_error>
 #include <thread>
 #include <type_traits>
 #include <cstring>
@@ -139,6 +140,16 @@ struct DevTemp {
 // Set by the host phase from the device_factor option: large factors are
 // factored on the GPU; small ones (launch-latency bound there) on the host.
 bool dev_factor(const stmg_handle *h) { return h->device_factor_on; }
+
+// Most worker threads of the parallel slab factorisations: FACTOR_WORKERS,
+// or the environment's STMG_SETUP_THREADS (1..FACTOR_WORKERS; 1 factors on
+// the calling thread's stream only).
+int setup_threads_limit() {
+  const char *e = getenv("STMG_SETUP_THREADS");
+  if (!e || !*e) return FACTOR_WORKERS;
+  const int v = atoi(e);
+  return v < 1 ? 1 : (v > FACTOR_WORKERS ? FACTOR_WORKERS : v);
+}
 
 // Setup progress on stderr (environment STMG_VERBOSE set and not 0).
 bool verbose() {
@@ -1910,50 +1921,57 @@ void setup_device_phase(stmg_handle *h, hipStream_t stream) {
   // temporaries then share the device with the mesh data and the other
   // workers' temporaries only), then the level vectors
   const std::vector<size_t> order = factor_order(h);
-  const int workers = std::min<int>(h->factor_workers, (int)order.size());
-  if (workers <= 1) {
-    for (size_t l : order) {
-      setup_level_factor_device(h, h->levels[l]);
-      if (verbose())
-        fprintf(stderr, "[stmg] level %zu slab factor (%s factorisation) %.2fs\n", l, dev_factor(h) ? "GPU" : "host",
-                wall_time() - t0);
-    }
-  } else {
+  const int workers = std::min<int>(h->factor_workers, (int)order.size() - 1);
+  // the first (largest) factor on this thread: every kernel and library
+  // routine the workers use is then loaded and initialised before they start
+  for (size_t i = 0; i < order.size() && (i == 0 || workers <= 1); ++i) {
+    setup_level_factor_device(h, h->levels[order[i]]);
+    if (verbose())
+      fprintf(stderr, "[stmg] level %zu slab factor (%s factorisation) %.2fs\n", order[i],
+              dev_factor(h) ? "GPU" : "host", wall_time() - t0);
+  }
+  if (workers > 1) {
     // the factorisations are sequences of small dependent launches whose
     // issue dominates their time: workers with a stream and a rocBLAS handle
     // each take the next level in `order` until none is left
-    std::atomic<size_t> next{0};
+    std::atomic<size_t> next{1};
     std::vector<std::exception_ptr> errs(workers);
     std::vector<std::thread> pool;
-    for (int t = 0; t < workers; ++t)
-      pool.emplace_back([&, t] {
-        hipStream_t st = nullptr;
-        rocblas_handle rb = nullptr;
-        try {
-          hip_check(hipSetDevice(h->device), "hipSetDevice");
-          hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
-          STMG_REQUIRE(rocblas_create_handle(&rb) == rocblas_status_success, STMG_EHIP, "rocblas_create_handle failed");
-          STMG_REQUIRE(rocblas_set_stream(rb, st) == rocblas_status_success, STMG_EHIP, "rocblas_set_stream failed");
-          tl_setup_stream = st;
-          tl_setup_rb = rb;
-          for (size_t i; (i = next.fetch_add(1)) < order.size();) {
-            setup_level_factor_device(h, h->levels[order[i]]);
-            if (verbose())
-              fprintf(stderr, "[stmg] level %zu slab factor (GPU factorisation, worker %d) %.2fs\n", order[i], t,
-                      wall_time() - t0);
-          }
-        } catch (...) {
-          errs[t] = std::current_exception();
-          next.store(order.size());
+    auto work = [&](int t) {
+      hipStream_t st = nullptr;
+      rocblas_handle rb = nullptr;
+      try {
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+        STMG_REQUIRE(rocblas_create_handle(&rb) == rocblas_status_success, STMG_EHIP, "rocblas_create_handle failed");
+        STMG_REQUIRE(rocblas_set_stream(rb, st) == rocblas_status_success, STMG_EHIP, "rocblas_set_stream failed");
+        tl_setup_stream = st;
+        tl_setup_rb = rb;
+        for (size_t i; (i = next.fetch_add(1)) < order.size();) {
+          setup_level_factor_device(h, h->levels[order[i]]);
+          if (verbose())
+            fprintf(stderr, "[stmg] level %zu slab factor (GPU factorisation, worker %d) %.2fs\n", order[i], t,
+                    wall_time() - t0);
         }
-        tl_setup_stream = nullptr;
-        tl_setup_rb = nullptr;
-        if (rb) (void)rocblas_destroy_handle(rb);
-        if (st) {
-          (void)hipStreamSynchronize(st);
-          (void)hipStreamDestroy(st);
-        }
-      });
+      } catch (...) {
+        errs[t] = std::current_exception();
+        next.store(order.size());
+      }
+      tl_setup_stream = nullptr;
+      tl_setup_rb = nullptr;
+      if (rb) (void)rocblas_destroy_handle(rb);
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+    };
+    try {
+      for (int t = 0; t < workers; ++t) pool.emplace_back(work, t);
+    } catch (const std::system_error &) {
+      // a thread that cannot start: the started ones (or this thread) take the rest
+    }
+    if (pool.empty())
+      for (size_t i; (i = next.fetch_add(1)) < order.size();) setup_level_factor_device(h, h->levels[order[i]]);
     for (auto &th : pool) th.join();
     for (auto &e : errs)
       if (e) std::rethrow_exception(e);
@@ -2061,9 +2079,10 @@ int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream, 
       // refuse before allocating when the device cannot hold the handle
       size_t free_b = 0, total_b = 0;
       hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-      // parallel GPU factorisations, as many as their temporaries fit
+      // parallel GPU factorisations, as many as their temporaries fit (at
+      // most STMG_SETUP_THREADS from the environment; 1 = one stream)
       if (dev_factor(h) && !h->stream_ordered)
-        for (h->factor_workers = FACTOR_WORKERS;
+        for (h->factor_workers = setup_threads_limit();
              h->factor_workers > 1 && estimate_device_bytes(h) > (int64_t)free_b; h->factor_workers /= 2) {
         }
       const int64_t need = estimate_device_bytes(h);
