@@ -93,6 +93,9 @@ CASES = {
     "tg4_jitter_n6_N16_p0_devfactor": lambda: inputs.config_core_box(n=6, Nt=16, pt=0, seed=6, jitter=0.2),
     "tg3_neumann_n8_N16_p1": lambda: _neumann(inputs.config_block_random(n=8, Nt=16, pt=1, seed=19,
                                                                          block_hexes=4)),
+    # N = 64 on the top level: the slab operator's wave-per-row kernel (N a multiple of 64)
+    "tg2_block_n8_N64_p1": lambda: inputs.config_block_random(n=8, Nt=64, pt=1, seed=21, block_hexes=4),
+    "tg1_block_n8_N128_p0": lambda: inputs.config_block_random(n=8, Nt=128, pt=0, seed=22, block_hexes=4),
 }
 # the oracle's options for the cases that change the method
 ORACLE_OPTS = {"cheb3_block_n8_N32_p1": dict(nodal_cheb=3), "cheb2_jitter_n6_N16_p0": dict(nodal_cheb=2),
@@ -100,7 +103,9 @@ ORACLE_OPTS = {"cheb3_block_n8_N32_p1": dict(nodal_cheb=3), "cheb2_jitter_n6_N16
                "tg2_block_n8_N32_p1": dict(slab_solver="twogrid:2"),
                "tg1_block_n8_N16_p0": dict(slab_solver="twogrid:1"),
                "tg4_jitter_n6_N16_p0_devfactor": dict(slab_solver="twogrid:4"),
-               "tg3_neumann_n8_N16_p1": dict(slab_solver="twogrid:3")}
+               "tg3_neumann_n8_N16_p1": dict(slab_solver="twogrid:3"),
+               "tg2_block_n8_N64_p1": dict(slab_solver="twogrid:2"),
+               "tg1_block_n8_N128_p0": dict(slab_solver="twogrid:1")}
 OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
         "block_n8_N32_p1": dict(gemm_rows=32),
         "block_n8_N32_p1_noT_split3": dict(factor_transpose=0, gemm_splitk=3),
@@ -112,7 +117,8 @@ OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": 
         "cheb4_neumann_n6_N16_p1": dict(nodal=4),
         "tg2_block_n8_N32_p1": dict(slab=2), "tg1_block_n8_N16_p0": dict(slab=1),
         "tg4_jitter_n6_N16_p0_devfactor": dict(slab=4, device_factor=1),
-        "tg3_neumann_n8_N16_p1": dict(slab=3)}
+        "tg3_neumann_n8_N16_p1": dict(slab=3), "tg2_block_n8_N64_p1": dict(slab=2),
+        "tg1_block_n8_N128_p0": dict(slab=1)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
