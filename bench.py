@@ -479,10 +479,10 @@ def core_box(args):
     """The unstructured high-contrast case (jittered Kuhn mesh, conducting
     core box [0.3, 0.7]^3 with sigma = 1e4 and nu = 1e-3 inside, sigma = 1e-2
     outside): setup, then the solve to 1e-8 in the FP64 and in the precision
-    form with exact slab solves, or (--core-box-slab k) in the FP64 form with
-    k two-grid Richardson steps per slab solve, which keeps only the coarser
-    mesh's slab factors on the levels above the coarsest (the size that the
-    exact factors do not fit on one GPU). Cycles run one at a time with a
+    form with exact slab solves, or (--core-box-slab k) with k two-grid
+    Richardson steps per slab solve, which keeps only the coarser mesh's slab
+    factors on the levels above the coarsest (the size that the exact factors
+    do not fit on one GPU). Cycles run one at a time with a
     progress line every 10 s; the time to 1e-8 covers the cycles up to the
     first residual at or below 1e-8. Prints one JSON line."""
     import numpy as np
@@ -496,7 +496,8 @@ def core_box(args):
     out = {"workload": f"jittered core box, {n}^3 x 6 Kuhn tets (vertices moved by up to 20% of h), "
                        f"N_t={Nt}, p_t={pt}, Gaussian rhs", "factor_transpose": args.core_box_transpose,
            "slab_steps": k, "forms": {}}
-    forms = ((f"fp64_twogrid{k}", stmg.FP64),) if k > 0 else (("fp64", stmg.FP64), ("fp32_refined", stmg.FP32_REFINED))
+    sfx = f"_twogrid{k}" if k > 0 else ""
+    forms = (("fp64" + sfx, stmg.FP64), ("fp32_refined" + sfx, stmg.FP32_REFINED))
     max_cycles = args.core_box_cycles
     for form, prec in forms:
         log(f"[core box] setup {form} n={n} Nt={Nt}")
@@ -592,7 +593,7 @@ def main():
                     help="only the jittered high-contrast core-box case on an N^3 mesh")
     ap.add_argument("--core-box-Nt", type=int, default=128)
     ap.add_argument("--core-box-slab", type=int, default=0, metavar="K",
-                    help="inexact slab solves: K two-grid Richardson steps (FP64 form only)")
+                    help="inexact slab solves: K two-grid Richardson steps")
     ap.add_argument("--core-box-cycles", type=int, default=100, help="cycle cap of the core-box solves")
     ap.add_argument("--core-box-transpose", type=int, default=-1, choices=(-1, 0, 1),
                     help="keep P^T for the backward solves: -1 auto, 0 never (half the factor memory)")

@@ -167,7 +167,8 @@ typedef struct {
                                     replaced by k steps of Richardson iteration from zero, each preconditioned
                                     by one two-grid cycle on the two meshes (section 5 solves the spatial
                                     problems inexactly); such a level keeps the slab factor of the coarser
-                                    mesh only. Plain FP64 form only (STMG_EINVAL with STMG_FP32_REFINED). */
+                                    mesh only. In the precision form the iteration runs in the FP32
+                                    smoother (FP32 diagonals, matrix values and coarse factors). */
 } stmg_options;
 
 typedef struct {

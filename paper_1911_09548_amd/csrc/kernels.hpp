@@ -27,6 +27,19 @@ struct cd {  // complex double
 struct cf {  // complex float
   float re, im;
 };
+// Real scalar type of a (complex or real) scalar type.
+template <typename T>
+struct RealOf {
+  using type = T;
+};
+template <>
+struct RealOf<cd> {
+  using type = double;
+};
+template <>
+struct RealOf<cf> {
+  using type = float;
+};
 
 // Space-time residual of one level (fused SpMM with M and K on their shared
 // pattern + DG coupling to the previous slab in the same row).
@@ -112,7 +125,8 @@ void launch_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *c
                       const R *g, const R *y, R *d, R *y_out, double a, double b, hipStream_t s);
 
 // Inexact slab solves (two-grid cycle), on slab-solve vectors of N scalars
-// per row (T = cd for DG degree 1, double for degree 0):
+// per row (T = cd or cf for DG degree 1, double or float for degree 0; M and
+// K values in T's real type):
 //   launch_tg_apply: mode 0: out = w - (mu M + tau K) z; mode 1: out = z +
 //     omega dinv (w - (mu M + tau K) z) (out distinct from z, may be w);
 //     mode 2: out = omega dinv w (z unused); rows visited in the order sched
@@ -121,13 +135,16 @@ void launch_cheb_step(int32_t n, int32_t W, const int64_t *ptr, const int32_t *c
 //   launch_scale_slabs: y = diag(d) y.
 template <typename T>
 void launch_tg_apply(int32_t n, int32_t N, const int32_t *sched, const int64_t *ptr, const int32_t *col,
-                     const double *mval, const double *kval, T mu, double tau, const T *dinv, double omega,
-                     const T *w, const T *z, T *out, int mode, hipStream_t s);
+                     const typename RealOf<T>::type *mval, const typename RealOf<T>::type *kval, T mu, double tau,
+                     const T *dinv, double omega, const T *w, const T *z, T *out, int mode, hipStream_t s);
 template <typename T>
 void launch_csr_slabs(int32_t n, int32_t N, const int64_t *ptr, const int32_t *col, const double *val, const T *x,
                       T *y, int add, hipStream_t s);
 template <typename T>
 void launch_scale_slabs(int32_t n, int32_t N, const T *d, T *y, hipStream_t s);
+// y += x over n reals (R = double or float)
+template <typename R>
+void launch_tg_axpy(int64_t n, const R *x, R *y, hipStream_t s);
 
 // Space-time transfers. P_s given as CSR (rows: coarse for restrict = P^T,
 // fine for prolong = P); the identity when ptr == nullptr (same mesh).

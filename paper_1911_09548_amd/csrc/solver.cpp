@@ -806,8 +806,9 @@ void setup_level_factor_device(stmg_handle *h, LevelData &L) {
 
 // Diagonals of the two-grid smoother in the internal numberings: 1 / A_ii,
 // A = mu M + tau K, per edge, and 1 / (mu (K_n)_vv) per vertex (complex
-// pairs for DG degree 1, mu = 2 + i sqrt(2); real for degree 0, mu = 1).
-void upload_twogrid_diagonals(stmg_handle *h, LevelData &L, const MeshData &md) {
+// pairs for DG degree 1, mu = 2 + i sqrt(2); real for degree 0, mu = 1),
+// computed in FP64 and stored rounded to FP32 for the FP32 smoother.
+void upload_twogrid_diagonals(stmg_handle *h, LevelData &L, const MeshData &md, bool fp32) {
   const int32_t ne = md.S->topo.n_int_edges(), nv = md.S->topo.n_int_verts();
   const bool cpx = h->pt == 1;
   const double mre = cpx ? 2.0 : 1.0, mim = cpx ? std::sqrt(2.0) : 0.0;
@@ -841,8 +842,13 @@ void upload_twogrid_diagonals(stmg_handle *h, LevelData &L, const MeshData &md) 
     STMG_REQUIRE(kd > 0.0, STMG_ENUMERIC, "nodal matrix with a non-positive diagonal entry");
     inv(mre * kd, mim * kd, &dn[(size_t)r * q]);
   }
-  L.tg_dinv = dev_upload(h, de);
-  L.tg_dn = dev_upload(h, dn);
+  if (fp32) {  // the FP32 smoother's copies
+    L.tg_dinv32 = dev_upload(h, std::vector<float>(de.begin(), de.end()));
+    L.tg_dn32 = dev_upload(h, std::vector<float>(dn.begin(), dn.end()));
+  } else {
+    L.tg_dinv = dev_upload(h, de);
+    L.tg_dn = dev_upload(h, dn);
+  }
 }
 
 void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
@@ -869,14 +875,23 @@ void alloc_level_vectors(stmg_handle *h, LevelData &L, bool first) {
     L.un = dev_alloc<double>(h, std::max<int64_t>(1, (cheb ? nv : md.nodal.u_rows) * W));
     if (cheb) L.yn = dev_alloc<double>(h, nv * W);
   }
-  if (L.twogrid) {
+  if (L.twogrid) {  // in the precision form the FP32 smoother's buffers only
     const MeshData &mf = h->meshes[h->mesh_slot[L.fmesh]];
-    if (h->opt.slab > 1) L.tg_r = dev_alloc<double>(h, ne * W);
-    L.tg_a = dev_alloc<double>(h, ne * W);
-    L.tg_b = dev_alloc<double>(h, ne * W);
-    L.tg_t = dev_alloc<double>(h, ne * W);
-    L.tg_c = dev_alloc<double>(h, (int64_t)mf.S->topo.n_int_edges() * W);
-    upload_twogrid_diagonals(h, L, md);
+    const int64_t nc = (int64_t)mf.S->topo.n_int_edges() * W;
+    if (prec) {
+      if (h->opt.slab > 1) L.tg_r32 = dev_alloc<float>(h, ne * W);
+      L.tg_a32 = dev_alloc<float>(h, ne * W);
+      L.tg_b32 = dev_alloc<float>(h, ne * W);
+      L.tg_t32 = dev_alloc<float>(h, ne * W);
+      L.tg_c32 = dev_alloc<float>(h, nc);
+    } else {
+      if (h->opt.slab > 1) L.tg_r = dev_alloc<double>(h, ne * W);
+      L.tg_a = dev_alloc<double>(h, ne * W);
+      L.tg_b = dev_alloc<double>(h, ne * W);
+      L.tg_t = dev_alloc<double>(h, ne * W);
+      L.tg_c = dev_alloc<double>(h, nc);
+    }
+    upload_twogrid_diagonals(h, L, md, prec);
   }
   if (prec && first && last) {
     L.xe = dev_alloc<double>(h, ne * W);
@@ -920,6 +935,13 @@ struct Bufs<double> {
   static const double *kval(MeshData &m) { return m.d_kval; }
   static const double *gval(MeshData &m) { return m.d_gval; }
   static const FactorDev &fac(DevFactor &d) { return d.f; }
+  static double *tg_dinv(LevelData &L) { return L.tg_dinv; }
+  static double *tg_dn(LevelData &L) { return L.tg_dn; }
+  static double *tg_r(LevelData &L) { return L.tg_r; }
+  static double *tg_a(LevelData &L) { return L.tg_a; }
+  static double *tg_b(LevelData &L) { return L.tg_b; }
+  static double *tg_t(LevelData &L) { return L.tg_t; }
+  static double *tg_c(LevelData &L) { return L.tg_c; }
   using C = cd;
 };
 template <>
@@ -939,6 +961,13 @@ struct Bufs<float> {
   static const float *kval(MeshData &m) { return m.d_kval32; }
   static const float *gval(MeshData &m) { return m.d_gval32; }
   static const FactorDev &fac(DevFactor &d) { return d.f32; }
+  static float *tg_dinv(LevelData &L) { return L.tg_dinv32; }
+  static float *tg_dn(LevelData &L) { return L.tg_dn32; }
+  static float *tg_r(LevelData &L) { return L.tg_r32; }
+  static float *tg_a(LevelData &L) { return L.tg_a32; }
+  static float *tg_b(LevelData &L) { return L.tg_b32; }
+  static float *tg_t(LevelData &L) { return L.tg_t32; }
+  static float *tg_c(LevelData &L) { return L.tg_c32; }
   using C = cf;
 };
 
@@ -1028,14 +1057,11 @@ struct OpsT {
   void slab_solve(int l, R *w) {
     LevelData &L = h->levels[l];
     if (L.twogrid) {
-      if constexpr (std::is_same<R, double>::value) {
-        if (L.slab.is_complex)
-          slab_solve_twogrid<cd>(l, w);
-        else
-          slab_solve_twogrid<double>(l, w);
-        return;
-      }
-      fail(STMG_ENOSYS, "inexact slab solves in the FP32 smoother");
+      if (L.slab.is_complex)
+        slab_solve_twogrid<CX>(l, w);
+      else
+        slab_solve_twogrid<R>(l, w);
+      return;
     }
     const int32_t nc = L.N;
     const FactorDev &F = B::fac(L.slab);
@@ -1057,45 +1083,46 @@ struct OpsT {
   // mu M_c + tau K_c on the next coarser mesh between the transfers P^T and
   // P, then the two sweeps with their steps reversed.
   template <typename T>
-  void slab_solve_twogrid(int l, double *w_) {
+  void slab_solve_twogrid(int l, R *w_) {
     LevelData &L = h->levels[l];
     MeshData &md = mesh(l);
     MeshData &mc = h->meshes[h->mesh_slot[L.fmesh]];
     const int32_t n = ne(l), nvl = nv(l), N = L.N, ncl = mc.S->topo.n_int_edges(), wl = W(l);
-    const double tau = L.tau, om = 0.5, sz = sizeof(double);
+    const double tau = L.tau, om = 0.5, sz = sizeof(R);
     T mu;
-    if constexpr (std::is_same<T, cd>::value)
-      mu = cd{2.0, std::sqrt(2.0)};
+    if constexpr (std::is_same<T, CX>::value)
+      mu = CX{(R)2.0, (R)std::sqrt(2.0)};
     else
-      mu = 1.0;
-    const T *dinv = (const T *)L.tg_dinv, *dn = (const T *)L.tg_dn;
-    T *w = (T *)w_, *t = (T *)L.tg_t, *c = (T *)L.tg_c;
-    const double vec = sz * wl * n, pat = (double)md.Mp.nnz() * (4 + 8 + 8) + 8.0 * n;
+      mu = (R)1.0;
+    const T *dinv = (const T *)B::tg_dinv(L), *dn = (const T *)B::tg_dn(L);
+    T *w = (T *)w_, *t = (T *)B::tg_t(L), *c = (T *)B::tg_c(L);
+    R *g = B::g(L);
+    const double vec = sz * wl * n, pat = (double)md.Mp.nnz() * (4 + 2 * sz) + 8.0 * n;
     // out = r - A z (mode 0); out = z + om dinv (r - A z) (mode 1, out != z,
     // out may be r); out = om dinv r (mode 2)
     auto apply = [&](const T *r, const T *z, T *out, int mode) {
       timed("k_tg_apply", mode == 2 ? 2.0 * vec : 3.0 * vec + pat + (mode == 1 ? sz * wl * n / N : 0.0), [&] {
-        launch_tg_apply<T>(n, N, md.d_sched, md.d_ptr, md.d_col, md.d_mval, md.d_kval, mu, tau, dinv, om, r, z, out,
-                           mode, s);
+        launch_tg_apply<T>(n, N, md.d_sched, md.d_ptr, md.d_col, B::mval(md), B::kval(md), mu, tau, dinv, om, r, z,
+                           out, mode, s);
       });
     };
     auto nodal = [&](const T *r, T *z) {
       if (nvl == 0) return;
       apply(r, z, t, 0);
       timed("k_gradT", sz * wl * ((double)n + nvl), [&] {
-        launch_gradT<double>(nvl, wl, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, (const double *)t, L.g, s);
+        launch_gradT<R>(nvl, wl, md.d_gt_ptr, md.d_gt_edge, md.d_gt_sign, (const R *)t, g, s);
       });
-      timed("k_scale_slabs", 2.0 * sz * wl * nvl, [&] { launch_scale_slabs<T>(nvl, N, dn, (T *)L.g, s); });
+      timed("k_scale_slabs", 2.0 * sz * wl * nvl, [&] { launch_scale_slabs<T>(nvl, N, dn, (T *)g, s); });
       timed("k_grad_add", sz * wl * ((double)nvl + 2.0 * n),
-            [&] { launch_grad_add<double>(n, wl, md.d_head, md.d_tail, L.g, (double *)z, s); });
+            [&] { launch_grad_add<R>(n, wl, md.d_head, md.d_tail, g, (R *)z, s); });
     };
     auto coarse = [&](const T *r, T *z) {
       apply(r, z, t, 0);
       timed("k_csr_slabs", sz * wl * ((double)n + ncl),
             [&] { launch_csr_slabs<T>(ncl, N, mc.d_pt_ptr, mc.d_pt_col, mc.d_pt_val, t, c, 0, s); });
       // t is free again: the coarse solve's workspace
-      const FactorDev &F = L.slab.f;
-      solve_forward<T>(F, L.slab.plan, N, c, t, (T *)L.u, s);
+      const FactorDev &F = B::fac(L.slab);
+      solve_forward<T>(F, L.slab.plan, N, c, t, (T *)B::u(L), s);
       solve_backward<T>(F, L.slab.plan, N, c, t, s);
       timed("k_csr_slabs", sz * wl * ((double)ncl + 2.0 * n),
             [&] { launch_csr_slabs<T>(n, N, mc.d_p_ptr, mc.d_p_col, mc.d_p_val, c, z, 1, s); });
@@ -1112,7 +1139,7 @@ struct OpsT {
       nodal(r, a);
       apply(r, a, out, 1);
     };
-    T *a = (T *)L.tg_a, *b = (T *)L.tg_b, *z = (T *)B::z(L), *rho = (T *)L.tg_r;
+    T *a = (T *)B::tg_a(L), *b = (T *)B::tg_b(L), *z = (T *)B::z(L), *rho = (T *)B::tg_r(L);
     const int k = h->opt.slab;
     const int64_t nd = (int64_t)n * wl;
     if (k == 1) {
@@ -1124,10 +1151,10 @@ struct OpsT {
       apply(w, z, rho, 0);
       if (j < k) {
         precondition(rho, a, b, b);
-        timed("k_axpy", 3.0 * sz * nd, [&] { launch_axpy(nd, 1.0, (const double *)b, (double *)z, s); });
+        timed("k_tg_axpy", 3.0 * sz * nd, [&] { launch_tg_axpy<R>(nd, (const R *)b, (R *)z, s); });
       } else {  // the last step writes z + B rho over w
         precondition(rho, a, b, w);
-        timed("k_axpy", 3.0 * sz * nd, [&] { launch_axpy(nd, 1.0, (const double *)z, (double *)w, s); });
+        timed("k_tg_axpy", 3.0 * sz * nd, [&] { launch_tg_axpy<R>(nd, (const R *)z, (R *)w, s); });
       }
     }
   }
@@ -1729,8 +1756,6 @@ stmg_handle *setup_host_phase(const stmg_problem *prob, const stmg_options *opt)
                "nodal must be STMG_NODAL_EXACT (0) or a number of Chebyshev steps 1..16");
   STMG_REQUIRE(h->opt.slab >= 0 && h->opt.slab <= STMG_SLAB_TWOGRID_MAX, STMG_EINVAL,
                "slab must be STMG_SLAB_EXACT (0) or a number of two-grid Richardson steps 1..16");
-  STMG_REQUIRE(h->opt.slab == 0 || h->opt.precision == STMG_FP64, STMG_EINVAL,
-               "inexact slab solves (slab > 0) are built for the plain FP64 form only");
   if (h->opt.leaf_size <= 0) h->opt.leaf_size = 8;
   STMG_REQUIRE(h->opt.gemm_rows == 0 || h->opt.gemm_rows == 32 || h->opt.gemm_rows == 64, STMG_EINVAL,
                "gemm_rows must be 0, 32 or 64");
@@ -1843,7 +1868,7 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
     bytes += level_factor[l];
     const int64_t urow = mf.sym_e.rptr[mf.sym_e.ns];
     if (L.twogrid)  // Richardson residual, smoother iterates, temporary, coarse vector, diagonals
-      bytes += 8 * W * (4 * ne + mf.S->topo.n_int_edges()) + 16 * (ne + nv);
+      bytes += (prec ? 4 : 8) * W * (4 * ne + mf.S->topo.n_int_edges()) + 16 * (ne + nv);
     const bool last = l + 1 == h->levels.size();
     const int64_t nodal_extra = h->opt.nodal > 0 ? 2 * nv : md.sym_v.rptr[md.sym_v.ns];
     if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + nodal_extra);

@@ -111,6 +111,8 @@ struct LevelData {
   // coarse vector (coarse n_e x W)
   double *tg_dinv = nullptr, *tg_dn = nullptr;
   double *tg_r = nullptr, *tg_a = nullptr, *tg_b = nullptr, *tg_t = nullptr, *tg_c = nullptr;
+  float *tg_dinv32 = nullptr, *tg_dn32 = nullptr;  // the precision form's (FP32 smoother)
+  float *tg_r32 = nullptr, *tg_a32 = nullptr, *tg_b32 = nullptr, *tg_t32 = nullptr, *tg_c32 = nullptr;
   // precision form with one level (N_t = 1): the FP64 coarsest solve's own
   // iterate and right-hand side, apart from the outer x and b of level 0
   double *xe = nullptr, *be = nullptr;

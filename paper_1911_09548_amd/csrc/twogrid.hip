@@ -33,20 +33,26 @@ __device__ inline int64_t xcd_block(int64_t bid, int64_t nblocks) {
 //   mode 1: out = z + omega dinv (w - A z)   (a damped Jacobi step; out != z,
 //           out may be w: w is read at the thread's own entry only);
 //   mode 2: out = omega dinv w               (the same step from z = 0; z unused).
-template <typename T>
-__device__ inline T cmul(T a, T b);
-template <>
 __device__ inline double cmul(double a, double b) { return a * b; }
-template <>
+__device__ inline float cmul(float a, float b) { return a * b; }
 __device__ inline cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cf cmul(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline double cadd(double a, double b) { return a + b; }
+__device__ inline float cadd(float a, float b) { return a + b; }
 __device__ inline cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cf cadd(cf a, cf b) { return {a.re + b.re, a.im + b.im}; }
 __device__ inline double csub(double a, double b) { return a - b; }
+__device__ inline float csub(float a, float b) { return a - b; }
 __device__ inline cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cf csub(cf a, cf b) { return {a.re - b.re, a.im - b.im}; }
 __device__ inline double cscale(double a, double s) { return a * s; }
+__device__ inline float cscale(float a, float s) { return a * s; }
 __device__ inline cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
-__device__ inline double czero(double) { return 0.0; }
-__device__ inline cd czero(cd) { return {0.0, 0.0}; }
+__device__ inline cf cscale(cf a, float s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ inline T czero() {
+  return T{};
+}
 
 // Rows are visited in the order sched[] (a permutation of the rows), four
 // nonzeros per step with their loads issued before the first FMA. WIDE (N a
@@ -55,9 +61,11 @@ __device__ inline cd czero(cd) { return {0.0, 0.0}; }
 // scalars per thread measured 7% slower at N = 256.)
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_tg_apply(int32_t n, int32_t N, const int32_t *sched, const int64_t *ptr,
-                                                    const int32_t *col, const double *mval, const double *kval, T mu,
-                                                    double tau, const T *dinv, double omega, const T *w, const T *z,
-                                                    T *out, int mode) {
+                                                    const int32_t *col, const typename RealOf<T>::type *mval,
+                                                    const typename RealOf<T>::type *kval, T mu,
+                                                    typename RealOf<T>::type tau, const T *dinv,
+                                                    typename RealOf<T>::type omega, const T *w, const T *z, T *out,
+                                                    int mode) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= (int64_t)n * N) return;
   const int32_t slot = (int32_t)(i / N), c = (int32_t)(i % N);
@@ -68,7 +76,7 @@ __global__ __launch_bounds__(BLOCK) void k_tg_apply(int32_t n, int32_t N, const 
     out[off] = cscale(cmul(dinv[row], w[off]), omega);
     return;
   }
-  T mz = czero(T{}), kz = czero(T{});
+  T mz = czero<T>(), kz = czero<T>();
   const int64_t k1 = ptr[row + 1];
   int64_t k = ptr[row];
   for (; k + 4 <= k1; k += 4) {
@@ -93,6 +101,12 @@ __global__ __launch_bounds__(BLOCK) void k_tg_apply(int32_t n, int32_t N, const 
   out[off] = mode == 0 ? r : cadd(z[off], cscale(cmul(dinv[row], r), omega));
 }
 
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_tg_axpy(int64_t n, const R *x, R *y) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
 // y[row] (+)= sum_k val[k] x[col[k]] for the N slab scalars of each row (a
 // spatial transfer P or P^T in CSR), add != 0 accumulates into y.
 template <typename T>
@@ -101,9 +115,10 @@ __global__ __launch_bounds__(BLOCK) void k_csr_slabs(int32_t n, int32_t N, const
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i >= (int64_t)n * N) return;
   const int32_t row = (int32_t)(i / N), c = (int32_t)(i % N);
-  T acc = czero(T{});
+  using Rv = typename RealOf<T>::type;
+  T acc = czero<T>();
   const int64_t k1 = ptr[row + 1];
-  for (int64_t k = ptr[row]; k < k1; ++k) acc = cadd(acc, cscale(x[(int64_t)col[k] * N + c], val[k]));
+  for (int64_t k = ptr[row]; k < k1; ++k) acc = cadd(acc, cscale(x[(int64_t)col[k] * N + c], (Rv)val[k]));
   const int64_t off = (int64_t)row * N + c;
   y[off] = add ? cadd(y[off], acc) : acc;
 }
@@ -120,17 +135,23 @@ __global__ __launch_bounds__(BLOCK) void k_scale_slabs(int32_t n, int32_t N, con
 
 template <typename T>
 void launch_tg_apply(int32_t n, int32_t N, const int32_t *sched, const int64_t *ptr, const int32_t *col,
-                     const double *mval, const double *kval, T mu, double tau, const T *dinv, double omega,
-                     const T *w, const T *z, T *out, int mode, hipStream_t s) {
+                     const typename RealOf<T>::type *mval, const typename RealOf<T>::type *kval, T mu, double tau,
+                     const T *dinv, double omega, const T *w, const T *z, T *out, int mode, hipStream_t s) {
+  using Rv = typename RealOf<T>::type;
   const int64_t nt = (int64_t)n * N;
   if (nt == 0) return;
   const dim3 grid((unsigned)((nt + BLOCK - 1) / BLOCK));
   if (N % 64 == 0)
-    hipLaunchKernelGGL((k_tg_apply<T, true>), grid, dim3(BLOCK), 0, s, n, N, sched, ptr, col, mval, kval, mu, tau,
-                       dinv, omega, w, z, out, mode);
+    hipLaunchKernelGGL((k_tg_apply<T, true>), grid, dim3(BLOCK), 0, s, n, N, sched, ptr, col, mval, kval, mu, (Rv)tau,
+                       dinv, (Rv)omega, w, z, out, mode);
   else
-    hipLaunchKernelGGL((k_tg_apply<T, false>), grid, dim3(BLOCK), 0, s, n, N, sched, ptr, col, mval, kval, mu, tau,
-                       dinv, omega, w, z, out, mode);
+    hipLaunchKernelGGL((k_tg_apply<T, false>), grid, dim3(BLOCK), 0, s, n, N, sched, ptr, col, mval, kval, mu,
+                       (Rv)tau, dinv, (Rv)omega, w, z, out, mode);
+}
+template <typename R>
+void launch_tg_axpy(int64_t n, const R *x, R *y, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_tg_axpy<R>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, n, x, y);
 }
 template <typename T>
 void launch_csr_slabs(int32_t n, int32_t N, const int64_t *ptr, const int32_t *col, const double *val, const T *x,
@@ -148,13 +169,17 @@ void launch_scale_slabs(int32_t n, int32_t N, const T *d, T *y, hipStream_t s) {
 }
 #define TG_INST(T)                                                                                             \
   template void launch_tg_apply<T>(int32_t, int32_t, const int32_t *, const int64_t *, const int32_t *,        \
-                                   const double *, const double *, T, double, const T *, double, const T *,    \
-                                   const T *, T *, int, hipStream_t);                                          \
+                                   const typename RealOf<T>::type *, const typename RealOf<T>::type *, T,      \
+                                   double, const T *, double, const T *, const T *, T *, int, hipStream_t);    \
   template void launch_csr_slabs<T>(int32_t, int32_t, const int64_t *, const int32_t *, const double *,        \
                                     const T *, T *, int, hipStream_t);                                         \
   template void launch_scale_slabs<T>(int32_t, int32_t, const T *, T *, hipStream_t);
 TG_INST(double)
 TG_INST(cd)
+TG_INST(float)
+TG_INST(cf)
 #undef TG_INST
+template void launch_tg_axpy<double>(int64_t, const double *, double *, hipStream_t);
+template void launch_tg_axpy<float>(int64_t, const float *, float *, hipStream_t);
 
 }  // namespace stmg

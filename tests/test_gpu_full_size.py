@@ -135,7 +135,7 @@ def test_core_box_solve(form):
 @pytest.mark.skipif(os.environ.get("STMG_CORE_BOX_64") != "1",
                     reason="the 64^3 x 128 core box takes a minute of setup, up to two of solve and about "
                            "200 GB; run with STMG_CORE_BOX_64=1 (and a test timeout of 600 s)")
-@pytest.mark.parametrize("form", ["fp32_refined", "fp64", "fp64_twogrid3"])
+@pytest.mark.parametrize("form", ["fp32_refined", "fp64", "fp64_twogrid3", "fp32_refined_twogrid3"])
 def test_core_box_64_full_size(form):
     """The high-contrast case at its stated size: 64^3 jittered Kuhn mesh
     (1,798,336 interior edges), N_t = 128, p_t = 1, without stored factor
@@ -151,9 +151,9 @@ def test_core_box_64_full_size(form):
     from oracle.vcycle import Level
     prob = inputs.config_core_box(n=64, Nt=128, pt=1, seed=3, jitter=0.2)
     print(f"\n[case] core box 64^3 x 128 {form}", flush=True)
-    prec = stmg.FP32_REFINED if form == "fp32_refined" else stmg.FP64
-    target = 1e-8 if form == "fp32_refined" else 1e-10
-    slab = 3 if form == "fp64_twogrid3" else 0
+    prec = stmg.FP32_REFINED if form.startswith("fp32_refined") else stmg.FP64
+    target = 1e-8 if form.startswith("fp32_refined") else 1e-10
+    slab = 3 if form.endswith("twogrid3") else 0
     try:
         gpu = stmg.Solver(prob, rtol=target, max_cycles=100, precision=prec, factor_transpose=0, slab=slab)
     except stmg.StmgError as e:

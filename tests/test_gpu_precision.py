@@ -10,6 +10,13 @@ condition number (tests/_parity.py):
 * S as a solve A (x' - x) = omega (b - L x): backward error <= 1e-6;
 * A: the new residual's gradient component <= 1e-6 of its rounding scale;
 * SAS: bitwise equal to the GPU's S, A, S applied by three separate calls.
+* inexact slab solves (k two-grid Richardson steps in FP32, section 5): the
+  slab solve and S against the oracle's FP64 iteration of the same k steps,
+  forward <= 1e-3. The difference is FP32 rounding carried through the FP32
+  coarse solves and grows with the level's tau (measured 2.5e-6 on the top
+  level to 1.1e-4 on the coarsest two-grid level); the bound catches a wrong
+  step (an O(1) difference), and the refined solve's oracle residual below
+  is the accuracy check. The backward errors above belong to exact solves.
 A refined solve to 1e-8 must have an oracle-computed relative residual
 <= 1e-8; its distance to the oracle's FP64 solution is reported per case.
 One-slab problems (the coarsest level is the finest) are solved in both
@@ -28,8 +35,14 @@ CASES = {
     "block_n8_N32_p1": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=5, block_hexes=4),
     "block_n8_N8_p0": lambda: inputs.config_block_random(n=8, Nt=8, pt=0, seed=6, block_hexes=4),
     "block_n8_N16_p1_devfactor": lambda: inputs.config_block_random(n=8, Nt=16, pt=1, seed=7, block_hexes=4),
+    "tg2_block_n8_N64_p1": lambda: inputs.config_block_random(n=8, Nt=64, pt=1, seed=21, block_hexes=4),
+    "tg1_block_n8_N16_p0_devfactor": lambda: inputs.config_block_random(n=8, Nt=16, pt=0, seed=20, block_hexes=4),
 }
-OPTS = {"block_n8_N16_p1_devfactor": dict(device_factor=1)}
+OPTS = {"block_n8_N16_p1_devfactor": dict(device_factor=1), "tg2_block_n8_N64_p1": dict(slab=2),
+        "tg1_block_n8_N16_p0_devfactor": dict(slab=1, device_factor=1)}
+ORACLE_OPTS = {"tg2_block_n8_N64_p1": dict(slab_solver="twogrid:2"),
+               "tg1_block_n8_N16_p0_devfactor": dict(slab_solver="twogrid:1")}
+FWD32_INEXACT = 1e-3
 
 
 def _dev(a):
@@ -53,7 +66,7 @@ def pair(request):
     prob = CASES[request.param]()
     print(f"\n[case] {request.param} (precision form)", flush=True)
     gpu = stmg.Solver(prob, precision=stmg.FP32_REFINED, rtol=1e-8, **OPTS.get(request.param, {}))
-    ora = SpaceTimeMultigrid(prob)
+    ora = SpaceTimeMultigrid(prob, **ORACLE_OPTS.get(request.param, {}))
     tols = None
     yield request.param, prob, gpu, ora, tols
     gpu.close()
@@ -73,16 +86,18 @@ def test_fp32_steps(pair):
         got = _host(gpu.level_apply(l, stmg.OP_RESIDUAL, _dev(x), _dev(b)))
         assert fwd(got, lev.residual(x, b)) <= 1e-5, (name, "residual", l)
         got = _host(gpu.level_apply(l, stmg.OP_SLAB_SOLVE, _dev(x)))
-        eta, d = slab_backward_error(lev, got, x), fwd(got, lev.slab.solve(x))
+        inexact = type(lev.slab).__name__ == "SlabSolverTwoGrid"
+        eta, d = (0.0 if inexact else slab_backward_error(lev, got, x)), fwd(got, lev.slab.solve(x))
         print(f"[fp32 slab] {name} level {l}: backward error {eta:.1e}, forward {d:.1e}")
         if l == last:
             assert eta <= BWD64 and d <= FWD64, (name, "slab", l, eta, d)
             continue
-        assert eta <= BWD32, (name, "slab", l, eta)
+        assert eta <= BWD32 and (not inexact or d <= FWD32_INEXACT), (name, "slab", l, eta, d)
         got = _host(gpu.level_apply(l, stmg.OP_SMOOTH_S, _dev(x), _dev(b)))
-        e = smoother_backward_error(lev, x, b, got)
-        print(f"[fp32 S] {name} level {l}: backward error {e:.1e}, forward {fwd(got, lev.smooth_S(x, b)):.1e}")
-        assert e <= BWD32, (name, "S", l, e)
+        e = 0.0 if inexact else smoother_backward_error(lev, x, b, got)
+        dS = fwd(got, lev.smooth_S(x, b))
+        print(f"[fp32 S] {name} level {l}: backward error {e:.1e}, forward {dS:.1e}")
+        assert e <= BWD32 and (not inexact or dS <= FWD32_INEXACT), (name, "S", l, e, dS)
         got = _host(gpu.level_apply(l, stmg.OP_NODAL_A, _dev(x), _dev(b)))
         if lev.space.n_v > 0:
             e = gradient_orthogonality(lev, got, b)

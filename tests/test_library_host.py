@@ -380,5 +380,5 @@ def test_slab_option_values(stmg):
     assert _setup_rc(stmg, good, slab=stmg.SLAB_TWOGRID_MAX) == stmg.STMG_OK
     assert _setup_rc(stmg, good, slab=stmg.SLAB_TWOGRID_MAX + 1) == stmg.STMG_EINVAL
     assert _setup_rc(stmg, good, slab=-1) == stmg.STMG_EINVAL
-    # the FP32 smoother has no inexact slab solve
-    assert _setup_rc(stmg, good, slab=2, precision=stmg.FP32_REFINED) == stmg.STMG_EINVAL
+    # the precision form runs the two-grid iteration in its FP32 smoother
+    assert _setup_rc(stmg, good, slab=2, precision=stmg.FP32_REFINED) == stmg.STMG_OK
