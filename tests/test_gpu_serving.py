@@ -162,25 +162,34 @@ def test_device_factorisation_in_the_mix():
 
 
 def test_batched_requests_equal_unbatched():
-    """Requests of one cycle shape (N_t = 16, p_t = 1, precision form) on the
-    GPU together run batched iterations (merged slab and nodal solves); their
-    results are bitwise those of a server that never batches."""
+    """Requests of one cycle shape and size (8^3 mesh, N_t = 16, p_t = 1,
+    precision form, different materials and right-hand sides) on the GPU
+    together run batched iterations (merged slab and nodal solves); their
+    results are bitwise those of a server that never batches. Batching needs
+    iterations that fall due at the same poll of the scheduler, a matter of
+    timing: the batched server is run up to three times until one run has
+    batched iterations."""
     from paper_1911_09548_amd import stmg
-    shape = [(4, 16, 1, 201), (6, 16, 1, 202), (8, 16, 1, 203), (4, 16, 1, 204),
-             (8, 16, 1, 205), (6, 16, 1, 206), (12, 16, 1, 207), (8, 16, 1, 208)]
+    shape = [(8, 16, 1, 201 + k) for k in range(8)]
     reqs = [_request(*m) for m in shape]
     opts = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
-    out = {}
-    for batch in (True, False):
+
+    def run(batch):
         srv = stmg.Server(max_active=8, setup_threads=4, batch=batch)
         tickets = [srv.submit(p, r, **opts) for p, r in reqs]
         res = []
         for (p, r), t in zip(reqs, tickets):
             assert srv.wait(t, 300)
             res.append(srv.poll(t, r.shape))
-        out[batch] = (res, srv.stats())
+        st = srv.stats()
         srv.close()
-    (res_b, st_b), (res_u, st_u) = out[True], out[False]
+        return res, st
+
+    res_u, st_u = run(False)
+    for _ in range(3):
+        res_b, st_b = run(True)
+        if st_b["batched_iterations"] > 0:
+            break
     print(f"\n[serving] batched: {st_b['batched_iterations']} batched iterations, "
           f"{st_b['batched_members']} request iterations in them; unbatched: {st_u['batched_iterations']}")
     assert st_b["batched_iterations"] > 0 and st_u["batched_iterations"] == 0
@@ -189,3 +198,26 @@ def test_batched_requests_equal_unbatched():
         assert rc_b == rc_u == stmg.STMG_OK
         assert rep_b["cycles"] == rep_u["cycles"]
         assert np.array_equal(x_b, x_u)
+
+
+def test_two_grid_requests_in_the_mix():
+    """Requests with inexact slab solves (two-grid Richardson steps in the
+    FP32 smoother) next to requests with exact ones: every result equals the
+    plain solver's with the same options, bitwise, and meets 1e-8."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    reqs = [(_request(8, 16, 1, 601), 2), (_request(8, 32, 0, 602), 1), (_request(8, 16, 1, 603), 0),
+            (_request(6, 16, 1, 604), 3)]
+    srv = stmg.Server(max_active=4, setup_threads=2)
+    opts = dict(precision=stmg.FP32_REFINED, rtol=1e-8, max_cycles=60)
+    tickets = [srv.submit(p, r, slab=k, **opts) for (p, r), k in reqs]
+    for ((p, r), k), t in zip(reqs, tickets):
+        assert srv.wait(t, 300)
+        rc, x, rep = srv.poll(t, r.shape)
+        assert rc == stmg.STMG_OK and rep["rel_res"] <= 1e-8, (k, rc, rep)
+        s = stmg.Solver(p, slab=k, **opts)
+        xs, rep_s = s.solve(torch.from_numpy(r).cuda())
+        s.close()
+        assert rep_s["cycles"] == rep["cycles"], (k, rep_s["cycles"], rep["cycles"])
+        assert np.array_equal(xs.cpu().numpy(), x)
+    srv.close()
