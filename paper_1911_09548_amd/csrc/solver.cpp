@@ -1870,7 +1870,7 @@ int64_t estimate_device_bytes(const stmg_handle *h) {
     if (L.twogrid)  // Richardson residual, smoother iterates, temporary, coarse vector, diagonals
       bytes += (prec ? 4 : 8) * W * (4 * ne + mf.S->topo.n_int_edges()) + 16 * (ne + nv);
     const bool last = l + 1 == h->levels.size();
-    const int64_t nodal_extra = h->opt.nodal > 0 ? 2 * nv : md.sym_v.rptr[md.sym_v.ns];
+    const int64_t nodal_extra = nv == 0 ? 0 : (h->opt.nodal > 0 ? 2 * nv : md.sym_v.rptr[md.sym_v.ns]);
     if (!prec) bytes += 8 * W * (4 * ne + urow + 2 * nv + nodal_extra);
     if (prec) {
       bytes += 4 * W * (4 * ne + urow + 2 * nv + nodal_extra);
