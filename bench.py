@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1911_09548_amd", "csrc", "kernels.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_32cube_Nt256_pt1_fp64.md")
 
@@ -761,19 +762,46 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms32 = e0.elapsed_time(e1) / args.steps
+        # the FP32 iteration's kernels with per-launch events (same stream);
+        # the dominant FP32 supernode GEMM with its split-K reduce against the
+        # FP32 matrix-core peak
+        s32.profile(True)
+        s32.cycles(args.steps)
+        torch.cuda.synchronize()
+        k32 = s32.profile_report()
+        s32.profile(False)
+        by32 = {k["kernel"]: k for k in k32}
+
+        def comb32(k):
+            red = by32.get(k["kernel"].replace("k_sn_gemm", "k_sn_reduce"))
+            return k["ms"] + (red["ms"] if red and k["kernel"].startswith("k_sn_gemm") else 0.0)
+
+        top32 = max((k for k in k32 if k["kernel"].startswith("k_sn_gemm<c")), key=comb32, default=None)
+        roof32 = None
+        if top32:
+            avg32 = comb32(top32) * 1e-3 / top32["launches"]
+            ach32 = top32["flops"] / top32["launches"] / avg32 / 1e12
+            roof32 = {"bound": "mfma", "achieved": ach32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach32 / FP32_PEAK_TFLOPS, "kernel": top32["kernel"], "avg_launch_us": avg32 * 1e6,
+                      "launches": top32["launches"]}
         t = time.perf_counter()
         x32, rep32 = s32.solve(rhs)
         torch.cuda.synchronize()
         tts32 = time.perf_counter() - t
         prec = {"form": "fp32 smoother + fp64 refinement", "value": dofs / (ms32 * 1e-3),
                 "ms_per_step": ms32, "time_to_1e-8_s": tts32, "cycles_to_1e-8": rep32["cycles"],
-                "final_rel_res": rep32["rel_res"], "setup_s": setup32}
+                "final_rel_res": rep32["rel_res"], "setup_s": setup32, "roofline_fp32_solve": roof32,
+                "kernels": [{"kernel": k["kernel"], "ms_per_step": k["ms"] / args.steps,
+                             "launches_per_step": k["launches"] // args.steps,
+                             "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12,
+                             "gbs": k["bytes"] / (k["ms"] * 1e-3) / 1e9} for k in k32[:12]]}
         if x64 is not None:
             # distance to the FP64 form's solution of the same system (both
             # solved to 1e-8; final_rel_res is already the FP64 residual)
             prec["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
         log(f"[bench] precision form: {ms32:.2f} ms per iteration, 1e-8 in {rep32['cycles']} cycles "
-            f"({tts32:.2f}s)")
+            f"({tts32:.2f}s)" + (f"; {roof32['kernel']} {roof32['achieved']:.1f} TFLOP/s = "
+                                 f"{roof32['frac']:.2f} of the FP32 peak" if roof32 else ""))
         s32.close()
 
     def inexact_form(label, key, what, **opts):
