@@ -220,8 +220,14 @@ void stmg_default_options(stmg_options *opt);
  * space), Galerkin coarse operators, nested-dissection orderings, symbolic and
  * numeric factorisations of every level's slab block and nodal matrix K_n, and
  * uploads to HBM. Host arrays are borrowed for the call only. `stream` is a
- * hipStream_t (NULL = default stream). On failure *out is NULL and nothing
- * leaks. */
+ * hipStream_t (NULL = default stream). Refuses with STMG_ENOMEM, before any
+ * device allocation, when its device-memory estimate exceeds the free memory.
+ * GPU factorisations of the slab levels after the largest run on up to 8
+ * worker threads, each with its own stream and rocBLAS handle (fewer when
+ * their temporaries would not fit; at most the environment's
+ * STMG_SETUP_THREADS); the call returns when all are done. STMG_VERBOSE=1 in
+ * the environment prints the setup's phases and timings on stderr. On failure
+ * *out is NULL and nothing leaks. */
 int stmg_setup(const stmg_problem *prob, const stmg_options *opt, void *stream,
                stmg_handle **out);
 void stmg_destroy(stmg_handle *h);
