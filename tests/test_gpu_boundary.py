@@ -6,7 +6,9 @@
 * allocation failures injected at device allocations of a setup return
   STMG_ENOMEM and release every device buffer the setup had made: free
   device memory returns to its level before the call, and a following setup
-  on the same process solves normally.
+  on the same process solves normally;
+* the setup's parallel slab factorisations give bitwise the factors and
+  solves of a setup on one stream.
 """
 import numpy as np
 import pytest
@@ -135,3 +137,30 @@ def test_graph_replay_equals_eager_launches(precision):
     finally:
         for s in solvers.values():
             s.close()
+
+
+def test_parallel_setup_equals_one_stream(monkeypatch):
+    """The slab factorisations on worker threads (the default) give bitwise
+    the factors, iterates and residual history of a setup on one stream
+    (STMG_SETUP_THREADS=1), in both forms."""
+    import torch
+    from paper_1911_09548_amd import stmg
+    prob = inputs.config_block_random(n=8, Nt=64, pt=1, seed=25, block_hexes=4)
+    print("\n[case] parallel setup against one stream, 8^3 x 64", flush=True)
+    for precision in (0, 1):
+        out = {}
+        for threads in ("1", "8"):
+            monkeypatch.setenv("STMG_SETUP_THREADS", threads)
+            s = stmg.Solver(prob, precision=precision, device_factor=1, rtol=1e-9)
+            try:
+                b = _dev(np.random.default_rng(8).standard_normal((prob.Nt, 2, s.n_edges)))
+                x, rep = s.solve(b)
+                torch.cuda.synchronize()
+                out[threads] = (x.clone(), rep["history"], [s.export_factor(l, 0)["panel"]
+                                                           for l in range(s.n_levels) if precision == 0])
+            finally:
+                s.close()
+        (x1, h1, f1), (x8, h8, f8) = out["1"], out["8"]
+        assert torch.equal(x1, x8) and h1 == h8, precision
+        assert all(np.array_equal(a, c) for a, c in zip(f1, f8)), precision
+    monkeypatch.delenv("STMG_SETUP_THREADS")
