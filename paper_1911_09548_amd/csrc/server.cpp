@@ -155,7 +155,8 @@ void hipc(hipError_t e, const char *what) {
 }  // namespace
 
 void stmg_server::worker_loop() {
-  hipSetDevice(device);
+  // a failure here shows in the first HIP call of each request, whose error is reported per request
+  (void)hipSetDevice(device);
   for (;;) {
     std::shared_ptr<Request> r;
     bool dev = false;
@@ -443,7 +444,7 @@ void stmg_server::launch_iterations() {
 }
 
 void stmg_server::scheduler_loop() {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);  // as in worker_loop
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
     bool moved = false;
