@@ -505,7 +505,8 @@ def core_box(args):
         t0 = time.perf_counter()
         try:
             s = stmg.Solver(prob, rtol=1e-8, max_cycles=max_cycles, precision=prec,
-                            factor_transpose=args.core_box_transpose, slab=k)
+                            factor_transpose=args.core_box_transpose, slab=k,
+                            device_factor={"auto": -1, "gpu": 1, "host": 0}[args.factor])
         except stmg.StmgError as e:
             # refused by the device-memory estimate (or out of memory)
             out["forms"][form] = {"refused": str(e), "code": e.code, "after_s": time.perf_counter() - t0}
@@ -629,10 +630,6 @@ def main():
     if args.two_lambda:
         print(json.dumps({"two_lambda": two_lambda(args)}), flush=True)
         return
-    if args.core_box > 0:
-        core_box(args)
-        return
-
     import numpy as np
     import torch
     from paper_1911_09548_amd import inputs, stmg
@@ -647,6 +644,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
+    if args.core_box > 0:
+        core_box(args)
+        return
     prob = inputs.config_block_random(n=args.n, Nt=args.Nt, pt=args.pt, seed=1, block_hexes=8)
     log(f"[bench] setup n={args.n} Nt={args.Nt} pt={args.pt}")
     t0 = time.perf_counter()
