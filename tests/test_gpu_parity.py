@@ -96,6 +96,8 @@ CASES = {
     # N = 64 on the top level: the slab operator's wave-per-row kernel (N a multiple of 64)
     "tg2_block_n8_N64_p1": lambda: inputs.config_block_random(n=8, Nt=64, pt=1, seed=21, block_hexes=4),
     "tg1_block_n8_N128_p0": lambda: inputs.config_block_random(n=8, Nt=128, pt=0, seed=22, block_hexes=4),
+    # both spatial solves inexact: two-grid slab solves and Chebyshev nodal solves
+    "tg2cheb3_block_n8_N32_p1": lambda: inputs.config_block_random(n=8, Nt=32, pt=1, seed=23, block_hexes=4),
 }
 # the oracle's options for the cases that change the method
 ORACLE_OPTS = {"cheb3_block_n8_N32_p1": dict(nodal_cheb=3), "cheb2_jitter_n6_N16_p0": dict(nodal_cheb=2),
@@ -105,7 +107,8 @@ ORACLE_OPTS = {"cheb3_block_n8_N32_p1": dict(nodal_cheb=3), "cheb2_jitter_n6_N16
                "tg4_jitter_n6_N16_p0_devfactor": dict(slab_solver="twogrid:4"),
                "tg3_neumann_n8_N16_p1": dict(slab_solver="twogrid:3"),
                "tg2_block_n8_N64_p1": dict(slab_solver="twogrid:2"),
-               "tg1_block_n8_N128_p0": dict(slab_solver="twogrid:1")}
+               "tg1_block_n8_N128_p0": dict(slab_solver="twogrid:1"),
+               "tg2cheb3_block_n8_N32_p1": dict(slab_solver="twogrid:2", nodal_cheb=3)}
 OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": dict(gemm_rows=64),
         "block_n8_N32_p1": dict(gemm_rows=32),
         "block_n8_N32_p1_noT_split3": dict(factor_transpose=0, gemm_splitk=3),
@@ -118,7 +121,7 @@ OPTS = {"block_n8_N64_p1_rows64": dict(gemm_rows=64), "block_n8_N16_p0_rows64": 
         "tg2_block_n8_N32_p1": dict(slab=2), "tg1_block_n8_N16_p0": dict(slab=1),
         "tg4_jitter_n6_N16_p0_devfactor": dict(slab=4, device_factor=1),
         "tg3_neumann_n8_N16_p1": dict(slab=3), "tg2_block_n8_N64_p1": dict(slab=2),
-        "tg1_block_n8_N128_p0": dict(slab=1)}
+        "tg1_block_n8_N128_p0": dict(slab=1), "tg2cheb3_block_n8_N32_p1": dict(slab=2, nodal=3)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
