@@ -5,8 +5,9 @@ per tree height and tile shape.
 * Every member's iterates and residual histories are bitwise those of the
   same handle iterated alone (stmg_cycles), for a mix of mesh sizes,
   materials, a jittered mesh and a Neumann problem, both DG degrees and both
-  precision forms, and with inexact slab solves (two-grid steps run member
-  by member, the exact solves of members without a coarser mesh merged).
+  precision forms, with inexact slab solves (two-grid steps run member by
+  member, the exact solves of members without a coarser mesh merged) and
+  with inexact nodal solves (Chebyshev steps member by member).
 * A batched solve reaches the oracle's residual target (the space-time
   system of eq. (1), FP64 oracle) for each member.
 * Handles of different shapes, duplicates and more than 8 handles are
@@ -36,14 +37,16 @@ def _mix(Nt, pt):
     return probs
 
 
-@pytest.mark.parametrize("pt,precision,slab", [(1, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 2)])
-def test_batched_equals_separate_bitwise(pt, precision, slab):
+@pytest.mark.parametrize("pt,precision,slab,nodal", [(1, 0, 0, 0), (0, 0, 0, 0), (1, 1, 0, 0), (1, 0, 2, 0),
+                                                      (1, 1, 0, 3)])
+def test_batched_equals_separate_bitwise(pt, precision, slab, nodal):
     import torch
     from paper_1911_09548_amd import stmg
     Nt, k = 16, 4
     probs = _mix(Nt, pt)
-    print(f"\n[case] batched p_t={pt} precision={precision} slab={slab}: {len(probs)} members", flush=True)
-    solvers = [stmg.Solver(p, precision=precision, slab=slab, device_factor=1 if i == 1 else -1)
+    print(f"\n[case] batched p_t={pt} precision={precision} slab={slab} nodal={nodal}: {len(probs)} members",
+          flush=True)
+    solvers = [stmg.Solver(p, precision=precision, slab=slab, nodal=nodal, device_factor=1 if i == 1 else -1)
                for i, p in enumerate(probs)]
     try:
         rhs = [_dev(np.random.default_rng(90 + i).standard_normal((Nt, pt + 1, s.n_edges)))
